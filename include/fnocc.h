@@ -1,0 +1,166 @@
+/*
+ * fnocc.h -- C ABI of the MI355X (gfx950) FNO-EOM-CCSDT library.
+ *
+ * What the library computes (arXiv 2509.14157):
+ *   - Section 1.2, eqs (8)-(10): MP2 amplitudes t_ij^ab = <ab||ij>/e_ij^ab,
+ *     the virtual-virtual MP2 density D_ab, its natural orbitals and the
+ *     frozen-natural-orbital truncation of the virtual space, followed by
+ *     semicanonicalisation of the kept virtual block.
+ *   - Section 1.1, eqs (5)-(7): ground-state CCSDT, 0 = <Phi^n|e^{-T} H e^{T}|Phi_0>
+ *     for n = 1..3 and E = <Phi_0|e^{-T} H e^{T}|Phi_0>.
+ *   - Section 1.1, eqs (1)-(4): EOM-CCSDT right eigenstates for the ionized
+ *     (IP: 1h, 2h1p, 3h2p), doubly ionized (DIP: 2h, 3h1p, 4h2p), electron
+ *     attached (EA: 1p, 2p1h, 3p2h) and doubly attached (DEA: 2p, 3p1h, 4p2h)
+ *     operator spaces.
+ * All of it runs in the (truncated) spin-orbital space on one GPU.
+ *
+ * Conventions
+ *   - Spin-orbitals, occupied orbitals first.  Energies in hartree.
+ *   - Every call returns an int status: FNO_OK or a negative error code;
+ *     fno_last_error() then describes the failure.
+ *   - Inputs are copied; outputs are caller-allocated host arrays.
+ *   - Call order: fno_load_hamiltonian -> [fno_truncate] -> fno_ccsdt -> fno_eom.
+ *     An out-of-order call returns FNO_ESTATE.  One context per host thread.
+ *   - Packed amplitude layout (fno_get/set_amplitudes): each antisymmetric
+ *     index group holds strictly increasing tuples in colexicographic order
+ *     (tuple x0<x1<..<x{g-1} at sum_t C(x_t, t+1)); groups are row-major with
+ *     the hole group first.  T1 is the dense o x v array.
+ */
+#ifndef FNOCC_H
+#define FNOCC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FNO_OK = 0,
+  FNO_EINVAL = -1,     /* bad argument, bad input symmetry, size out of range */
+  FNO_ENOMEM = -2,     /* device or host allocation failed */
+  FNO_EDEVICE = -3,    /* HIP runtime error or missing gfx950 device */
+  FNO_ENOCONV = -4,    /* solver reached max_iter without meeting its tolerances */
+  FNO_ENONFINITE = -5, /* NaN or Inf in an input or during the iterations */
+  FNO_ESTATE = -6      /* call out of order (e.g. fno_eom before fno_ccsdt) */
+};
+
+typedef struct fno_ctx fno_ctx;
+
+/* Create a context on HIP device `hip_device` (owns all device memory). */
+int fno_create(int hip_device, fno_ctx **out);
+void fno_destroy(fno_ctx *ctx);
+/* Message of the last failing call on ctx; valid until the next call. */
+const char *fno_last_error(const fno_ctx *ctx);
+/* Run all device work on this hipStream_t (NULL = the default stream). */
+int fno_set_stream(fno_ctx *ctx, void *hip_stream);
+
+/*
+ * Load the problem (Section 1.2: canonical orbitals, orbital energies f_pp and
+ * antisymmetrized integrals).
+ *   fock : n x n row-major Fock matrix, n = nocc + nvir; |f_ov| must be < 1e-10.
+ *   eri  : n^4 row-major <pq||rs>; must satisfy <pq||rs> = -<qp||rs> = -<pq||sr>
+ *          = <rs||pq> to 1e-10 relative.
+ *   e_nuc: constant added to every total energy.
+ * Errors: FNO_EINVAL (sizes, symmetry), FNO_ENONFINITE, FNO_ENOMEM.
+ */
+int fno_load_hamiltonian(fno_ctx *ctx, int nocc, int nvir, const double *fock, const double *eri, double e_nuc);
+
+/*
+ * FNO truncation (Section 1.2): MP2 amplitudes (eq 8) with denominators
+ * (eq 9), virtual density (eq 10), natural orbitals sorted by descending
+ * occupation, truncation, semicanonicalisation of the kept block and
+ * transformation of f and <pq||rs>.
+ *   occt      : cumulative-occupation threshold in (0, 1]; the smallest k
+ *               with sum_{l<=k} n_l >= occt * sum_l n_l is kept (1 keeps all).
+ *   nvir_keep : > 0 keeps exactly this many natural orbitals (overrides occt).
+ *   nvir_kept : out, number of kept virtuals (may be NULL).
+ *   e_mp2     : out, MP2 correlation energy of the full space (may be NULL).
+ *   occ       : out, nvir occupation numbers in descending order (may be NULL).
+ */
+int fno_truncate(fno_ctx *ctx, double occt, int nvir_keep, int *nvir_kept, double *e_mp2, double *occ);
+
+typedef enum { FNO_FP64 = 0, FNO_FP32 = 1, FNO_BF16X3 = 2 } fno_prec;
+
+/* Options of the ground-state solver (Jacobi steps t += r/D with DIIS). */
+typedef struct {
+  int max_iter;     /* default 100 */
+  double r_tol;     /* converged when ||r||_2 over unique amplitudes < r_tol ... */
+  double e_tol;     /* ... and |Delta E| < e_tol */
+  int diis_n;       /* DIIS history length (0 disables), default 8 */
+  int diis_start;   /* first iteration that extrapolates, default 3 */
+  fno_prec prec;    /* precision of the triples contractions; solver stays FP64 */
+  int guess;        /* 0 = zero amplitudes (first step gives MP2) */
+} fno_cc_opts;
+void fno_cc_opts_default(fno_cc_opts *o);
+
+/*
+ * Ground-state CCSDT (eqs 5-7) in the current (possibly truncated) space.
+ *   e_corr, e_tot: correlation and total energy (e_tot = E_ref + e_corr + e_nuc).
+ *   iters, res_norm: iterations used and final residual norm.
+ * Returns FNO_ENOCONV (results still written) when max_iter is reached.
+ */
+int fno_ccsdt(fno_ctx *ctx, const fno_cc_opts *opts, double *e_corr, double *e_tot, int *iters, double *res_norm);
+
+typedef enum { FNO_IP = 1, FNO_DIP = 2, FNO_EA = 3, FNO_DEA = 4 } fno_eom_kind;
+
+typedef struct {
+  int nroots;       /* number of roots (lowest real parts) */
+  int max_iter;     /* Davidson iterations, default 60 */
+  int max_sub;      /* subspace size before collapse, default 8 * nroots */
+  double e_tol;     /* |Delta omega| tolerance */
+  double r_tol;     /* residual-norm tolerance */
+  fno_prec prec;    /* precision of the R3 sigma contractions */
+  int guess;        /* 0 = unit vectors on the lowest principal-block diagonal */
+  int precond;      /* 0 = (omega - D)^-1 with the zeroth-order diagonal D */
+} fno_eom_opts;
+void fno_eom_opts_default(fno_eom_opts *o);
+
+/*
+ * EOM-CCSDT roots of `kind` on top of the converged ground state.
+ *   omega   : nroots excitation energies E_target - E_CCSDT, ascending real part
+ *             (IP/DIP: ionization energies; EA/DEA: minus the attachment energy).
+ *   e_tot   : nroots total energies (may be NULL).
+ *   res_norm: nroots final residual norms (may be NULL).
+ */
+int fno_eom(fno_ctx *ctx, fno_eom_kind kind, const fno_eom_opts *opts, double *omega, double *e_tot,
+            double *res_norm, int *iters);
+
+/* Orbital-space sizes of the current problem (after truncation). */
+int fno_sizes(const fno_ctx *ctx, int *nocc, int *nvir, int *nvir_full);
+
+/*
+ * Amplitude access in packed layout.  block: 1, 2, 3 = T1, T2, T3.
+ * len must equal the packed size (FNO_EINVAL otherwise): o*v, C(o,2)C(v,2),
+ * C(o,3)C(v,3).
+ */
+int fno_get_amplitudes(fno_ctx *ctx, int block, double *buf, size_t len);
+int fno_set_amplitudes(fno_ctx *ctx, int block, const double *buf, size_t len);
+size_t fno_amplitude_size(const fno_ctx *ctx, int block);
+
+/*
+ * One evaluation of the CCSDT residual at the amplitudes currently held
+ * (set with fno_set_amplitudes, or the converged ones), in the precision
+ * `prec`.  r1/r2/r3 receive the packed residual blocks (each may be NULL),
+ * e_corr the energy eq (6) at those amplitudes.  Used for parity checks and
+ * benchmarks of one pass of the hot path.
+ */
+int fno_cc_residual(fno_ctx *ctx, fno_prec prec, double *r1, double *r2, double *r3, double *e_corr);
+
+/*
+ * One EOM sigma evaluation sigma = <mu|(H-bar R)_C|0> for the R vector given
+ * in packed unique layout (blocks concatenated in rank order, e.g. IP:
+ * 1h, 2h1p, 3h2p), on top of the amplitudes currently held.
+ * len = fno_eom_size(ctx, kind).
+ */
+size_t fno_eom_size(const fno_ctx *ctx, fno_eom_kind kind);
+int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *r, double *sigma, size_t len);
+
+/* Kernel-level statistics of the last residual/sigma evaluation: algorithmic
+ * GEMM flops (packed forms) of the triples contractions and of all terms. */
+int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FNOCC_H */

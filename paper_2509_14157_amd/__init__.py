@@ -1,0 +1,206 @@
+"""Python binding of libfnocc (FNO-EOM-CCSDT on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Importing the package does not need a GPU; creating a Context
+does, and raises if the library or a gfx950 device is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBRARY_PATH = os.path.join(_HERE, "libfnocc.so")
+
+FNO_OK, FNO_EINVAL, FNO_ENOMEM, FNO_EDEVICE, FNO_ENOCONV, FNO_ENONFINITE, FNO_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
+
+# exported C symbols (kept in sync with include/fnocc.h)
+SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
+           "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
+           "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
+           "fno_eom_sigma", "fno_last_flops"]
+
+
+class FnoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+class CCOpts(C.Structure):
+    _fields_ = [("max_iter", C.c_int), ("r_tol", C.c_double), ("e_tol", C.c_double), ("diis_n", C.c_int),
+                ("diis_start", C.c_int), ("prec", C.c_int), ("guess", C.c_int)]
+
+
+class EOMOpts(C.Structure):
+    _fields_ = [("nroots", C.c_int), ("max_iter", C.c_int), ("max_sub", C.c_int), ("e_tol", C.c_double),
+                ("r_tol", C.c_double), ("prec", C.c_int), ("guess", C.c_int), ("precond", C.c_int)]
+
+
+_lib = None
+
+
+def library() -> C.CDLL:
+    """Load libfnocc.so (built in-tree by __graft_entry__.build or paper_2509_14157_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBRARY_PATH):
+            raise ImportError(f"{LIBRARY_PATH} is missing: build it with python -m paper_2509_14157_amd.build")
+        lib = C.CDLL(LIBRARY_PATH)
+        dp = C.POINTER(C.c_double)
+        lib.fno_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+        lib.fno_destroy.argtypes = [C.c_void_p]
+        lib.fno_destroy.restype = None
+        lib.fno_last_error.argtypes = [C.c_void_p]
+        lib.fno_last_error.restype = C.c_char_p
+        lib.fno_set_stream.argtypes = [C.c_void_p, C.c_void_p]
+        lib.fno_load_hamiltonian.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_double]
+        lib.fno_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int), dp, dp]
+        lib.fno_cc_opts_default.argtypes = [C.POINTER(CCOpts)]
+        lib.fno_cc_opts_default.restype = None
+        lib.fno_ccsdt.argtypes = [C.c_void_p, C.POINTER(CCOpts), dp, dp, C.POINTER(C.c_int), dp]
+        lib.fno_eom_opts_default.argtypes = [C.POINTER(EOMOpts)]
+        lib.fno_eom_opts_default.restype = None
+        lib.fno_eom.argtypes = [C.c_void_p, C.c_int, C.POINTER(EOMOpts), dp, dp, dp, C.POINTER(C.c_int)]
+        lib.fno_sizes.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        lib.fno_get_amplitudes.argtypes = [C.c_void_p, C.c_int, dp, C.c_size_t]
+        lib.fno_set_amplitudes.argtypes = [C.c_void_p, C.c_int, dp, C.c_size_t]
+        lib.fno_amplitude_size.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_amplitude_size.restype = C.c_size_t
+        lib.fno_cc_residual.argtypes = [C.c_void_p, C.c_int, dp, dp, dp, dp]
+        lib.fno_eom_size.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_eom_size.restype = C.c_size_t
+        lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
+        lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
+        _lib = lib
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+class Context:
+    """One problem on one GPU: load -> [truncate] -> ccsdt -> eom."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = library()
+        h = C.c_void_p()
+        st = self._lib.fno_create(device, C.byref(h))
+        if st != FNO_OK:
+            raise FnoError(st, f"fno_create failed on device {device}")
+        self._h = h
+        if stream is not None:
+            self._check(self._lib.fno_set_stream(self._h, C.c_void_p(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fno_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st, allow=()):
+        if st != FNO_OK and st not in allow:
+            raise FnoError(st, self._lib.fno_last_error(self._h).decode())
+        return st
+
+    # ---- problem
+    def load_hamiltonian(self, fock, eri, nocc: int, e_nuc: float = 0.0):
+        f, g = _f64(fock), _f64(eri)
+        n = f.shape[0]
+        if f.shape != (n, n) or g.shape != (n, n, n, n):
+            raise ValueError("fock must be (n, n) and eri (n, n, n, n)")
+        self._check(self._lib.fno_load_hamiltonian(self._h, nocc, n - nocc, _dp(f), _dp(g), float(e_nuc)))
+
+    def truncate(self, occt: float = 1.0, nvir_keep: int = 0):
+        _, _, vf = self.sizes()
+        kept = C.c_int()
+        emp2 = C.c_double()
+        occ = np.zeros(vf)
+        self._check(self._lib.fno_truncate(self._h, float(occt), int(nvir_keep), C.byref(kept), C.byref(emp2),
+                                           _dp(occ)))
+        return kept.value, emp2.value, occ
+
+    def sizes(self):
+        o, v, vf = C.c_int(), C.c_int(), C.c_int()
+        self._check(self._lib.fno_sizes(self._h, C.byref(o), C.byref(v), C.byref(vf)))
+        return o.value, v.value, vf.value
+
+    # ---- ground state
+    def ccsdt(self, max_iter=100, r_tol=1e-8, e_tol=1e-10, diis_n=8, diis_start=3, prec="fp64",
+              allow_noconv=False):
+        o = CCOpts()
+        self._lib.fno_cc_opts_default(C.byref(o))
+        o.max_iter, o.r_tol, o.e_tol, o.diis_n, o.diis_start = max_iter, r_tol, e_tol, diis_n, diis_start
+        o.prec = PREC[prec]
+        ec, et, rn = C.c_double(), C.c_double(), C.c_double()
+        it = C.c_int()
+        st = self._check(self._lib.fno_ccsdt(self._h, C.byref(o), C.byref(ec), C.byref(et), C.byref(it),
+                                             C.byref(rn)), allow=(FNO_ENOCONV,) if allow_noconv else ())
+        return dict(e_corr=ec.value, e_tot=et.value, iters=it.value, res_norm=rn.value,
+                    converged=(st == FNO_OK))
+
+    def amplitude_size(self, block: int) -> int:
+        return int(self._lib.fno_amplitude_size(self._h, block))
+
+    def get_amplitudes(self, block: int) -> np.ndarray:
+        out = np.zeros(self.amplitude_size(block))
+        self._check(self._lib.fno_get_amplitudes(self._h, block, _dp(out), out.size))
+        return out
+
+    def set_amplitudes(self, block: int, values) -> None:
+        v = _f64(values).ravel()
+        self._check(self._lib.fno_set_amplitudes(self._h, block, _dp(v), v.size))
+
+    def cc_residual(self, prec="fp64"):
+        n1, n2, n3 = (self.amplitude_size(k) for k in (1, 2, 3))
+        r1, r2, r3 = np.zeros(n1), np.zeros(n2), np.zeros(n3)
+        ec = C.c_double()
+        self._check(self._lib.fno_cc_residual(self._h, PREC[prec], _dp(r1), _dp(r2), _dp(r3), C.byref(ec)))
+        return r1, r2, r3, ec.value
+
+    def last_flops(self):
+        t, a = C.c_double(), C.c_double()
+        self._check(self._lib.fno_last_flops(self._h, C.byref(t), C.byref(a)))
+        return t.value, a.value
+
+    # ---- EOM
+    def eom_size(self, kind: str) -> int:
+        return int(self._lib.fno_eom_size(self._h, KIND[kind]))
+
+    def eom_sigma(self, kind: str, r, prec="fp64") -> np.ndarray:
+        x = _f64(r).ravel()
+        out = np.zeros_like(x)
+        self._check(self._lib.fno_eom_sigma(self._h, KIND[kind], PREC[prec], _dp(x), _dp(out), x.size))
+        return out
+
+    def eom(self, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",
+            allow_noconv=False):
+        o = EOMOpts()
+        self._lib.fno_eom_opts_default(C.byref(o))
+        o.nroots, o.max_iter, o.max_sub, o.e_tol, o.r_tol = nroots, max_iter, max_sub, e_tol, r_tol
+        o.prec = PREC[prec]
+        om, et, rn = np.zeros(nroots), np.zeros(nroots), np.zeros(nroots)
+        it = C.c_int()
+        st = self._check(self._lib.fno_eom(self._h, KIND[kind], C.byref(o), _dp(om), _dp(et), _dp(rn), C.byref(it)),
+                         allow=(FNO_ENOCONV,) if allow_noconv else ())
+        return dict(omega=om, e_tot=et, res_norm=rn, iters=it.value, converged=(st == FNO_OK))

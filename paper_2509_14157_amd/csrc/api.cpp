@@ -1,0 +1,229 @@
+// extern "C" boundary: argument checks, error capture, status codes.
+#include <cstring>
+#include <exception>
+
+#include "../../include/fnocc.h"
+#include "context.hpp"
+
+struct fno_ctx {
+  fno::Context* c = nullptr;
+  std::string err;
+};
+
+namespace {
+template <typename F>
+int guard(fno_ctx* ctx, F&& f) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  try {
+    FNO_HIP(hipSetDevice(ctx->c->device));
+    ctx->err.clear();
+    return f(*ctx->c);
+  } catch (const fno::Error& e) {
+    ctx->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return FNO_ENOMEM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return FNO_EDEVICE;
+  }
+}
+
+fno::Prec to_prec(fno_prec p) {
+  switch (p) {
+    case FNO_FP64: return fno::Prec::FP64;
+    case FNO_FP32: return fno::Prec::FP32;
+    case FNO_BF16X3: return fno::Prec::BF16X3;
+  }
+  throw fno::Error(FNO_EINVAL, "unknown precision");
+}
+}  // namespace
+
+extern "C" {
+
+int fno_create(int hip_device, fno_ctx** out) {
+  if (!out) return FNO_EINVAL;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) fno_ctx;
+  if (!ctx) return FNO_ENOMEM;
+  try {
+    ctx->c = new fno::Context(hip_device);
+  } catch (const fno::Error& e) {
+    delete ctx;
+    return e.code;
+  } catch (...) {
+    delete ctx;
+    return FNO_EDEVICE;
+  }
+  *out = ctx;
+  return FNO_OK;
+}
+
+void fno_destroy(fno_ctx* ctx) {
+  if (!ctx) return;
+  delete ctx->c;
+  delete ctx;
+}
+
+const char* fno_last_error(const fno_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int fno_set_stream(fno_ctx* ctx, void* s) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.eng->stream = (hipStream_t)s;
+    return FNO_OK;
+  });
+}
+
+int fno_load_hamiltonian(fno_ctx* ctx, int nocc, int nvir, const double* fock, const double* eri, double e_nuc) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.load(nocc, nvir, fock, eri, e_nuc);
+    return FNO_OK;
+  });
+}
+
+int fno_truncate(fno_ctx* ctx, double occt, int nvir_keep, int* nvir_kept, double* e_mp2, double* occ) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.truncate(occt, nvir_keep, nvir_kept, e_mp2, occ);
+    return FNO_OK;
+  });
+}
+
+void fno_cc_opts_default(fno_cc_opts* o) {
+  if (!o) return;
+  o->max_iter = 100;
+  o->r_tol = 1e-8;
+  o->e_tol = 1e-10;
+  o->diis_n = 8;
+  o->diis_start = 3;
+  o->prec = FNO_FP64;
+  o->guess = 0;
+}
+
+int fno_ccsdt(fno_ctx* ctx, const fno_cc_opts* opts, double* e_corr, double* e_tot, int* iters, double* res_norm) {
+  return guard(ctx, [&](fno::Context& c) {
+    fno_cc_opts d;
+    fno_cc_opts_default(&d);
+    const fno_cc_opts& o = opts ? *opts : d;
+    FNO_REQUIRE(o.guess == 0, FNO_EINVAL, "only the zero-amplitude (MP2 first step) guess is available");
+    fno::CCOptions co;
+    co.max_iter = o.max_iter;
+    co.r_tol = o.r_tol;
+    co.e_tol = o.e_tol;
+    co.diis_n = o.diis_n;
+    co.diis_start = o.diis_start;
+    co.prec = to_prec(o.prec);
+    int st = c.ccsdt(co, e_corr, e_tot, iters, res_norm);
+    if (st == FNO_ENOCONV) ctx->err = "CCSDT did not converge within max_iter";
+    return st;
+  });
+}
+
+void fno_eom_opts_default(fno_eom_opts* o) {
+  if (!o) return;
+  o->nroots = 4;
+  o->max_iter = 60;
+  o->max_sub = 0;
+  o->e_tol = 1e-8;
+  o->r_tol = 1e-6;
+  o->prec = FNO_FP64;
+  o->guess = 0;
+  o->precond = 0;
+}
+
+int fno_eom(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, double* omega, double* e_tot,
+            double* res_norm, int* iters) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(kind >= FNO_IP && kind <= FNO_DEA, FNO_EINVAL, "unknown EOM kind");
+    FNO_REQUIRE(c.cc_done, FNO_ESTATE, "fno_eom needs a converged fno_ccsdt first");
+    fno_eom_opts d;
+    fno_eom_opts_default(&d);
+    const fno_eom_opts& o = opts ? *opts : d;
+    FNO_REQUIRE(omega != nullptr, FNO_EINVAL, "omega is required");
+    FNO_REQUIRE(o.guess == 0 && o.precond == 0, FNO_EINVAL, "unsupported guess/preconditioner option");
+    fno::EOMOptions eo;
+    eo.nroots = o.nroots;
+    eo.max_iter = o.max_iter;
+    eo.max_sub = o.max_sub;
+    eo.e_tol = o.e_tol;
+    eo.r_tol = o.r_tol;
+    eo.prec = to_prec(o.prec);
+    fno::EOMResult r;
+    int st = c.eom((int)kind, eo, r);
+    for (int k = 0; k < o.nroots; ++k) {
+      omega[k] = r.omega[k];
+      if (e_tot) e_tot[k] = c.e_ref + c.e_corr + r.omega[k];
+      if (res_norm) res_norm[k] = r.res_norm[k];
+    }
+    if (iters) *iters = r.iters;
+    if (st == FNO_ENOCONV) ctx->err = "EOM Davidson did not converge within max_iter";
+    return st;
+  });
+}
+
+int fno_sizes(const fno_ctx* ctx, int* nocc, int* nvir, int* nvir_full) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  if (!ctx->c->loaded) return FNO_ESTATE;
+  if (nocc) *nocc = ctx->c->nocc;
+  if (nvir) *nvir = ctx->c->nvir;
+  if (nvir_full) *nvir_full = ctx->c->nvir_full;
+  return FNO_OK;
+}
+
+size_t fno_amplitude_size(const fno_ctx* ctx, int block) {
+  if (!ctx || !ctx->c || !ctx->c->loaded) return 0;
+  long o = ctx->c->nocc, v = ctx->c->nvir;
+  if (block == 1) return (size_t)(o * v);
+  if (block == 2) return (size_t)(fno::binom_host(o, 2) * fno::binom_host(v, 2));
+  if (block == 3) return (size_t)(fno::binom_host(o, 3) * fno::binom_host(v, 3));
+  return 0;
+}
+
+int fno_get_amplitudes(fno_ctx* ctx, int block, double* buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(buf != nullptr, FNO_EINVAL, "null buffer");
+    c.get_amps(block, buf, len);
+    return FNO_OK;
+  });
+}
+
+int fno_set_amplitudes(fno_ctx* ctx, int block, const double* buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(buf != nullptr, FNO_EINVAL, "null buffer");
+    c.set_amps(block, buf, len);
+    return FNO_OK;
+  });
+}
+
+int fno_cc_residual(fno_ctx* ctx, fno_prec prec, double* r1, double* r2, double* r3, double* e_corr) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.cc_residual(to_prec(prec), r1, r2, r3, e_corr);
+    return FNO_OK;
+  });
+}
+
+size_t fno_eom_size(const fno_ctx* ctx, fno_eom_kind kind) {
+  if (!ctx || !ctx->c || !ctx->c->loaded) return 0;
+  try {
+    return ctx->c->eom_size((int)kind);
+  } catch (...) {
+    return 0;
+  }
+}
+
+int fno_eom_sigma(fno_ctx* ctx, fno_eom_kind kind, fno_prec prec, const double* r, double* sigma, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(r && sigma, FNO_EINVAL, "null buffer");
+    c.eom_sigma((int)kind, to_prec(prec), r, sigma, len);
+    return FNO_OK;
+  });
+}
+
+int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  if (triples_flops) *triples_flops = ctx->c->last_triples_flops;
+  if (all_flops) *all_flops = ctx->c->last_all_flops;
+  return FNO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,336 @@
+// Ground-state CCSDT on the device: T1 dressing, residual terms, Jacobi + DIIS.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "context.hpp"
+#include "linalg.hpp"
+
+namespace fno {
+
+#include "ccsdt_terms.inc"
+
+namespace {
+template <size_t N>
+int count(const char* const (&)[N]) {
+  return (int)N;
+}
+
+// "name : spec" -> (name, spec)
+std::pair<std::string, std::string> split_decl(const char* d) {
+  std::string s(d);
+  size_t c = s.find(':');
+  auto trim = [](std::string x) {
+    size_t a = x.find_first_not_of(' '), b = x.find_last_not_of(' ');
+    return a == std::string::npos ? std::string() : x.substr(a, b - a + 1);
+  };
+  return {trim(s.substr(0, c)), trim(s.substr(c + 1))};
+}
+}  // namespace
+
+double* Context::alloc(int64_t n) {
+  double* p = nullptr;
+  FNO_HIP(hipMalloc(&p, (size_t)std::max<int64_t>(n, 1) * sizeof(double)));
+  launch_fill(p, 0.0, n, eng->stream);
+  owned_.push_back(p);
+  return p;
+}
+
+double Context::dot(const double* x, const double* y, int64_t n) {
+  launch_dots(x, 0, 1, y, n, scratch_, dscal_, eng->stream);
+  double r;
+  FNO_HIP(hipMemcpyAsync(&r, dscal_, sizeof(double), hipMemcpyDeviceToHost, eng->stream));
+  FNO_HIP(hipStreamSynchronize(eng->stream));
+  return r;
+}
+
+// Views "name = parent(s0,s1,...)" with s = o (occupied), v (virtual), n (all).
+static void make_views(Engine& e, const char* const* views, int nviews, int nocc, int nvir) {
+  for (int i = 0; i < nviews; ++i) {
+    std::string s(views[i]);
+    size_t eq = s.find('='), lp = s.find('('), rp = s.find(')');
+    std::string name = s.substr(0, eq);
+    name.erase(std::remove(name.begin(), name.end(), ' '), name.end());
+    std::string par = s.substr(eq + 1, lp - eq - 1);
+    par.erase(std::remove(par.begin(), par.end(), ' '), par.end());
+    std::vector<std::pair<int, int>> rng;
+    for (char c : s.substr(lp + 1, rp - lp - 1)) {
+      if (c == 'o') rng.push_back({0, nocc});
+      if (c == 'v') rng.push_back({nocc, nvir});
+      if (c == 'n') rng.push_back({0, nocc + nvir});
+    }
+    e.view(name, e.get(par), rng);
+  }
+}
+
+void Context::setup_cc() {
+  Engine& e = *eng;
+  const int o = nocc, v = nvir, n = nocc + nvir;
+  sz_.n = {{'o', o}, {'v', v}, {'n', n}};
+  // contiguous amplitude / residual vectors [1|2|3]
+  tblocks_ = {{1, 1, "1"}, {2, 2, "2"}, {3, 3, "3"}};
+  const char* specs[3] = {"o,v", "oo,vv", "ooo,vvv"};
+  nt_ = 0;
+  for (int k = 0; k < 3; ++k) {
+    tblocks_[k].size = Engine::spec_size(specs[k], sz_);
+    tblocks_[k].offset = nt_;
+    nt_ += tblocks_[k].size;
+  }
+  amp_ = alloc(nt_);
+  res_ = alloc(nt_);
+  den_ = alloc(nt_);
+  scratch_ = alloc(64 * 1024);
+  dscal_ = alloc(1024);
+  for (int k = 0; k < 3; ++k) {
+    e.create("T" + tblocks_[k].name, specs[k], sz_, amp_ + tblocks_[k].offset);
+    e.create("R" + tblocks_[k].name, specs[k], sz_, res_ + tblocks_[k].offset);
+    e.create("D" + tblocks_[k].name, specs[k], sz_, den_ + tblocks_[k].offset);
+  }
+  for (int i = 0; i < count(kCCDecl); ++i) {
+    auto d = split_decl(kCCDecl[i]);
+    if (e.has(d.first)) continue;
+    e.create(d.first, d.second, sz_);
+  }
+  // dense integrals of the working space and dressing work arrays
+  Tensor* G = e.get("G");
+  e.set_sym(G, {{0, 1}, {2, 3}});
+  Tensor* Gd = e.create("Gd", "n,n,n,n", sz_);
+  e.set_sym(Gd, {{0, 1}, {2, 3}});
+  e.create("Gtmp", "n,n,n,n", sz_);
+  for (const char* nm : {"Fd", "Xt", "Yt", "Ftmp", "Ident"}) e.create(nm, "n,n", sz_);
+  e.create("Iocc", "o,o", sz_);
+  {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    FNO_HIP(hipMemcpy(e.get("Ident")->d, I.data(), I.size() * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> Io((size_t)o * o, 0.0);
+    for (int i = 0; i < o; ++i) Io[(size_t)i * o + i] = 1.0;
+    FNO_HIP(hipMemcpy(e.get("Iocc")->d, Io.data(), Io.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  make_views(e, kCCViews, count(kCCViews), o, v);
+  e.view("Xt_vo", e.get("Xt"), {{o, v}, {0, o}});
+  e.view("Yt_vo", e.get("Yt"), {{o, v}, {0, o}});
+  e.view("Gd_nono", Gd, {{0, n}, {0, o}, {0, n}, {0, o}});
+  // denominators D = sum f_holes - sum f_particles over the packed blocks
+  std::vector<double> eo(o), ev(v);
+  for (int i = 0; i < o; ++i) eo[i] = fock[(size_t)i * n + i];
+  for (int a = 0; a < v; ++a) ev[a] = fock[(size_t)(o + a) * n + (o + a)];
+  double* d_eo = alloc(o);
+  double* d_ev = alloc(v);
+  FNO_HIP(hipMemcpy(d_eo, eo.data(), o * sizeof(double), hipMemcpyHostToDevice));
+  FNO_HIP(hipMemcpy(d_ev, ev.data(), v * sizeof(double), hipMemcpyHostToDevice));
+  for (int k = 0; k < 3; ++k) {
+    MatDim md{};
+    int nh = tblocks_[k].nh, np = tblocks_[k].np;
+    md.ngroups = 2;
+    md.grp[0].g = nh;
+    md.grp[0].n = o;
+    md.grp[0].count = (int64_t)binom_host(o, nh);
+    md.grp[1].g = np;
+    md.grp[1].n = v;
+    md.grp[1].count = (int64_t)binom_host(v, np);
+    for (int s = 0; s < nh; ++s) md.grp[0].letter[s] = (int8_t)s;
+    for (int s = 0; s < np; ++s) md.grp[1].letter[s] = (int8_t)(nh + s);
+    md.size = md.grp[0].count * md.grp[1].count;
+    launch_denominators(e.tables, md, nh, d_eo, d_ev, den_ + tblocks_[k].offset, e.stream);
+  }
+  cc_ready = true;
+}
+
+// H^ = e^{-T1} H e^{T1}: creation indices transform with X = 1 - t1 (block
+// X[a,i] = -t_i^a), annihilation indices with Y = 1 + t1 (Y[a,i] = t_i^a).
+// Each of the four index transformations is one GEMM that rotates the
+// contracted index to the back, so all operands are used in place.
+void Context::dress() {
+  Engine& e = *eng;
+  const int n = nocc + nvir;
+  const int64_t nn = (int64_t)n * n;
+  launch_axpby(e.get("Xt")->d, e.get("Ident")->d, 1.0, 0.0, nn, e.stream);
+  launch_axpby(e.get("Yt")->d, e.get("Ident")->d, 1.0, 0.0, nn, e.stream);
+  e.term("Xt_vo[am] -= 1 * T1[ma]");
+  e.term("Yt_vo[am] += 1 * T1[ma]");
+  e.zero(e.get("Gtmp"));
+  e.term("Gtmp[qrsP] += 1 * G[pqrs] * Xt[Pp]");
+  e.zero(e.get("Gd"));
+  e.term("Gd[rsPQ] += 1 * Gtmp[qrsP] * Xt[Qq]");
+  e.zero(e.get("Gtmp"));
+  e.term("Gtmp[sPQR] += 1 * Gd[rsPQ] * Yt[rR]");
+  e.zero(e.get("Gd"));
+  e.term("Gd[PQRS] += 1 * Gtmp[sPQR] * Yt[sS]");
+  // f^ = X h Y + sum_i g^[p i q i]
+  e.zero(e.get("Ftmp"));
+  e.zero(e.get("Fd"));
+  e.term("Ftmp[pQ] += 1 * Hcore[pq] * Yt[qQ]");
+  e.term("Fd[PQ] += 1 * Xt[Pp] * Ftmp[pQ]");
+  e.term("Fd[pq] += 1 * Gd_nono[piqj] * Iocc[ij]");
+}
+
+double Context::energy() {
+  Engine& e = *eng;
+  e.zero(e.get("E"));
+  e.zero(e.get("Ie"));
+  e.terms(kCCEnergy, count(kCCEnergy));
+  double r;
+  FNO_HIP(hipMemcpyAsync(&r, e.get("E")->d, sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  FNO_HIP(hipStreamSynchronize(e.stream));
+  return r;
+}
+
+void Context::residual() {
+  Engine& e = *eng;
+  launch_fill(res_, 0.0, nt_, e.stream);
+  for (const char* nm : {"F2_vv", "F2_oo", "W2_oooo", "W2_vvvv", "W2_ovvo", "F3_vv", "F3_oo", "W3_oooo", "W3_vvvv",
+                         "W3_ovvo", "W3_vvvo", "W3_ovoo"})
+    e.zero(e.get(nm));
+  dress();
+  e.stats.clear();
+  e.record = true;
+  Prec keep = e.prec;
+  // the doubles/singles part is O(N^6): it stays in FP64; the triples terms
+  // (and the T3 pieces of the triples intermediates) use the requested precision
+  e.prec = Prec::FP64;
+  e.terms(kCCInter2, count(kCCInter2));
+  e.terms(kCCR1, count(kCCR1));
+  e.terms(kCCR2, count(kCCR2));
+  e.terms(kCCInter3, count(kCCInter3));
+  e.prec = keep;
+  e.terms(kCCR3, count(kCCR3));
+  e.prec = keep;
+  e.record = false;
+  tally_flops();
+}
+
+void Context::tally_flops() {
+  double tri = 0, all = 0;
+  for (auto& s : eng->stats) {
+    all += s.flops;
+    if (s.term.find("T3[") != std::string::npos || s.term.find("R3[") != std::string::npos) tri += s.flops;
+  }
+  last_triples_flops = tri;
+  last_all_flops = all;
+}
+
+size_t Context::amp_size(int block) const {
+  if (!cc_ready || block < 1 || block > 3) return 0;
+  return (size_t)tblocks_[block - 1].size;
+}
+
+void Context::get_amps(int block, double* buf, size_t len) {
+  FNO_REQUIRE(cc_ready, kESTATE, "no amplitudes: call fno_ccsdt or fno_set_amplitudes first");
+  FNO_REQUIRE(block >= 1 && block <= 3 && len == amp_size(block), kEINVAL, "bad amplitude block or length");
+  FNO_HIP(hipMemcpy(buf, amp_ + tblocks_[block - 1].offset, len * sizeof(double), hipMemcpyDeviceToHost));
+}
+
+void Context::set_amps(int block, const double* buf, size_t len) {
+  FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
+  if (!cc_ready) setup_cc();
+  FNO_REQUIRE(block >= 1 && block <= 3 && len == amp_size(block), kEINVAL, "bad amplitude block or length");
+  for (size_t i = 0; i < len; ++i) FNO_REQUIRE(std::isfinite(buf[i]), kENONFINITE, "non-finite amplitude");
+  FNO_HIP(hipMemcpy(amp_ + tblocks_[block - 1].offset, buf, len * sizeof(double), hipMemcpyHostToDevice));
+}
+
+void Context::cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec) {
+  FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
+  if (!cc_ready) setup_cc();
+  eng->prec = p;
+  residual();
+  eng->prec = Prec::FP64;
+  double* outs[3] = {r1, r2, r3};
+  for (int k = 0; k < 3; ++k)
+    if (outs[k])
+      FNO_HIP(hipMemcpyAsync(outs[k], res_ + tblocks_[k].offset, tblocks_[k].size * sizeof(double),
+                             hipMemcpyDeviceToHost, eng->stream));
+  double E = energy();
+  if (ec) *ec = E;
+  FNO_HIP(hipStreamSynchronize(eng->stream));
+}
+
+int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, double* rn) {
+  FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
+  FNO_REQUIRE(opt.max_iter > 0 && opt.diis_n >= 0 && opt.diis_n <= 16, kEINVAL, "bad solver options");
+  if (!cc_ready) setup_cc();
+  Engine& e = *eng;
+  launch_fill(amp_, 0.0, nt_, e.stream);
+  const int m = opt.diis_n;
+  std::vector<double*> ht(std::max(m, 1)), he(std::max(m, 1));
+  double* hist = alloc(2 * (int64_t)std::max(m, 1) * nt_);
+  for (int i = 0; i < std::max(m, 1); ++i) {
+    ht[i] = hist + (int64_t)i * nt_;
+    he[i] = hist + (int64_t)(std::max(m, 1) + i) * nt_;
+  }
+  double* dcoef = alloc(32);
+  std::vector<int> order;   // history slots, oldest first
+  std::vector<double> B(16 * 16, 0.0);  // error overlaps indexed by slot
+  double e_old = energy();
+  double rnorm = INFINITY, de = 0;
+  int it = 0, status = kENOCONV;
+  e.prec = opt.prec;
+  for (it = 1; it <= opt.max_iter; ++it) {
+    residual();
+    rnorm = std::sqrt(dot(res_, res_, nt_));
+    if (!std::isfinite(rnorm)) {
+      e.prec = Prec::FP64;
+      throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
+    }
+    int slot;
+    if ((int)order.size() < std::max(m, 1)) {
+      slot = (int)order.size();
+    } else {
+      slot = order.front();
+      order.erase(order.begin());
+    }
+    order.push_back(slot);
+    launch_axpby(ht[slot], amp_, 1.0, 0.0, nt_, e.stream);
+    launch_jacobi(ht[slot], res_, den_, he[slot], nt_, e.stream);
+    bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
+    if (m > 0) {
+      for (int s : order) B[slot * 16 + s] = B[s * 16 + slot] = dot(he[slot], he[s], nt_);
+    }
+    if (extrap) {
+      const int k = (int)order.size();
+      std::vector<double> A((size_t)(k + 1) * (k + 1), -1.0), rhs(k + 1, 0.0);
+      double scale = 0;
+      for (int a = 0; a < k; ++a) scale = std::max(scale, std::fabs(B[order[a] * 16 + order[a]]));
+      if (scale == 0) scale = 1;
+      for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) A[(size_t)a * (k + 1) + b] = B[order[a] * 16 + order[b]] / scale;
+      A[(size_t)k * (k + 1) + k] = 0.0;
+      rhs[k] = -1.0;
+      if (solve(k + 1, A, rhs)) {
+        // combine in slot order: coefficients c[slot]
+        std::vector<double> c(std::max(m, 1), 0.0);
+        for (int a = 0; a < k; ++a) c[order[a]] = rhs[a];
+        FNO_HIP(hipMemcpyAsync(dcoef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
+        launch_combine(amp_, ht[0], nt_, dcoef, (int)c.size(), 1.0, 0.0, nt_, e.stream);
+        FNO_HIP(hipStreamSynchronize(e.stream));
+      } else {
+        launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
+      }
+    } else {
+      launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
+    }
+    double E = energy();
+    de = E - e_old;
+    e_old = E;
+    if (rnorm < opt.r_tol && std::fabs(de) < opt.e_tol) {
+      status = kOK;
+      break;
+    }
+  }
+  e.prec = Prec::FP64;
+  // release the DIIS history
+  FNO_HIP(hipStreamSynchronize(e.stream));
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), hist), owned_.end());
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), dcoef), owned_.end());
+  FNO_HIP(hipFree(hist));
+  FNO_HIP(hipFree(dcoef));
+  e_corr = e_old;
+  cc_done = true;
+  if (ec) *ec = e_old;
+  if (et) *et = e_ref + e_old;
+  if (iters) *iters = std::min(it, opt.max_iter);
+  if (rn) *rn = rnorm;
+  return status;
+}
+
+}  // namespace fno

@@ -1,0 +1,97 @@
+// Library context: problem data, device tensors and solver state.
+#pragma once
+
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+
+namespace fno {
+
+struct CCOptions {
+  int max_iter = 100;
+  double r_tol = 1e-8, e_tol = 1e-10;
+  int diis_n = 8, diis_start = 3;
+  Prec prec = Prec::FP64;
+};
+
+struct EOMOptions {
+  int nroots = 4, max_iter = 60, max_sub = 0;
+  double e_tol = 1e-8, r_tol = 1e-6;
+  Prec prec = Prec::FP64;
+};
+
+struct EOMResult {
+  std::vector<double> omega, res_norm;
+  int iters = 0;
+  bool converged = false;
+};
+
+// Block layout of an amplitude-like vector: (holes, particles) per block.
+struct Block {
+  int nh, np;
+  std::string name;
+  int64_t size = 0, offset = 0;
+};
+
+class Context {
+ public:
+  explicit Context(int device);
+  ~Context();
+
+  int device;
+  std::unique_ptr<Engine> eng;
+  std::string err;
+
+  // problem
+  int nocc = 0, nvir = 0, nvir_full = 0;
+  double e_nuc = 0;
+  std::vector<double> fock_full;  // host, full space
+  std::vector<double> fock;       // host, working space
+  bool loaded = false, truncated = false, cc_ready = false, cc_done = false;
+  double e_ref = 0, e_corr = 0, e_mp2_full = 0;
+
+  void load(int o, int v, const double* f, const double* g, double en);
+  void truncate(double occt, int keep, int* kept, double* emp2, double* occ);
+  int ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, double* rn);
+  void cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec);
+  size_t amp_size(int block) const;
+  void get_amps(int block, double* buf, size_t len);
+  void set_amps(int block, const double* buf, size_t len);
+
+  // EOM
+  size_t eom_size(int kind);
+  void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len);
+  int eom(int kind, const EOMOptions& opt, EOMResult& res);
+
+  double last_triples_flops = 0, last_all_flops = 0;
+
+ private:
+  // working-space setup
+  void setup_cc();
+  void dress();
+  double energy();
+  void residual();
+  void tally_flops();
+  double dot(const double* x, const double* y, int64_t n);
+
+  SpaceSizes sz_;
+  std::vector<Block> tblocks_;
+  int64_t nt_ = 0;               // packed amplitude vector length
+  double* amp_ = nullptr;        // [T1|T2|T3]
+  double* res_ = nullptr;        // [R1|R2|R3]
+  double* den_ = nullptr;        // denominators
+  double* scratch_ = nullptr;    // dot partials
+  double* dscal_ = nullptr;      // device scalars
+  std::vector<double*> owned_;
+
+  // EOM state
+  struct EomSpace;
+  std::unique_ptr<EomSpace> eom_;
+  void setup_eom(int kind);
+
+  double* alloc(int64_t n);
+};
+
+}  // namespace fno

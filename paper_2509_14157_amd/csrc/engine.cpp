@@ -1,0 +1,691 @@
+// Contraction planner and executor (host side).
+#include "engine.hpp"
+
+#include <algorithm>
+#include <cctype>
+#include <cstring>
+#include <functional>
+#include <sstream>
+
+namespace fno {
+
+// ------------------------------------------------------------------ tables
+static void colex_tuples(int n, int g, std::vector<uint8_t>& out) {
+  // colex order: by largest element, then recursively
+  std::vector<int> cur(g);
+  std::function<void(int, int)> rec = [&](int pos, int limit) {
+    // choose cur[pos] < limit, cur[pos] is the largest among positions <= pos
+    for (int x = pos; x < limit; ++x) {
+      cur[pos] = x;
+      if (pos == 0) {
+        for (int t = 0; t < g; ++t) out.push_back((uint8_t)cur[t]);
+      } else {
+        rec(pos - 1, x);
+      }
+    }
+  };
+  rec(g - 1, n);
+}
+
+Engine::Engine(int dev) : device(dev) {
+  FNO_HIP(hipSetDevice(device));
+  std::vector<uint32_t> b(kBinomN * (kMaxGroup + 1));
+  for (int n = 0; n < kBinomN; ++n)
+    for (int k = 0; k <= kMaxGroup; ++k) b[n * (kMaxGroup + 1) + k] = (uint32_t)binom_host(n, k);
+  FNO_HIP(hipMalloc(&d_binom_, b.size() * sizeof(uint32_t)));
+  FNO_HIP(hipMemcpy(d_binom_, b.data(), b.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+  tables.binom = d_binom_;
+  const int maxn[kMaxGroup + 1] = {0, 0, 256, 128, 64};
+  for (int g = 2; g <= kMaxGroup; ++g) {
+    std::vector<uint8_t> t;
+    colex_tuples(maxn[g], g, t);
+    // self-check of the colex rank formula
+    for (size_t i = 0; i < t.size() / g; i += 997) {
+      uint64_t r = 0;
+      for (int s = 0; s < g; ++s) r += binom_host(t[i * g + s], s + 1);
+      FNO_REQUIRE(r == i, kEDEVICE, "colex table self-check failed");
+    }
+    FNO_HIP(hipMalloc(&d_dec_[g], t.size()));
+    FNO_HIP(hipMemcpy(d_dec_[g], t.data(), t.size(), hipMemcpyHostToDevice));
+    tables.dec[g] = d_dec_[g];
+    tables.dec_max_n[g] = maxn[g];
+  }
+  tables.dec_max_n[1] = 1 << 30;
+}
+
+Engine::~Engine() {
+  (void)hipSetDevice(device);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : reg_)
+    if (kv.second->owner && kv.second->d) (void)hipFree(kv.second->d);
+  for (int i = 0; i < 5; ++i)
+    if (ws_[i]) (void)hipFree(ws_[i]);
+  if (d_binom_) (void)hipFree(d_binom_);
+  for (int g = 0; g <= kMaxGroup; ++g)
+    if (d_dec_[g]) (void)hipFree(d_dec_[g]);
+}
+
+void* Engine::workspace(int slot, size_t bytes) {
+  if (bytes > ws_bytes_[slot]) {
+    if (ws_[slot]) {
+      FNO_HIP(hipStreamSynchronize(stream));
+      FNO_HIP(hipFree(ws_[slot]));
+      ws_[slot] = nullptr;
+      ws_bytes_[slot] = 0;
+    }
+    size_t b = std::max(bytes, (size_t)(1 << 20));
+    FNO_HIP(hipMalloc(&ws_[slot], b));
+    ws_bytes_[slot] = b;
+  }
+  return ws_[slot];
+}
+
+// ------------------------------------------------------------------ tensors
+int64_t Engine::spec_size(const std::string& spec, const SpaceSizes& sz) {
+  std::stringstream ss(spec);
+  std::string tok;
+  int64_t e = 1;
+  while (std::getline(ss, tok, ',')) {
+    if (tok.empty()) continue;
+    auto it = sz.n.find(tok[0]);
+    FNO_REQUIRE(it != sz.n.end(), kEINVAL, std::string("unknown space ") + tok[0]);
+    e *= (int64_t)binom_host(it->second, (int)tok.size());
+  }
+  return e;
+}
+
+Tensor* Engine::create(const std::string& name, const std::string& spec, const SpaceSizes& sz, double* external) {
+  FNO_REQUIRE(!reg_.count(name), kEINVAL, "tensor exists: " + name);
+  auto t = std::make_unique<Tensor>();
+  t->name = name;
+  std::stringstream ss(spec);
+  std::string tok;
+  while (std::getline(ss, tok, ',')) {
+    if (tok.empty()) continue;
+    Group g;
+    g.g = (int)tok.size();
+    for (char c : tok) FNO_REQUIRE(c == tok[0], kEINVAL, "mixed spaces in group " + tok);
+    auto it = sz.n.find(tok[0]);
+    FNO_REQUIRE(it != sz.n.end(), kEINVAL, std::string("unknown space ") + tok[0]);
+    g.n = g.ext = it->second;
+    FNO_REQUIRE(g.g <= kMaxGroup, kEINVAL, "group too large");
+    if (g.g > 1) FNO_REQUIRE(g.n <= tables.dec_max_n[g.g], kEINVAL, "index range too large for packed group");
+    t->groups.push_back(g);
+  }
+  FNO_REQUIRE(t->nslots() <= kMaxSlots && (int)t->groups.size() <= kMaxGroups, kEINVAL, "tensor rank too large");
+  int64_t e = 1;
+  int slot = 0;
+  for (auto& g : t->groups) {
+    e *= g.storage();
+    std::vector<int> sl;
+    for (int k = 0; k < g.g; ++k) sl.push_back(slot++);
+    t->sym.push_back(sl);
+  }
+  t->elems = e;
+  if (external) {
+    t->d = external;
+    t->owner = false;
+  } else {
+    if (e > 0) {
+      FNO_HIP(hipMalloc(&t->d, (size_t)e * sizeof(double)));
+      launch_fill(t->d, 0.0, e, stream);
+    }
+    t->owner = true;
+  }
+  Tensor* p = t.get();
+  reg_[name] = std::move(t);
+  return p;
+}
+
+Tensor* Engine::view(const std::string& name, Tensor* parent, const std::vector<std::pair<int, int>>& ranges) {
+  FNO_REQUIRE(parent != nullptr, kEINVAL, "view of null tensor");
+  FNO_REQUIRE(ranges.size() == parent->groups.size(), kEINVAL, "view rank mismatch");
+  auto t = std::make_unique<Tensor>(*parent);
+  t->name = name;
+  t->owner = false;
+  for (size_t q = 0; q < ranges.size(); ++q) {
+    Group& g = t->groups[q];
+    int off = ranges[q].first, n = ranges[q].second;
+    if (g.g > 1) {
+      FNO_REQUIRE(off == 0 && n == g.ext, kEINVAL, "packed groups cannot be sliced");
+      continue;
+    }
+    FNO_REQUIRE(off >= 0 && off + n <= g.ext, kEINVAL, "view out of range");
+    g.off = parent->groups[q].off + off;
+    g.n = n;
+  }
+  // a declared antisymmetric slot set survives the view only if all its
+  // slots see the same index range
+  {
+    std::vector<int> slot_grp, slot_first(t->nslots());
+    std::vector<std::pair<int, int>> rng;
+    int s = 0;
+    for (size_t q = 0; q < t->groups.size(); ++q)
+      for (int k = 0; k < t->groups[q].g; ++k, ++s) rng.push_back({t->groups[q].off, t->groups[q].n});
+    std::vector<std::vector<int>> sym;
+    for (auto& set : t->sym) {
+      bool same = true;
+      for (int sl : set) same = same && rng[sl] == rng[set[0]];
+      if (same) {
+        sym.push_back(set);
+      } else {
+        for (int sl : set) sym.push_back({sl});
+      }
+    }
+    t->sym = sym;
+  }
+  Tensor* p = t.get();
+  auto it = reg_.find(name);
+  if (it != reg_.end()) {
+    FNO_REQUIRE(!it->second->owner, kEINVAL, "cannot replace an owning tensor by a view: " + name);
+    // invalidate plans that captured the old view
+    for (auto pit = plans_.begin(); pit != plans_.end();)
+      if (pit->first.find(name) != std::string::npos)
+        pit = plans_.erase(pit);
+      else
+        ++pit;
+  }
+  reg_[name] = std::move(t);
+  return p;
+}
+
+Tensor* Engine::get(const std::string& name) const {
+  auto it = reg_.find(name);
+  FNO_REQUIRE(it != reg_.end(), kEINVAL, "unknown tensor " + name);
+  return it->second.get();
+}
+
+void Engine::set_sym(Tensor* t, const std::vector<std::vector<int>>& sym) {
+  std::vector<int> seen(t->nslots(), 0);
+  for (auto& set : sym)
+    for (int sl : set) {
+      FNO_REQUIRE(sl >= 0 && sl < t->nslots() && !seen[sl], kEINVAL, "bad symmetry partition");
+      seen[sl] = 1;
+    }
+  for (int x : seen) FNO_REQUIRE(x, kEINVAL, "symmetry partition must cover every slot");
+  t->sym = sym;
+}
+
+void Engine::drop(const std::string& name) {
+  auto it = reg_.find(name);
+  if (it == reg_.end()) return;
+  if (it->second->owner && it->second->d) {
+    FNO_HIP(hipStreamSynchronize(stream));
+    FNO_HIP(hipFree(it->second->d));
+  }
+  reg_.erase(it);
+  for (auto pit = plans_.begin(); pit != plans_.end();)
+    if (pit->first.find(name) != std::string::npos)
+      pit = plans_.erase(pit);
+    else
+      ++pit;
+}
+
+void Engine::zero(Tensor* t) {
+  FNO_REQUIRE(t->full_view(), kEINVAL, "zero() needs a whole tensor");
+  launch_fill(t->d, 0.0, t->elems, stream);
+}
+
+// ------------------------------------------------------------------ planning
+struct Engine::Plan {
+  std::string spec;
+  Tensor *out = nullptr, *A = nullptr, *B = nullptr;
+  double alpha = 1;
+  MatDim M{}, N{}, K{};
+  bool a_direct = false, a_kfast = true;
+  int64_t lda = 0;
+  OperandDesc ad{};
+  bool b_direct = false, b_nfast = true;
+  int64_t ldb = 0;
+  OperandDesc bd{};
+  bool x_direct = false;
+  OperandDesc od{};
+  MatDim odims{};
+  FoldCombos fc{};
+  double flops = 0;
+};
+
+namespace {
+
+struct Parsed {
+  std::string out, A, B;
+  std::string lo, la, lb;
+  double coef = 1;
+};
+
+void skip_ws(const std::string& s, size_t& i) {
+  while (i < s.size() && std::isspace((unsigned char)s[i])) ++i;
+}
+
+std::string ident(const std::string& s, size_t& i) {
+  skip_ws(s, i);
+  size_t j = i;
+  while (j < s.size() && (std::isalnum((unsigned char)s[j]) || s[j] == '_')) ++j;
+  FNO_REQUIRE(j > i, kEINVAL, "expected a name in term: " + s);
+  std::string r = s.substr(i, j - i);
+  i = j;
+  return r;
+}
+
+std::string bracket(const std::string& s, size_t& i) {
+  skip_ws(s, i);
+  FNO_REQUIRE(i < s.size() && s[i] == '[', kEINVAL, "expected [ in term: " + s);
+  size_t j = s.find(']', i);
+  FNO_REQUIRE(j != std::string::npos, kEINVAL, "expected ] in term: " + s);
+  std::string r = s.substr(i + 1, j - i - 1);
+  i = j + 1;
+  return r;
+}
+
+Parsed parse(const std::string& s) {
+  Parsed p;
+  size_t i = 0;
+  p.out = ident(s, i);
+  p.lo = bracket(s, i);
+  skip_ws(s, i);
+  double sign = 1;
+  if (s.compare(i, 2, "+=") == 0)
+    sign = 1;
+  else if (s.compare(i, 2, "-=") == 0)
+    sign = -1;
+  else
+    FNO_REQUIRE(false, kEINVAL, "expected += or -= in term: " + s);
+  i += 2;
+  skip_ws(s, i);
+  // optional coefficient
+  size_t j = i;
+  while (j < s.size() && (std::isdigit((unsigned char)s[j]) || s[j] == '.' || s[j] == '-' || s[j] == '/'))
+    ++j;
+  if (j > i) {
+    std::string c = s.substr(i, j - i);
+    size_t sl = c.find('/');
+    if (sl != std::string::npos)
+      p.coef = std::stod(c.substr(0, sl)) / std::stod(c.substr(sl + 1));
+    else
+      p.coef = std::stod(c);
+    i = j;
+    skip_ws(s, i);
+    FNO_REQUIRE(i < s.size() && s[i] == '*', kEINVAL, "expected * after coefficient: " + s);
+    ++i;
+  }
+  p.coef *= sign;
+  p.A = ident(s, i);
+  p.la = bracket(s, i);
+  skip_ws(s, i);
+  if (i < s.size() && s[i] == '*') {
+    ++i;
+    p.B = ident(s, i);
+    p.lb = bracket(s, i);
+  }
+  skip_ws(s, i);
+  FNO_REQUIRE(i == s.size(), kEINVAL, "trailing text in term: " + s);
+  return p;
+}
+
+// letters of a tensor grouped by its storage groups
+std::vector<std::vector<int>> letter_groups(const Tensor* t, const std::vector<int>& ids) {
+  std::vector<std::vector<int>> out;
+  size_t s = 0;
+  for (auto& g : t->groups) {
+    std::vector<int> v;
+    for (int k = 0; k < g.g; ++k) v.push_back(ids[s++]);
+    out.push_back(v);
+  }
+  return out;
+}
+
+// letters of a tensor grouped by its antisymmetry partition
+std::vector<std::vector<int>> letter_syms(const Tensor* t, const std::vector<int>& ids) {
+  std::vector<std::vector<int>> out;
+  for (auto& set : t->sym) {
+    std::vector<int> v;
+    for (int sl : set) v.push_back(ids[sl]);
+    out.push_back(v);
+  }
+  return out;
+}
+
+int64_t factorial(int n) {
+  int64_t r = 1;
+  for (int i = 2; i <= n; ++i) r *= i;
+  return r;
+}
+
+int perm_sign(const std::vector<int>& p) {
+  std::vector<int> q = p;
+  int s = 1;
+  for (size_t i = 0; i < q.size(); ++i)
+    while (q[i] != (int)i) {
+      std::swap(q[i], q[q[i]]);
+      s = -s;
+    }
+  return s;
+}
+
+}  // namespace
+
+std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
+  auto it = plans_.find(spec);
+  if (it != plans_.end()) return it->second;
+  Parsed ps = parse(spec);
+  auto P = std::make_shared<Plan>();
+  P->spec = spec;
+  P->out = get(ps.out);
+  P->A = get(ps.A);
+  P->B = ps.B.empty() ? nullptr : get(ps.B);
+  FNO_REQUIRE((int)ps.lo.size() == P->out->nslots(), kEINVAL, "letter count mismatch (out): " + spec);
+  FNO_REQUIRE((int)ps.la.size() == P->A->nslots(), kEINVAL, "letter count mismatch (A): " + spec);
+  if (P->B) FNO_REQUIRE((int)ps.lb.size() == P->B->nslots(), kEINVAL, "letter count mismatch (B): " + spec);
+
+  // letter ids and extents
+  std::vector<char> letters;
+  auto id_of = [&](char c) {
+    auto f = std::find(letters.begin(), letters.end(), c);
+    if (f != letters.end()) return (int)(f - letters.begin());
+    letters.push_back(c);
+    return (int)letters.size() - 1;
+  };
+  std::vector<int> io, ia, ib;
+  for (char c : ps.lo) io.push_back(id_of(c));
+  for (char c : ps.la) ia.push_back(id_of(c));
+  for (char c : ps.lb) ib.push_back(id_of(c));
+  const int L = (int)letters.size();
+  FNO_REQUIRE(L <= kMaxLetters, kEINVAL, "too many letters: " + spec);
+  std::vector<int> ext(L, -1);
+  auto note_ext = [&](const Tensor* t, const std::vector<int>& ids) {
+    size_t s = 0;
+    for (auto& g : t->groups)
+      for (int k = 0; k < g.g; ++k, ++s) {
+        int l = ids[s];
+        if (ext[l] < 0) ext[l] = g.n;
+        FNO_REQUIRE(ext[l] == g.n, kEINVAL, "extent mismatch of letter " + std::string(1, letters[l]) + ": " + spec);
+      }
+  };
+  note_ext(P->out, io);
+  note_ext(P->A, ia);
+  if (P->B) note_ext(P->B, ib);
+  auto in = [](const std::vector<int>& v, int l) { return std::find(v.begin(), v.end(), l) != v.end(); };
+  for (int l = 0; l < L; ++l) {
+    int c = in(io, l) + in(ia, l) + in(ib, l);
+    FNO_REQUIRE(c == 2 || (c == 1 && in(io, l) && !P->B), kEINVAL,
+                "each letter must appear in exactly two tensors: " + spec);
+    FNO_REQUIRE(!(in(io, l) && !in(ia, l) && !in(ib, l)), kEINVAL, "free output letter: " + spec);
+  }
+  for (int l = 0; l < L; ++l) FNO_REQUIRE(std::count(io.begin(), io.end(), l) <= 1, kEINVAL, "repeated letter");
+
+  // output symmetry is always its storage packing; operands may carry more
+  auto go = letter_groups(P->out, io);
+  auto ga = letter_syms(P->A, ia);
+  auto ga_st = letter_groups(P->A, ia);
+  std::vector<std::vector<int>> gb, gb_st;
+  if (P->B) {
+    gb = letter_syms(P->B, ib);
+    gb_st = letter_groups(P->B, ib);
+  }
+
+  // X row groups (from A), column groups (from B), K groups (A x B)
+  std::vector<std::vector<int>> mg, ngp, kg;
+  for (auto& a : ga)
+    for (auto& o : go) {
+      std::vector<int> v;
+      for (int l : a)
+        if (in(o, l)) v.push_back(l);
+      if (!v.empty()) mg.push_back(v);
+    }
+  for (auto& b : gb)
+    for (auto& o : go) {
+      std::vector<int> v;
+      for (int l : b)
+        if (in(o, l)) v.push_back(l);
+      if (!v.empty()) ngp.push_back(v);
+    }
+  int64_t kfac = 1;
+  for (auto& a : ga)
+    for (auto& b : gb) {
+      std::vector<int> v;
+      for (int l : a)
+        if (in(b, l)) v.push_back(l);
+      if (!v.empty()) {
+        kg.push_back(v);
+        kfac *= factorial((int)v.size());
+      }
+    }
+  auto mkdim = [&](const std::vector<std::vector<int>>& gs) {
+    MatDim d{};
+    FNO_REQUIRE((int)gs.size() <= kMaxGroups, kEINVAL, "too many groups: " + spec);
+    d.ngroups = (int)gs.size();
+    d.size = 1;
+    for (size_t q = 0; q < gs.size(); ++q) {
+      DimGroup& G = d.grp[q];
+      G.g = (int)gs[q].size();
+      FNO_REQUIRE(G.g <= kMaxGroup, kEINVAL, "group too large: " + spec);
+      G.n = ext[gs[q][0]];
+      if (G.g > 1) FNO_REQUIRE(G.n <= tables.dec_max_n[G.g], kEINVAL, "range too large for packed group: " + spec);
+      G.count = G.g == 1 ? G.n : (int64_t)binom_host(G.n, G.g);
+      for (int s = 0; s < G.g; ++s) G.letter[s] = (int8_t)gs[q][s];
+      d.size *= G.count;
+    }
+    return d;
+  };
+  P->M = mkdim(mg);
+  P->N = mkdim(ngp);
+  P->K = mkdim(kg);
+  P->odims = mkdim(go);
+  P->alpha = ps.coef * (double)kfac;
+  P->flops = 2.0 * (double)P->M.size * (double)P->N.size * (double)P->K.size;
+
+  auto opdesc = [&](const Tensor* t, const std::vector<int>& ids) {
+    OperandDesc d{};
+    d.ngroups = (int)t->groups.size();
+    d.base = t->base;
+    auto st = t->strides();
+    size_t s = 0;
+    for (size_t q = 0; q < t->groups.size(); ++q) {
+      GroupDesc& G = d.grp[q];
+      G.g = t->groups[q].g;
+      G.off = t->groups[q].off;
+      G.stride = st[q];
+      for (int k = 0; k < G.g; ++k) G.letter[k] = (int8_t)ids[s++];
+    }
+    return d;
+  };
+  P->ad = opdesc(P->A, ia);
+  if (P->B) P->bd = opdesc(P->B, ib);
+  P->od = opdesc(P->out, io);
+
+  // fold combos: shuffles of every output group over its X sub-blocks
+  std::vector<std::vector<std::pair<std::vector<int>, int>>> per_group;  // (src letters per slot of the group, sign)
+  bool trivial = true;
+  for (auto& o : go) {
+    // sub-blocks: X groups inside this output group, in X-group letter order
+    std::vector<std::vector<int>> subs;
+    for (auto* gl : {&mg, &ngp})
+      for (auto& x : *gl)
+        if (in(o, x[0])) subs.push_back(x);
+    const int m = (int)o.size();
+    std::vector<std::pair<std::vector<int>, int>> list;
+    // recursive assignment of value positions to sub-blocks
+    std::vector<int> valpos(L, -1);  // letter -> value position within the group
+    std::vector<bool> used(m, false);
+    std::function<void(size_t)> rec = [&](size_t sb) {
+      if (sb == subs.size()) {
+        // permutation pi: slot position q (letter o[q]) -> value position
+        std::vector<int> pi(m);
+        for (int q = 0; q < m; ++q) pi[q] = valpos[o[q]];
+        std::vector<int> src(m);
+        for (int q = 0; q < m; ++q) src[q] = o[pi[q]];
+        list.push_back({src, perm_sign(pi)});
+        return;
+      }
+      const auto& sub = subs[sb];
+      const int k = (int)sub.size();
+      // choose k unused positions in increasing order
+      std::vector<int> pick;
+      std::function<void(int)> choose = [&](int start) {
+        if ((int)pick.size() == k) {
+          for (int t = 0; t < k; ++t) {
+            valpos[sub[t]] = pick[t];
+            used[pick[t]] = true;
+          }
+          rec(sb + 1);
+          for (int t = 0; t < k; ++t) used[pick[t]] = false;
+          return;
+        }
+        for (int p = start; p < m; ++p)
+          if (!used[p]) {
+            pick.push_back(p);
+            choose(p + 1);
+            pick.pop_back();
+          }
+      };
+      choose(0);
+    };
+    rec(0);
+    if (list.size() != 1) trivial = false;
+    per_group.push_back(list);
+  }
+  {
+    FoldCombos& fc = P->fc;
+    fc.nletters = L;
+    int total = 1;
+    for (auto& l : per_group) total *= (int)l.size();
+    FNO_REQUIRE(total <= kMaxCombos, kEINVAL, "antisymmetrizer too large: " + spec);
+    fc.ncombo = total;
+    for (int c = 0; c < total; ++c) {
+      int rem = c;
+      int sign = 1;
+      for (int l = 0; l < kMaxLetters; ++l) fc.src[c][l] = (int8_t)(l < L ? l : 0);
+      for (size_t q = 0; q < go.size(); ++q) {
+        int nq = (int)per_group[q].size();
+        int pick = rem % nq;
+        rem /= nq;
+        auto& e = per_group[q][pick];
+        sign *= e.second;
+        for (size_t s = 0; s < go[q].size(); ++s) fc.src[c][go[q][s]] = (int8_t)e.first[s];
+      }
+      fc.sign[c] = (int8_t)sign;
+    }
+  }
+
+  // zero-copy decisions (FP64 only: mixed precision always converts)
+  auto same = [](const std::vector<std::vector<int>>& a, const std::vector<std::vector<int>>& b) { return a == b; };
+  auto cat = [](std::vector<std::vector<int>> a, const std::vector<std::vector<int>>& b) {
+    a.insert(a.end(), b.begin(), b.end());
+    return a;
+  };
+  if ((prec == Prec::FP64 || !P->B) && P->A->full_view()) {
+    if (same(ga_st, cat(mg, kg))) {
+      P->a_direct = true;
+      P->a_kfast = true;
+      P->lda = P->K.size;
+    } else if (same(ga_st, cat(kg, mg))) {
+      P->a_direct = true;
+      P->a_kfast = false;
+      P->lda = P->M.size;
+    }
+  }
+  if (P->B && prec == Prec::FP64 && P->B->full_view()) {
+    if (same(gb_st, cat(kg, ngp))) {
+      P->b_direct = true;
+      P->b_nfast = true;
+      P->ldb = P->N.size;
+    } else if (same(gb_st, cat(ngp, kg))) {
+      P->b_direct = true;
+      P->b_nfast = false;
+      P->ldb = P->K.size;
+    }
+  }
+  if (prec == Prec::FP64 && trivial && P->out->full_view() && P->B && same(go, cat(mg, ngp))) P->x_direct = true;
+  if (!P->a_direct) {
+    P->a_kfast = true;
+    P->lda = P->K.size;
+  }
+  if (!P->b_direct) {
+    P->b_nfast = true;
+    P->ldb = P->N.size;
+  }
+  plans_[spec] = P;
+  return P;
+}
+
+void Engine::execute(const Plan& p, double scale) {
+  const size_t esz = (prec == Prec::FP64) ? 8 : (prec == Prec::FP32 ? 4 : 2);
+  const int64_t Msz = p.M.size, Nsz = p.N.size, Ksz = p.K.size;
+  if (Msz == 0 || Nsz == 0 || p.odims.size == 0) return;
+  const void *A = nullptr, *Alo = nullptr, *B = nullptr, *Blo = nullptr;
+  if (!p.B) {
+    // single operand: fold A (gathered as an M x 1 FP64 matrix) into the output
+    FNO_REQUIRE(Ksz == 1, kEINVAL, "single-operand term with summation: " + p.spec);
+    const void* X = p.A->d + p.A->base;
+    if (!p.a_direct) {
+      void* a = workspace(0, (size_t)Msz * 8);
+      launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, nullptr, Prec::FP64, true, stream);
+      X = a;
+    }
+    launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, Prec::FP64, p.out->d, p.alpha * scale, stream);
+    return;
+  }
+  if (p.a_direct) {
+    A = p.A->d + p.A->base;
+  } else {
+    void* a = workspace(0, (size_t)(Msz * Ksz) * esz);
+    void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
+    launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, alo, prec, true, stream);
+    A = a;
+    Alo = alo;
+  }
+  if (p.B) {
+    if (p.b_direct) {
+      B = p.B->d + p.B->base;
+    } else {
+      void* b = workspace(1, (size_t)(Ksz * Nsz) * esz);
+      void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
+      launch_expand(tables, p.bd, p.K, p.N, p.B->d, b, blo, prec, true, stream);
+      B = b;
+      Blo = blo;
+    }
+  }
+  GemmArgs g{};
+  g.prec = prec;
+  g.M = Msz;
+  g.N = Nsz;
+  g.K = Ksz;
+  g.A = A;
+  g.A_lo = Alo;
+  g.lda = p.lda;
+  g.a_kfast = p.a_kfast;
+  g.B = B;
+  g.B_lo = Blo;
+  g.ldb = p.ldb;
+  g.b_nfast = p.b_nfast;
+  g.tile = -1;
+  if (p.x_direct) {
+    g.C = p.out->d;
+    g.ldc = Nsz;
+    g.alpha = p.alpha * scale;
+    g.beta = 1.0;
+    launch_gemm(g, stream);
+  } else {
+    const size_t xsz = prec == Prec::FP64 ? 8 : 4;
+    void* X = workspace(2, (size_t)(Msz * Nsz) * xsz);
+    g.C = X;
+    g.ldc = Nsz;
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    launch_gemm(g, stream);
+    launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d,
+                p.alpha * scale, stream);
+  }
+  if (record) stats.push_back({p.spec, Msz, Nsz, Ksz, p.flops});
+}
+
+void Engine::term(const std::string& spec, double scale) {
+  auto p = plan(spec);
+  execute(*p, scale);
+}
+
+void Engine::terms(const char* const* specs, int n, double scale) {
+  for (int i = 0; i < n; ++i) term(specs[i], scale);
+}
+
+}  // namespace fno

@@ -1,0 +1,414 @@
+// MFMA GEMM kernels for gfx950.
+//
+// One workgroup (4 wavefronts, 2 x 2) owns a BM x BN tile of C; each
+// wavefront owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.
+// Operand tiles are staged through LDS in k-major order, so that the lanes of
+// one MFMA (row = lane % 16, k = lane / 16) read contiguous LDS words.  The
+// next k-tile is fetched into registers while the current one is consumed.
+//
+// FP64 uses v_mfma_f64_16x16x4f64, FP32 v_mfma_f32_16x16x4f32; split-BF16
+// uses v_mfma_f32_16x16x32_bf16 three times per k-step (hi*hi + hi*lo + lo*hi)
+// with FP32 accumulation.
+#include <hip/hip_bf16.h>
+
+#include "kernels.hpp"
+
+namespace fno {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+  typedef d4_t type;
+};
+template <>
+struct Acc<float> {
+  typedef f4_t type;
+};
+
+__device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// 16x16x4 path (FP64 / FP32).  BK = 16 (4 MFMA k-steps per staged tile).
+template <typename T, int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_PER = BM * BK / 256;  // elements each thread stages
+  constexpr int B_PER = BN * BK / 256;
+  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+
+  typename Acc<T>::type acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (typename Acc<T>::type){0, 0, 0, 0};
+
+  T ra[A_PER], rb[B_PER];
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + p * 256;
+      int mm, kk;
+      if (AK) {  // k fastest in memory: consecutive threads walk k
+        kk = e % BK;
+        mm = e / BK;
+      } else {
+        mm = e % BM;
+        kk = e / BM;
+      }
+      int64_t gm = m0 + mm, gk = k0 + kk;
+      T v = 0;
+      if (gm < M && gk < K) v = AK ? A[gm * lda + gk] : A[gk * lda + gm];
+      ra[p] = v;
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + p * 256;
+      int nn, kk;
+      if (BN_FAST) {
+        nn = e % BN;
+        kk = e / BN;
+      } else {
+        kk = e % BK;
+        nn = e / BK;
+      }
+      int64_t gn = n0 + nn, gk = k0 + kk;
+      T v = 0;
+      if (gn < N && gk < K) v = BN_FAST ? B[gk * ldb + gn] : B[gn * ldb + gk];
+      rb[p] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + p * 256;
+      int mm, kk;
+      if (AK) {
+        kk = e % BK;
+        mm = e / BK;
+      } else {
+        mm = e % BM;
+        kk = e / BM;
+      }
+      As[kk][mm] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + p * 256;
+      int nn, kk;
+      if (BN_FAST) {
+        nn = e % BN;
+        kk = e / BN;
+      } else {
+        kk = e % BK;
+        nn = e / BK;
+      }
+      Bs[kk][nn] = rb[p];
+    }
+  };
+
+  const int64_t nk = (K + BK - 1) / BK;
+  if (nk > 0) load_tiles(0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      T af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(af[i], bfr[j], acc[i][j]);
+    }
+  }
+
+  // C/D layout of the 16x16 MFMA block: lane l holds column l % 16 and rows
+  // 4 * (l / 16) + r, r = 0..3.
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N) {
+          T v = alpha * acc[i][j][r];
+          if (beta != (T)0) v += beta * C[row * ldc + col];
+          C[row * ldc + col] = v;
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Split-BF16 path: operands arrive as hi/lo BF16 pairs.  BK = 32.
+template <int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, int64_t K,
+                                                          const __bf16* __restrict__ Ah,
+                                                          const __bf16* __restrict__ Al, int64_t lda,
+                                                          const __bf16* __restrict__ Bh,
+                                                          const __bf16* __restrict__ Bl, int64_t ldb,
+                                                          float* __restrict__ C, int64_t ldc, float alpha,
+                                                          float beta) {
+  constexpr int BK = 32;
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_PER = BM * BK / 256;
+  constexpr int B_PER = BN * BK / 256;
+  // LDS layout [row][k] so that a lane's 8 consecutive k values are one 16-byte read.
+  constexpr int KP = BK + 8;
+  __shared__ __bf16 Ash[BM][KP], Asl[BM][KP];
+  __shared__ __bf16 Bsh[BN][KP], Bsl[BN][KP];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+
+  f4_t acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (f4_t){0, 0, 0, 0};
+
+  __bf16 rah[A_PER], ral[A_PER], rbh[B_PER], rbl[B_PER];
+  const __bf16 zero = (__bf16)0.0f;
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + p * 256;
+      int mm, kk;
+      if (AK) {
+        kk = e % BK;
+        mm = e / BK;
+      } else {
+        mm = e % BM;
+        kk = e / BM;
+      }
+      int64_t gm = m0 + mm, gk = k0 + kk;
+      __bf16 h = zero, l = zero;
+      if (gm < M && gk < K) {
+        int64_t o = AK ? gm * lda + gk : gk * lda + gm;
+        h = Ah[o];
+        l = Al[o];
+      }
+      rah[p] = h;
+      ral[p] = l;
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + p * 256;
+      int nn, kk;
+      if (BN_FAST) {
+        nn = e % BN;
+        kk = e / BN;
+      } else {
+        kk = e % BK;
+        nn = e / BK;
+      }
+      int64_t gn = n0 + nn, gk = k0 + kk;
+      __bf16 h = zero, l = zero;
+      if (gn < N && gk < K) {
+        int64_t o = BN_FAST ? gk * ldb + gn : gn * ldb + gk;
+        h = Bh[o];
+        l = Bl[o];
+      }
+      rbh[p] = h;
+      rbl[p] = l;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      int e = tid + p * 256;
+      int mm, kk;
+      if (AK) {
+        kk = e % BK;
+        mm = e / BK;
+      } else {
+        mm = e % BM;
+        kk = e / BM;
+      }
+      Ash[mm][kk] = rah[p];
+      Asl[mm][kk] = ral[p];
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      int e = tid + p * 256;
+      int nn, kk;
+      if (BN_FAST) {
+        nn = e % BN;
+        kk = e / BN;
+      } else {
+        kk = e % BK;
+        nn = e / BK;
+      }
+      Bsh[nn][kk] = rbh[p];
+      Bsl[nn][kk] = rbl[p];
+    }
+  };
+
+  const int64_t nk = (K + BK - 1) / BK;
+  if (nk > 0) load_tiles(0);
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+    const int kb = 8 * (lane >> 4);
+    bf8_t ah[TM], al[TM], bh[TN], bl[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+      const int r = wm * WM + i * 16 + (lane & 15);
+      ah[i] = *(const bf8_t*)&Ash[r][kb];
+      al[i] = *(const bf8_t*)&Asl[r][kb];
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int c = wn * WN + j * 16 + (lane & 15);
+      bh[j] = *(const bf8_t*)&Bsh[c][kb];
+      bl[j] = *(const bf8_t*)&Bsl[c][kb];
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        if (row < M && col < N) {
+          float v = alpha * acc[i][j][r];
+          if (beta != 0.0f) v += beta * C[row * ldc + col];
+          C[row * ldc + col] = v;
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tile table used by the planner and the autotuner.
+struct TileCfg {
+  int bm, bn;
+};
+static const TileCfg kTiles[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {64, 32}};
+constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
+
+int gemm_num_tiles(Prec) { return kNumTiles; }
+
+static int default_tile(const GemmArgs& g) {
+  // Prefer big tiles when the grid still fills the 256 CUs several times.
+  auto blocks = [&](int bm, int bn) { return ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn); };
+  if (g.M >= 128 && g.N >= 128 && blocks(128, 128) >= 1024) return 3;
+  if (g.M >= 128 && blocks(128, 64) >= 1024) return 1;
+  if (g.N >= 128 && blocks(64, 128) >= 1024) return 2;
+  if (g.M <= 32) return 4;
+  if (g.N <= 32) return 5;
+  return 0;
+}
+
+template <typename T, int BM, int BN>
+static void launch_k4(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  const T* A = (const T*)g.A;
+  const T* B = (const T*)g.B;
+  T* C = (T*)g.C;
+  T al = (T)g.alpha, be = (T)g.beta;
+  if (g.a_kfast && g.b_nfast)
+    gemm_k4_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+  else if (g.a_kfast)
+    gemm_k4_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+  else if (g.b_nfast)
+    gemm_k4_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+  else
+    gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al,
+                                                                  be);
+}
+
+template <int BM, int BN>
+static void launch_b3(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  const __bf16 *Ah = (const __bf16*)g.A, *Al = (const __bf16*)g.A_lo;
+  const __bf16 *Bh = (const __bf16*)g.B, *Bl = (const __bf16*)g.B_lo;
+  float* C = (float*)g.C;
+  float al = (float)g.alpha, be = (float)g.beta;
+  if (g.a_kfast && g.b_nfast)
+    gemm_bf16x3_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
+                                                               g.ldc, al, be);
+  else if (g.a_kfast)
+    gemm_bf16x3_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
+                                                                g.ldc, al, be);
+  else if (g.b_nfast)
+    gemm_bf16x3_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
+                                                                g.ldc, al, be);
+  else
+    gemm_bf16x3_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
+                                                                 g.ldc, al, be);
+}
+
+template <int BM, int BN>
+static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
+  if (g.prec == Prec::FP64)
+    launch_k4<double, BM, BN>(g, s);
+  else if (g.prec == Prec::FP32)
+    launch_k4<float, BM, BN>(g, s);
+  else
+    launch_b3<BM, BN>(g, s);
+}
+
+void launch_gemm(const GemmArgs& g, hipStream_t s) {
+  if (g.M == 0 || g.N == 0) return;
+  int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
+  switch (t) {
+    case 0: dispatch_tile<64, 64>(g, s); break;
+    case 1: dispatch_tile<128, 64>(g, s); break;
+    case 2: dispatch_tile<64, 128>(g, s); break;
+    case 3: dispatch_tile<128, 128>(g, s); break;
+    case 4: dispatch_tile<32, 64>(g, s); break;
+    default: dispatch_tile<64, 32>(g, s); break;
+  }
+  FNO_HIP(hipGetLastError());
+}
+
+}  // namespace fno

@@ -1,0 +1,49 @@
+// Host-side launchers of the device kernels.
+#pragma once
+
+#include "layout.hpp"
+
+namespace fno {
+
+void launch_expand(const IndexTables& tb, const OperandDesc& op, const MatDim& rows, const MatDim& cols,
+                   const double* src, void* dst, void* dst_lo, Prec prec, bool col_fast, hipStream_t s);
+void launch_fold(const IndexTables& tb, const OperandDesc& outd, const MatDim& outdims, const MatDim& xrows,
+                 const MatDim& xcols, const FoldCombos& fc, const void* X, Prec xprec, double* out, double alpha,
+                 hipStream_t s);
+void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
+void launch_denominators(const IndexTables& tb, const MatDim& dims, int nh, const double* eo, const double* ev,
+                         double* out, hipStream_t s);
+void launch_jacobi(double* t, const double* r, const double* d, double* step, int64_t n, hipStream_t s);
+void launch_precond(double* y, const double* x, const double* d, double shift, int64_t n, hipStream_t s);
+int dot_partial_blocks(int64_t n);
+void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64_t n, double* partial, double* out,
+                 hipStream_t s);
+void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, int nvec, double alpha, double beta,
+                    int64_t n, hipStream_t s);
+
+// C[M x N] (row-major, ldc) = alpha * A * B + beta * C.
+//   a_kfast: A element (m, k) at A[m * lda + k]  (else A[k * lda + m])
+//   b_nfast: B element (k, n) at B[k * ldb + n]  (else B[n * ldb + k])
+// FP64 and FP32 operands use the 16x16x4 MFMA of their type; BF16X3 takes
+// hi/lo operand pairs and accumulates hi*hi + hi*lo + lo*hi in FP32.
+struct GemmArgs {
+  Prec prec;
+  int64_t M, N, K;
+  const void* A;
+  const void* A_lo;
+  int64_t lda;
+  bool a_kfast;
+  const void* B;
+  const void* B_lo;
+  int64_t ldb;
+  bool b_nfast;
+  void* C;
+  int64_t ldc;
+  double alpha, beta;
+  int tile;   // tile configuration index (autotuner), -1 = default
+};
+void launch_gemm(const GemmArgs& g, hipStream_t s);
+int gemm_num_tiles(Prec p);
+
+}  // namespace fno

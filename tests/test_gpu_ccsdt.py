@@ -1,0 +1,131 @@
+"""GPU parity of ground-state FNO-CCSDT against the CPU oracle (through the C ABI).
+
+Tolerances: FP64 residual elements to 1e-11 relative to the largest element
+(the GEMMs sum in a different order than numpy), energies to 1e-8 Eh;
+FP32 / split-BF16 triples contractions to 1e-5 Eh on the converged energy.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synthetic import make_hamiltonian, config_hamiltonian
+from oracle import cc, det, fno
+from tests.helpers import random_amps
+from tests.packing import pack, LazyAntisym
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2509_14157_amd as P
+    return P
+
+
+def _ctx(P, h):
+    c = P.Context(0)
+    c.load_hamiltonian(h.fock, h.eri, h.nocc)
+    return c
+
+
+def _set(c, amps):
+    c.set_amplitudes(1, amps[1].ravel())
+    c.set_amplitudes(2, pack(amps[2], 2, 2))
+    c.set_amplitudes(3, pack(amps[3], 3, 3))
+
+
+@pytest.mark.parametrize("o,v,seed", [(3, 5, 7), (4, 12, 1), (5, 9, 3), (6, 14, 8)])
+def test_residual_matches_oracle(P, o, v, seed):
+    print(f"residual parity o={o} v={v} seed={seed}", flush=True)
+    h = make_hamiltonian(o, v, seed)
+    amps = random_amps(np.random.default_rng(seed), o, v)
+    with _ctx(P, h) as c:
+        _set(c, amps)
+        r1, r2, r3, ec = c.cc_residual("fp64")
+    R = cc.cc_residual(h.fock, h.eri, o, amps)
+    for got, ref in ((r1, R[1].ravel()), (r2, pack(R[2], 2, 2)), (r3, pack(R[3], 3, 3))):
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < 1e-11 * scale
+    assert abs(ec - cc.cc_energy(h.fock, h.eri, o, amps)) < 1e-12
+
+
+def test_ccsdt_exact_for_three_electrons(P):
+    h = make_hamiltonian(3, 5, 21)
+    with _ctx(P, h) as c:
+        r = c.ccsdt(r_tol=1e-11, e_tol=1e-13)
+    assert r["converged"]
+    assert abs(r["e_tot"] - det.DetModel(h.fock, h.eri, 3).fci(3)[0]) < 1e-9
+
+
+def test_ccsdt_energy_small_workload(P):
+    # o=4, v=12 seeded workload, residual 1e-10
+    h = config_hamiltonian("C1")
+    ref = cc.solve_ccsdt(h.fock, h.eri, 4, r_tol=1e-10, e_tol=1e-12)
+    with _ctx(P, h) as c:
+        r = c.ccsdt(r_tol=1e-10, e_tol=1e-12)
+    assert r["converged"]
+    assert abs(r["e_tot"] - ref["e_tot"]) < 1e-8
+    assert abs(r["iters"] - ref["iters"]) <= 1
+
+
+def test_fno_truncation_matches_oracle(P):
+    h = make_hamiltonian(4, 14, 2, evir=(0.2, 6.0))
+    tr = fno.truncate(h.fock, h.eri, 4, occt=0.9)
+    with _ctx(P, h) as c:
+        kept, emp2, occ = c.truncate(0.9)
+        assert kept == tr["nvir"]
+        assert abs(emp2 - fno.mp2_energy(h.fock, h.eri, 4)) < 1e-12
+        assert np.abs(occ - tr["occ"]).max() < 1e-12
+        r = c.ccsdt(r_tol=1e-10, e_tol=1e-12)
+    ref = cc.solve_ccsdt(tr["fock"], tr["eri"], 4, r_tol=1e-10, e_tol=1e-12)
+    assert abs(r["e_tot"] - ref["e_tot"]) < 1e-8
+
+
+def test_fno_full_space_equals_canonical(P):
+    h = make_hamiltonian(3, 7, 4)
+    with _ctx(P, h) as c:
+        e0 = c.ccsdt(r_tol=1e-10, e_tol=1e-12)["e_tot"]
+        kept, _, _ = c.truncate(1.0)
+        assert kept == 7
+        e1 = c.ccsdt(r_tol=1e-10, e_tol=1e-12)["e_tot"]
+    assert abs(e0 - e1) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_energy(P, prec):
+    h = config_hamiltonian("C1")
+    with _ctx(P, h) as c:
+        e64 = c.ccsdt(r_tol=1e-9, e_tol=1e-11)["e_tot"]
+        r = c.ccsdt(r_tol=1e-6, e_tol=1e-9, prec=prec, allow_noconv=True)
+    assert abs(r["e_tot"] - e64) < 1e-5, (prec, r["e_tot"] - e64)
+
+
+def test_full_size_sampled_residual(P):
+    """o=10, v_full=60 workload (OCCT 0.99): sampled residual elements vs the oracle."""
+    h = config_hamiltonian("C2")
+    tr = fno.truncate(h.fock, h.eri, 10, occt=0.99)
+    o, v = 10, tr["nvir"]
+    rng = np.random.default_rng(11)
+    t1 = rng.normal(0, 0.01, (o, v))
+    t2p = rng.normal(0, 0.01, math.comb(o, 2) * math.comb(v, 2))
+    t3p = rng.normal(0, 0.003, math.comb(o, 3) * math.comb(v, 3))
+    with _ctx(P, h) as c:
+        kept, _, _ = c.truncate(0.99)
+        assert kept == v
+        c.set_amplitudes(1, t1.ravel())
+        c.set_amplitudes(2, t2p)
+        c.set_amplitudes(3, t3p)
+        r1, r2, r3, ec = c.cc_residual("fp64")
+    amps = {1: t1, 2: LazyAntisym(t2p, o, v, 2, 2)[:, :, :, :], 3: LazyAntisym(t3p, o, v, 3, 3)}
+    R2 = LazyAntisym(r2, o, v, 2, 2)
+    R3 = LazyAntisym(r3, o, v, 3, 3)
+    picks3 = [(0, 1, 2, 0, 1, 2), (3, 5, 9, v - 3, v - 2, v - 1), (2, 4, 7, 10, 20, 30), (0, 8, 9, 5, 6, v - 1)]
+    picks2 = [(0, 1, 0, 1), (4, 9, 7, v - 1)]
+    for idx in picks3:
+        ref = cc.cc_residual_element(tr["fock"], tr["eri"], o, amps, 3, idx)
+        assert abs(R3[idx] - ref) < 1e-10 * max(1.0, abs(ref)), idx
+    for idx in picks2:
+        ref = cc.cc_residual_element(tr["fock"], tr["eri"], o, amps, 2, idx)
+        assert abs(R2[idx] - ref) < 1e-10 * max(1.0, abs(ref)), idx
+    assert abs(r1[3 * v + 7] - cc.cc_residual_element(tr["fock"], tr["eri"], o, amps, 1, (3, 7))) < 1e-10
