@@ -160,6 +160,23 @@ int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *
  * GEMM flops (packed forms) of the triples contractions and of all terms. */
 int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops);
 
+/*
+ * Diagnostics.
+ * fno_debug_tensor copies the whole storage (packed layout, FP64) of the named
+ * device tensor of the current problem (e.g. "T3", "R3", "W3_vvvv", "Gd") to
+ * buf; len must equal fno_debug_tensor_size (0 when the name is unknown).
+ * fno_debug_gemm runs one device GEMM C = alpha*A*B + beta*C on host arrays:
+ * A is M x K (a_kfast: row-major, else column-major), B is K x N (b_nfast:
+ * row-major, else column-major), C is M x N row-major; prec selects the MFMA
+ * path (operands are rounded to it on the device), tile a tile shape index
+ * (-1 = default heuristic).  Used to validate the kernels and by the tile
+ * autotuner.
+ */
+size_t fno_debug_tensor_size(fno_ctx *ctx, const char *name);
+int fno_debug_tensor(fno_ctx *ctx, const char *name, double *buf, size_t len);
+int fno_debug_gemm(fno_ctx *ctx, fno_prec prec, int tile, long M, long N, long K, int a_kfast, int b_nfast,
+                   double alpha, double beta, const double *A, const double *B, double *Cmat);
+
 #ifdef __cplusplus
 }
 #endif

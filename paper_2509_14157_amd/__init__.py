@@ -22,7 +22,7 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops"]
+           "fno_eom_sigma", "fno_last_flops", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
 
 
 class FnoError(RuntimeError):
@@ -76,6 +76,11 @@ def library() -> C.CDLL:
         lib.fno_eom_size.restype = C.c_size_t
         lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
+        lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
+        lib.fno_debug_tensor_size.restype = C.c_size_t
+        lib.fno_debug_tensor.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_size_t]
+        lib.fno_debug_gemm.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_long, C.c_long, C.c_long, C.c_int, C.c_int,
+                                       C.c_double, C.c_double, dp, dp, dp]
         _lib = lib
     return _lib
 
@@ -182,6 +187,28 @@ class Context:
         t, a = C.c_double(), C.c_double()
         self._check(self._lib.fno_last_flops(self._h, C.byref(t), C.byref(a)))
         return t.value, a.value
+
+    # ---- diagnostics
+    def debug_tensor(self, name: str) -> np.ndarray:
+        n = int(self._lib.fno_debug_tensor_size(self._h, name.encode()))
+        if n == 0:
+            raise KeyError(name)
+        out = np.zeros(n)
+        self._check(self._lib.fno_debug_tensor(self._h, name.encode(), _dp(out), n))
+        return out
+
+    def debug_gemm(self, A, B, C=None, alpha=1.0, beta=0.0, prec="fp64", tile=-1, a_kfast=True, b_nfast=True):
+        """C = alpha*A@B + beta*C on the device (A: M x K, B: K x N given as logical matrices)."""
+        A = _f64(A)
+        B = _f64(B)
+        M, K = A.shape
+        N = B.shape[1]
+        a = _f64(A if a_kfast else A.T)
+        b = _f64(B if b_nfast else B.T)
+        c = np.zeros((M, N)) if C is None else _f64(C).copy()
+        self._check(self._lib.fno_debug_gemm(self._h, PREC[prec], tile, M, N, K, int(a_kfast), int(b_nfast),
+                                             alpha, beta, _dp(a), _dp(b), _dp(c)))
+        return c
 
     # ---- EOM
     def eom_size(self, kind: str) -> int:

@@ -226,4 +226,28 @@ int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops)
   return FNO_OK;
 }
 
+size_t fno_debug_tensor_size(fno_ctx* ctx, const char* name) {
+  if (!ctx || !ctx->c || !name || !ctx->c->eng->has(name)) return 0;
+  return (size_t)ctx->c->eng->get(name)->elems;
+}
+
+int fno_debug_tensor(fno_ctx* ctx, const char* name, double* buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(name && buf && c.eng->has(name), FNO_EINVAL, "unknown tensor");
+    fno::Tensor* t = c.eng->get(name);
+    FNO_REQUIRE(len == (size_t)t->elems, FNO_EINVAL, "length mismatch");
+    FNO_HIP(hipStreamSynchronize(c.eng->stream));
+    FNO_HIP(hipMemcpy(buf, t->d, len * sizeof(double), hipMemcpyDeviceToHost));
+    return FNO_OK;
+  });
+}
+
+int fno_debug_gemm(fno_ctx* ctx, fno_prec prec, int tile, long M, long N, long K, int a_kfast, int b_nfast,
+                   double alpha, double beta, const double* A, const double* B, double* Cm) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(A && B && Cm && M > 0 && N > 0 && K >= 0, FNO_EINVAL, "bad GEMM arguments");
+    return c.debug_gemm(to_prec(prec), tile, M, N, K, a_kfast != 0, b_nfast != 0, alpha, beta, A, B, Cm);
+  });
+}
+
 }  // extern "C"

@@ -167,9 +167,12 @@ void Context::dress() {
 
 double Context::energy() {
   Engine& e = *eng;
+  Prec keep = e.prec;
+  e.prec = Prec::FP64;  // energies are always FP64
   e.zero(e.get("E"));
   e.zero(e.get("Ie"));
   e.terms(kCCEnergy, count(kCCEnergy));
+  e.prec = keep;
   double r;
   FNO_HIP(hipMemcpyAsync(&r, e.get("E")->d, sizeof(double), hipMemcpyDeviceToHost, e.stream));
   FNO_HIP(hipStreamSynchronize(e.stream));
@@ -178,6 +181,8 @@ double Context::energy() {
 
 void Context::residual() {
   Engine& e = *eng;
+  const Prec tri = e.prec;  // precision of the triples-residual contractions
+  e.prec = Prec::FP64;
   launch_fill(res_, 0.0, nt_, e.stream);
   for (const char* nm : {"F2_vv", "F2_oo", "W2_oooo", "W2_vvvv", "W2_ovvo", "F3_vv", "F3_oo", "W3_oooo", "W3_vvvv",
                          "W3_ovvo", "W3_vvvo", "W3_ovoo"})
@@ -185,17 +190,16 @@ void Context::residual() {
   dress();
   e.stats.clear();
   e.record = true;
-  Prec keep = e.prec;
-  // the doubles/singles part is O(N^6): it stays in FP64; the triples terms
-  // (and the T3 pieces of the triples intermediates) use the requested precision
-  e.prec = Prec::FP64;
+  // dressing, intermediates and the singles/doubles residual are FP64; the
+  // triples residual contractions (ladders, ring, one-body, drivers) run in
+  // the requested precision and accumulate into the FP64 residual
   e.terms(kCCInter2, count(kCCInter2));
   e.terms(kCCR1, count(kCCR1));
   e.terms(kCCR2, count(kCCR2));
   e.terms(kCCInter3, count(kCCInter3));
-  e.prec = keep;
+  e.prec = tri;
   e.terms(kCCR3, count(kCCR3));
-  e.prec = keep;
+  e.prec = tri;
   e.record = false;
   tally_flops();
 }

@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <numeric>
 
 #include "eom_space.hpp"
@@ -105,6 +106,89 @@ void Context::load(int o, int v, const double* f, const double* g, double en) {
   Tensor* H = e.create("Hcore", "n,n", ws);
   FNO_HIP(hipMemcpy(H->d, h.data(), (size_t)n2 * sizeof(double), hipMemcpyHostToDevice));
   FNO_HIP(hipDeviceSynchronize());
+}
+
+int Context::debug_gemm(Prec p, int tile, int64_t M, int64_t N, int64_t K, bool a_kfast, bool b_nfast,
+                        double alpha, double beta, const double* A, const double* B, double* Cm) {
+  // operands are converted on the host to the GEMM input type
+  auto to_bf16 = [](float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    uint32_t r = ((u >> 16) & 1u) + 0x7fffu;  // round to nearest even
+    return (uint16_t)((u + r) >> 16);
+  };
+  auto from_bf16 = [](uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+  };
+  const int64_t na = M * K, nb = K * N, nc = M * N;
+  void *dA = nullptr, *dB = nullptr, *dAl = nullptr, *dBl = nullptr, *dC = nullptr;
+  std::vector<char> hA, hB, hAl, hBl, hC;
+  auto conv = [&](const double* src, int64_t n, std::vector<char>& hi, std::vector<char>& lo) {
+    if (p == Prec::FP64) {
+      hi.assign((const char*)src, (const char*)(src + n));
+    } else if (p == Prec::FP32) {
+      hi.resize(n * 4);
+      for (int64_t i = 0; i < n; ++i) ((float*)hi.data())[i] = (float)src[i];
+    } else {
+      hi.resize(n * 2);
+      lo.resize(n * 2);
+      for (int64_t i = 0; i < n; ++i) {
+        float x = (float)src[i];
+        uint16_t h = to_bf16(x);
+        ((uint16_t*)hi.data())[i] = h;
+        ((uint16_t*)lo.data())[i] = to_bf16(x - from_bf16(h));
+      }
+    }
+  };
+  conv(A, na, hA, hAl);
+  conv(B, nb, hB, hBl);
+  if (p == Prec::FP64) {
+    hC.assign((const char*)Cm, (const char*)(Cm + nc));
+  } else {
+    hC.resize(nc * 4);
+    for (int64_t i = 0; i < nc; ++i) ((float*)hC.data())[i] = (float)Cm[i];
+  }
+  auto up = [&](std::vector<char>& h, void** d) {
+    if (h.empty()) return;
+    FNO_HIP(hipMalloc(d, h.size()));
+    FNO_HIP(hipMemcpy(*d, h.data(), h.size(), hipMemcpyHostToDevice));
+  };
+  up(hA, &dA);
+  up(hB, &dB);
+  up(hAl, &dAl);
+  up(hBl, &dBl);
+  up(hC, &dC);
+  GemmArgs g{};
+  g.prec = p;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = dA;
+  g.A_lo = dAl;
+  g.lda = a_kfast ? K : M;
+  g.a_kfast = a_kfast;
+  g.B = dB;
+  g.B_lo = dBl;
+  g.ldb = b_nfast ? N : K;
+  g.b_nfast = b_nfast;
+  g.C = dC;
+  g.ldc = N;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.tile = tile;
+  launch_gemm(g, eng->stream);
+  FNO_HIP(hipStreamSynchronize(eng->stream));
+  FNO_HIP(hipMemcpy(hC.data(), dC, hC.size(), hipMemcpyDeviceToHost));
+  if (p == Prec::FP64)
+    std::memcpy(Cm, hC.data(), nc * 8);
+  else
+    for (int64_t i = 0; i < nc; ++i) Cm[i] = ((float*)hC.data())[i];
+  for (void* d : {dA, dB, dAl, dBl, dC})
+    if (d) FNO_HIP(hipFree(d));
+  return kOK;
 }
 
 static void fix_signs(int rows, int cols, std::vector<double>& U) {

@@ -66,6 +66,8 @@ class Context {
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
 
   double last_triples_flops = 0, last_all_flops = 0;
+  int debug_gemm(Prec p, int tile, int64_t M, int64_t N, int64_t K, bool a_kfast, bool b_nfast, double alpha,
+                 double beta, const double* A, const double* B, double* Cm);
 
  private:
   // working-space setup

@@ -243,6 +243,7 @@ struct Engine::Plan {
   MatDim odims{};
   FoldCombos fc{};
   double flops = 0;
+  Prec prec = Prec::FP64;
 };
 
 namespace {
@@ -365,7 +366,9 @@ int perm_sign(const std::vector<int>& p) {
 }  // namespace
 
 std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
-  auto it = plans_.find(spec);
+  // zero-copy decisions depend on the precision: plans are cached per precision
+  const std::string key = spec + "#" + std::to_string((int)prec);
+  auto it = plans_.find(key);
   if (it != plans_.end()) return it->second;
   Parsed ps = parse(spec);
   auto P = std::make_shared<Plan>();
@@ -604,11 +607,13 @@ std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
     P->b_nfast = true;
     P->ldb = P->N.size;
   }
-  plans_[spec] = P;
+  P->prec = prec;
+  plans_[key] = P;
   return P;
 }
 
 void Engine::execute(const Plan& p, double scale) {
+  FNO_REQUIRE(p.prec == prec, kEINVAL, "plan precision mismatch: " + p.spec);
   const size_t esz = (prec == Prec::FP64) ? 8 : (prec == Prec::FP32 ? 4 : 2);
   const int64_t Msz = p.M.size, Nsz = p.N.size, Ksz = p.K.size;
   if (Msz == 0 || Nsz == 0 || p.odims.size == 0) return;
@@ -645,6 +650,8 @@ void Engine::execute(const Plan& p, double scale) {
       Blo = blo;
     }
   }
+  if (prec == Prec::BF16X3)
+    FNO_REQUIRE(Alo != nullptr && Blo != nullptr, kEINVAL, "split-BF16 GEMM needs expanded operands: " + p.spec);
   GemmArgs g{};
   g.prec = prec;
   g.M = Msz;

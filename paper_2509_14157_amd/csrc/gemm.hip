@@ -151,8 +151,9 @@ __global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int6
     }
   }
 
-  // C/D layout of the 16x16 MFMA block: lane l holds column l % 16 and rows
-  // 4 * (l / 16) + r, r = 0..3.
+  // C/D layout of the 16x16 MFMA block: lane l holds column l % 16; the
+  // FP32 instruction gives it rows 4 * (l / 16) + r, the FP64 instruction
+  // rows l / 16 + 4 * r (r = 0..3).
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -160,7 +161,8 @@ __global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int6
       const int64_t col = n0 + wn * WN + j * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wm * WM + i * 16 + 4 * (lane >> 4) + r;
+        const int rr = (sizeof(T) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int64_t row = m0 + wm * WM + i * 16 + rr;
         if (row < M && col < N) {
           T v = alpha * acc[i][j][r];
           if (beta != (T)0) v += beta * C[row * ldc + col];
