@@ -172,6 +172,16 @@ int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops)
  * (-1 = default heuristic).  Used to validate the kernels and by the tile
  * autotuner.
  */
+/*
+ * Kernel timing with HIP events on the context's stream.  fno_profile(ctx, 1)
+ * starts recording every expansion, GEMM and fold launch; fno_profile_report
+ * writes a JSON text (per kernel name: launches, total_ms, algorithmic GEMM
+ * flops, operand bytes; per term: the same for the GEMM) into buf (len bytes,
+ * NUL-terminated, FNO_EINVAL if too small) and clears the records.
+ */
+int fno_profile(fno_ctx *ctx, int on);
+int fno_profile_report(fno_ctx *ctx, char *buf, size_t len);
+
 size_t fno_debug_tensor_size(fno_ctx *ctx, const char *name);
 int fno_debug_tensor(fno_ctx *ctx, const char *name, double *buf, size_t len);
 int fno_debug_gemm(fno_ctx *ctx, fno_prec prec, int tile, long M, long N, long K, int a_kfast, int b_nfast,

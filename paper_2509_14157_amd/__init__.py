@@ -22,7 +22,7 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
+           "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
 
 
 class FnoError(RuntimeError):
@@ -76,6 +76,8 @@ def library() -> C.CDLL:
         lib.fno_eom_size.restype = C.c_size_t
         lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
+        lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_debug_tensor_size.restype = C.c_size_t
         lib.fno_debug_tensor.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_size_t]
@@ -187,6 +189,22 @@ class Context:
         t, a = C.c_double(), C.c_double()
         self._check(self._lib.fno_last_flops(self._h, C.byref(t), C.byref(a)))
         return t.value, a.value
+
+    # ---- profiling
+    def profile(self, on: bool = True) -> None:
+        self._check(self._lib.fno_profile(self._h, int(bool(on))))
+
+    def profile_report(self) -> dict:
+        import json
+        size = 1 << 20
+        while True:
+            buf = C.create_string_buffer(size)
+            st = self._lib.fno_profile_report(self._h, buf, size)
+            if st == FNO_OK:
+                return json.loads(buf.value.decode())
+            if size > (1 << 28):
+                self._check(st)
+            size *= 4
 
     # ---- diagnostics
     def debug_tensor(self, name: str) -> np.ndarray:

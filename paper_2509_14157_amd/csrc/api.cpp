@@ -226,6 +226,23 @@ int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops)
   return FNO_OK;
 }
 
+int fno_profile(fno_ctx* ctx, int on) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.eng->profile = on != 0;
+    return FNO_OK;
+  });
+}
+
+int fno_profile_report(fno_ctx* ctx, char* buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(buf != nullptr, FNO_EINVAL, "null buffer");
+    std::string js = c.eng->profile_report();
+    FNO_REQUIRE(js.size() + 1 <= len, FNO_EINVAL, "report buffer too small");
+    std::memcpy(buf, js.c_str(), js.size() + 1);
+    return FNO_OK;
+  });
+}
+
 size_t fno_debug_tensor_size(fno_ctx* ctx, const char* name) {
   if (!ctx || !ctx->c || !name || !ctx->c->eng->has(name)) return 0;
   return (size_t)ctx->c->eng->get(name)->elems;

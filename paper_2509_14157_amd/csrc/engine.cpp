@@ -60,6 +60,7 @@ Engine::~Engine() {
     if (kv.second->owner && kv.second->d) (void)hipFree(kv.second->d);
   for (int i = 0; i < 5; ++i)
     if (ws_[i]) (void)hipFree(ws_[i]);
+  for (auto ev : evpool_) (void)hipEventDestroy(ev);
   if (d_binom_) (void)hipFree(d_binom_);
   for (int g = 0; g <= kMaxGroup; ++g)
     if (d_dec_[g]) (void)hipFree(d_dec_[g]);
@@ -78,6 +79,76 @@ void* Engine::workspace(int slot, size_t bytes) {
     ws_bytes_[slot] = b;
   }
   return ws_[slot];
+}
+
+// ------------------------------------------------------------------ profiling
+hipEvent_t Engine::event() {
+  if (evnext_ == evpool_.size()) {
+    hipEvent_t ev;
+    FNO_HIP(hipEventCreate(&ev));
+    evpool_.push_back(ev);
+  }
+  return evpool_[evnext_++];
+}
+
+void Engine::prof_mark(const std::string& label, const std::string& spec, double flops, double bytes, hipEvent_t a,
+                       hipEvent_t b) {
+  prof_.push_back({label, spec, flops, bytes, a, b});
+}
+
+std::string Engine::profile_report() {
+  FNO_HIP(hipStreamSynchronize(stream));
+  struct Agg {
+    int64_t n = 0;
+    double ms = 0, flops = 0, bytes = 0;
+  };
+  std::map<std::string, Agg> agg;
+  std::map<std::string, Agg> per_term;
+  for (auto& r : prof_) {
+    float ms = 0;
+    FNO_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    Agg& a = agg[r.label];
+    a.n++;
+    a.ms += ms;
+    a.flops += r.flops;
+    a.bytes += r.bytes;
+    if (r.flops > 0) {
+      Agg& t = per_term[r.spec + " @ " + r.label];
+      t.n++;
+      t.ms += ms;
+      t.flops += r.flops;
+    }
+  }
+  auto esc = [](const std::string& s) {
+    std::string o;
+    for (char c : s) {
+      if (c == '"' || c == '\\') o += '\\';
+      o += c;
+    }
+    return o;
+  };
+  std::string js = "{\"kernels\": [";
+  bool first = true;
+  for (auto& kv : agg) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "\"launches\": %lld, \"total_ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+             (long long)kv.second.n, kv.second.ms, kv.second.flops, kv.second.bytes);
+    js += std::string(first ? "" : ", ") + "{\"name\": \"" + esc(kv.first) + "\", " + buf;
+    first = false;
+  }
+  js += "], \"terms\": [";
+  first = true;
+  for (auto& kv : per_term) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "\"launches\": %lld, \"total_ms\": %.6f, \"flops\": %.6e}",
+             (long long)kv.second.n, kv.second.ms, kv.second.flops);
+    js += std::string(first ? "" : ", ") + "{\"term\": \"" + esc(kv.first) + "\", " + buf;
+    first = false;
+  }
+  js += "]}";
+  prof_.clear();
+  evnext_ = 0;
+  return js;
 }
 
 // ------------------------------------------------------------------ tensors
@@ -622,12 +693,19 @@ void Engine::execute(const Plan& p, double scale) {
     // single operand: fold A (gathered as an M x 1 FP64 matrix) into the output
     FNO_REQUIRE(Ksz == 1, kEINVAL, "single-operand term with summation: " + p.spec);
     const void* X = p.A->d + p.A->base;
+    hipEvent_t e0 = profile ? event() : nullptr;
+    if (e0) FNO_HIP(hipEventRecord(e0, stream));
     if (!p.a_direct) {
       void* a = workspace(0, (size_t)Msz * 8);
       launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, nullptr, Prec::FP64, true, stream);
       X = a;
     }
     launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, Prec::FP64, p.out->d, p.alpha * scale, stream);
+    if (e0) {
+      hipEvent_t e1 = event();
+      FNO_HIP(hipEventRecord(e1, stream));
+      prof_mark("fno::copy_fold", p.spec, 0, 16.0 * (double)p.odims.size, e0, e1);
+    }
     return;
   }
   if (p.a_direct) {
@@ -635,7 +713,15 @@ void Engine::execute(const Plan& p, double scale) {
   } else {
     void* a = workspace(0, (size_t)(Msz * Ksz) * esz);
     void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
+    hipEvent_t e0 = profile ? event() : nullptr;
+    if (e0) FNO_HIP(hipEventRecord(e0, stream));
     launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, alo, prec, true, stream);
+    if (e0) {
+      hipEvent_t e1 = event();
+      FNO_HIP(hipEventRecord(e1, stream));
+      prof_mark(prec == Prec::FP64 ? "fno::expand_kernel<double>" : "fno::expand_kernel<lowp>", p.spec, 0,
+                (double)(Msz * Ksz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
+    }
     A = a;
     Alo = alo;
   }
@@ -645,7 +731,15 @@ void Engine::execute(const Plan& p, double scale) {
     } else {
       void* b = workspace(1, (size_t)(Ksz * Nsz) * esz);
       void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
+      hipEvent_t e0 = profile ? event() : nullptr;
+      if (e0) FNO_HIP(hipEventRecord(e0, stream));
       launch_expand(tables, p.bd, p.K, p.N, p.B->d, b, blo, prec, true, stream);
+      if (e0) {
+        hipEvent_t e1 = event();
+        FNO_HIP(hipEventRecord(e1, stream));
+        prof_mark(prec == Prec::FP64 ? "fno::expand_kernel<double>" : "fno::expand_kernel<lowp>", p.spec, 0,
+                  (double)(Ksz * Nsz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
+      }
       B = b;
       Blo = blo;
     }
@@ -666,12 +760,24 @@ void Engine::execute(const Plan& p, double scale) {
   g.ldb = p.ldb;
   g.b_nfast = p.b_nfast;
   g.tile = -1;
+  auto timed_gemm = [&]() {
+    hipEvent_t e0 = profile ? event() : nullptr;
+    if (e0) FNO_HIP(hipEventRecord(e0, stream));
+    launch_gemm(g, stream);
+    if (e0) {
+      hipEvent_t e1 = event();
+      FNO_HIP(hipEventRecord(e1, stream));
+      const double b = (double)esz * (double)(Msz * Ksz + Ksz * Nsz) * (prec == Prec::BF16X3 ? 2 : 1) +
+                       (prec == Prec::FP64 ? 8.0 : 4.0) * (double)(Msz * Nsz);
+      prof_mark(gemm_label(g), p.spec, p.flops, b, e0, e1);
+    }
+  };
   if (p.x_direct) {
     g.C = p.out->d;
     g.ldc = Nsz;
     g.alpha = p.alpha * scale;
     g.beta = 1.0;
-    launch_gemm(g, stream);
+    timed_gemm();
   } else {
     const size_t xsz = prec == Prec::FP64 ? 8 : 4;
     void* X = workspace(2, (size_t)(Msz * Nsz) * xsz);
@@ -679,9 +785,17 @@ void Engine::execute(const Plan& p, double scale) {
     g.ldc = Nsz;
     g.alpha = 1.0;
     g.beta = 0.0;
-    launch_gemm(g, stream);
+    timed_gemm();
+    hipEvent_t e0 = profile ? event() : nullptr;
+    if (e0) FNO_HIP(hipEventRecord(e0, stream));
     launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d,
                 p.alpha * scale, stream);
+    if (e0) {
+      hipEvent_t e1 = event();
+      FNO_HIP(hipEventRecord(e1, stream));
+      prof_mark(prec == Prec::FP64 ? "fno::fold_kernel<double>" : "fno::fold_kernel<float>", p.spec, 0,
+                (double)p.odims.size * (16.0 + (double)p.fc.ncombo * (double)xsz), e0, e1);
+    }
   }
   if (record) stats.push_back({p.spec, Msz, Nsz, Ksz, p.flops});
 }

@@ -112,6 +112,13 @@ class Engine {
   bool record = false;
   std::vector<GemmStats> stats;
 
+  // --- per-kernel profiling with HIP events on `stream`
+  bool profile = false;
+  void prof_mark(const std::string& label, const std::string& spec, double flops, double bytes, hipEvent_t a,
+                 hipEvent_t b);
+  hipEvent_t event();
+  std::string profile_report();  // JSON aggregate per kernel label; clears the records
+
   // workspace sizes (bytes) currently held
   size_t workspace_bytes() const { return ws_bytes_[0] + ws_bytes_[1] + ws_bytes_[2] + ws_bytes_[3] + ws_bytes_[4]; }
   void* workspace(int slot, size_t bytes);
@@ -125,6 +132,14 @@ class Engine {
   size_t ws_bytes_[5] = {0, 0, 0, 0, 0};
   uint32_t* d_binom_ = nullptr;
   uint8_t* d_dec_[kMaxGroup + 1] = {};
+  struct ProfRec {
+    std::string label, spec;
+    double flops, bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<ProfRec> prof_;
+  std::vector<hipEvent_t> evpool_;
+  size_t evnext_ = 0;
   std::shared_ptr<Plan> plan(const std::string& spec);
   void execute(const Plan& p, double scale);
 };

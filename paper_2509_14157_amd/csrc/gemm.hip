@@ -399,6 +399,15 @@ static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
     launch_b3<BM, BN>(g, s);
 }
 
+std::string gemm_label(const GemmArgs& g) {
+  int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
+  std::string bm = std::to_string(kTiles[t].bm), bn = std::to_string(kTiles[t].bn);
+  std::string lay = std::string(g.a_kfast ? "true" : "false") + ", " + (g.b_nfast ? "true" : "false");
+  if (g.prec == Prec::BF16X3) return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ">";
+  return std::string("fno::gemm_k4_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " + bn +
+         ", " + lay + ">";
+}
+
 void launch_gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M == 0 || g.N == 0) return;
   int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);

@@ -1,6 +1,8 @@
 // Host-side launchers of the device kernels.
 #pragma once
 
+#include <string>
+
 #include "layout.hpp"
 
 namespace fno {
@@ -44,6 +46,8 @@ struct GemmArgs {
   int tile;   // tile configuration index (autotuner), -1 = default
 };
 void launch_gemm(const GemmArgs& g, hipStream_t s);
+// Name of the kernel instantiation launch_gemm would use (as tools demangle it).
+std::string gemm_label(const GemmArgs& g);
 int gemm_num_tiles(Prec p);
 
 }  // namespace fno

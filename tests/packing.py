@@ -81,3 +81,28 @@ class LazyAntisym:
 def unpack(packed, nocc, nvir, nh, np_):
     """Packed vector -> full dense antisymmetric array (small sizes)."""
     return LazyAntisym(packed, nocc, nvir, nh, np_)[(slice(None),) * (nh + np_)]
+
+
+def unpack_fast(packed, nocc, nvir, nh, np_):
+    """Packed vector -> dense antisymmetric array by scattering each signed permutation."""
+    from itertools import permutations
+
+    H = colex_tuples(nocc, nh)
+    Pt = colex_tuples(nvir, np_)
+    vals = np.asarray(packed).reshape(len(H), len(Pt))
+    out = np.zeros((nocc,) * nh + (nvir,) * np_)
+
+    def sgn(p):
+        s, p = 1, list(p)
+        for i in range(len(p)):
+            while p[i] != i:
+                j = p[i]
+                p[i], p[j] = p[j], p[i]
+                s = -s
+        return s
+
+    for ph in permutations(range(nh)):
+        for pp in permutations(range(np_)):
+            idx = tuple(H[:, k][:, None] for k in ph) + tuple(Pt[:, k][None, :] for k in pp)
+            out[idx] = sgn(ph) * sgn(pp) * vals
+    return out
