@@ -179,8 +179,15 @@ int Context::debug_gemm(Prec p, int tile, int64_t M, int64_t N, int64_t K, bool 
   g.alpha = alpha;
   g.beta = beta;
   g.tile = tile;
+  g.split = gemm_split_factor(g);
+  void* dW = nullptr;
+  if (g.split > 1) {
+    FNO_HIP(hipMalloc(&dW, gemm_split_bytes(g, g.split)));
+    g.ws = dW;
+  }
   launch_gemm(g, eng->stream);
   FNO_HIP(hipStreamSynchronize(eng->stream));
+  if (dW) FNO_HIP(hipFree(dW));
   FNO_HIP(hipMemcpy(hC.data(), dC, hC.size(), hipMemcpyDeviceToHost));
   if (p == Prec::FP64)
     std::memcpy(Cm, hC.data(), nc * 8);

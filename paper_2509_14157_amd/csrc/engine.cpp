@@ -58,7 +58,7 @@ Engine::~Engine() {
   (void)hipDeviceSynchronize();
   for (auto& kv : reg_)
     if (kv.second->owner && kv.second->d) (void)hipFree(kv.second->d);
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 6; ++i)
     if (ws_[i]) (void)hipFree(ws_[i]);
   for (auto ev : evpool_) (void)hipEventDestroy(ev);
   if (d_binom_) (void)hipFree(d_binom_);
@@ -315,7 +315,108 @@ struct Engine::Plan {
   FoldCombos fc{};
   double flops = 0;
   Prec prec = Prec::FP64;
+  // table-driven expansion / fold (device tables owned by the plan)
+  bool a_tab_ok = false, b_tab_ok = false, f_tab_ok = false;
+  ExpandTab a_tab{}, b_tab{};
+  FoldTab f_tab{};
+  std::vector<void*> bufs;
+  ~Plan() {
+    for (void* p : bufs) (void)hipFree(p);
+  }
 };
+
+namespace {
+// Expansion tables of operand `od` (storage letter groups `st`) into a
+// rows x cols matrix; false when the operand has more straddling groups than
+// the kernel supports.
+bool build_expand_tab(const IndexTables& tb, const OperandDesc& od, const std::vector<std::vector<int>>& st,
+                      const MatDim& rows, const MatDim& cols, ExpandTab& t, std::vector<void*>& bufs,
+                      hipStream_t s) {
+  auto in_dim = [](const MatDim& d, int l) {
+    for (int q = 0; q < d.ngroups; ++q)
+      for (int k = 0; k < d.grp[q].g; ++k)
+        if (d.grp[q].letter[k] == l) return q;
+    return -1;
+  };
+  unsigned row_mask = 0, col_mask = 0;
+  std::vector<int> mixed;
+  for (size_t q = 0; q < st.size(); ++q) {
+    bool r = false, c = false;
+    for (int l : st[q]) {
+      if (in_dim(rows, l) >= 0) r = true;
+      else if (in_dim(cols, l) >= 0) c = true;
+      else return false;
+    }
+    if (r && c)
+      mixed.push_back((int)q);
+    else if (r)
+      row_mask |= 1u << q;
+    else
+      col_mask |= 1u << q;
+  }
+  if ((int)mixed.size() > kMaxMixed) return false;
+  auto dalloc = [&](size_t bytes) {
+    void* p = nullptr;
+    FNO_HIP(hipMalloc(&p, std::max<size_t>(bytes, 8)));
+    bufs.push_back(p);
+    return p;
+  };
+  t = ExpandTab{};
+  t.rows = rows.size;
+  t.cols = cols.size;
+  int64_t* ro = (int64_t*)dalloc(rows.size * 8);
+  int8_t* rs = (int8_t*)dalloc(rows.size);
+  int64_t* co = (int64_t*)dalloc(cols.size * 8);
+  int8_t* cs = (int8_t*)dalloc(cols.size);
+  OperandDesc rod = od, cod = od;
+  rod.base = od.base;  // the view origin is carried by the row table
+  cod.base = 0;
+  launch_dim_table(tb, rod, rows, row_mask, ro, rs, s);
+  launch_dim_table(tb, cod, cols, col_mask, co, cs, s);
+  t.row_off = ro;
+  t.row_sign = rs;
+  t.col_off = co;
+  t.col_sign = cs;
+  t.nmixed = (int)mixed.size();
+  for (int m = 0; m < t.nmixed; ++m) {
+    const int q = mixed[m];
+    unsigned rdm = 0, cdm = 0;
+    MatDim pr{}, pc{};
+    pr.size = pc.size = 1;
+    for (int g = 0; g < rows.ngroups; ++g) {
+      bool inq = false;
+      for (int l : st[q]) inq |= in_dim(rows, l) == g;
+      if (inq) {
+        rdm |= 1u << g;
+        pr.grp[pr.ngroups++] = rows.grp[g];
+        pr.size *= rows.grp[g].count;
+      }
+    }
+    for (int g = 0; g < cols.ngroups; ++g) {
+      bool inq = false;
+      for (int l : st[q]) inq |= in_dim(cols, l) == g;
+      if (inq) {
+        cdm |= 1u << g;
+        pc.grp[pc.ngroups++] = cols.grp[g];
+        pc.size *= cols.grp[g].count;
+      }
+    }
+    int32_t* rsub = (int32_t*)dalloc(rows.size * 4);
+    int32_t* csub = (int32_t*)dalloc(cols.size * 4);
+    int64_t* to = (int64_t*)dalloc(pr.size * pc.size * 8);
+    int8_t* ts = (int8_t*)dalloc(pr.size * pc.size);
+    launch_sub_index(tb, rows, rdm, rsub, s);
+    launch_sub_index(tb, cols, cdm, csub, s);
+    launch_mixed_table(tb, od, q, pr, pc, to, ts, s);
+    t.ncsub[m] = pc.size;
+    t.row_sub[m] = rsub;
+    t.col_sub[m] = csub;
+    t.tab_off[m] = to;
+    t.tab_sign[m] = ts;
+  }
+  return true;
+}
+}  // namespace
 
 namespace {
 
@@ -678,6 +779,62 @@ std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
     P->b_nfast = true;
     P->ldb = P->N.size;
   }
+  // table-driven expansion and fold
+  if (!P->a_direct) P->a_tab_ok = build_expand_tab(tables, P->ad, ga_st, P->M, P->K, P->a_tab, P->bufs, stream);
+  if (P->B && !P->b_direct)
+    P->b_tab_ok = build_expand_tab(tables, P->bd, gb_st, P->K, P->N, P->b_tab, P->bufs, stream);
+  if (!P->x_direct && P->out->full_view() && (int)go.size() <= kMaxOutGroups) {
+    FoldTab& t = P->f_tab;
+    t = FoldTab{};
+    t.ngroups = (int)go.size();
+    t.xcols = P->N.size;
+    auto in_grp = [&](const DimGroup& G, const std::vector<int>& o) {
+      for (int k = 0; k < G.g; ++k)
+        if (!in(o, G.letter[k])) return false;
+      return true;
+    };
+    for (size_t k = 0; k < go.size(); ++k) {
+      const DimGroup& og = P->odims.grp[k];
+      const auto& lst = per_group[k];
+      const int ns = (int)lst.size();
+      std::vector<int8_t> src((size_t)ns * kMaxLetters);
+      for (int s = 0; s < ns; ++s) {
+        for (int l = 0; l < kMaxLetters; ++l) src[(size_t)s * kMaxLetters + l] = (int8_t)(l < L ? l : 0);
+        for (size_t sl = 0; sl < go[k].size(); ++sl) src[(size_t)s * kMaxLetters + go[k][sl]] = (int8_t)lst[s].first[sl];
+      }
+      unsigned xr = 0, xc = 0;
+      for (int q = 0; q < P->M.ngroups; ++q)
+        if (in_grp(P->M.grp[q], go[k])) xr |= 1u << q;
+      for (int q = 0; q < P->N.ngroups; ++q)
+        if (in_grp(P->N.grp[q], go[k])) xc |= 1u << q;
+      int64_t* rowc = nullptr;
+      int64_t* colc = nullptr;
+      FNO_HIP(hipMalloc(&rowc, std::max<size_t>((size_t)ns * og.count * 8, 8)));
+      P->bufs.push_back(rowc);
+      FNO_HIP(hipMalloc(&colc, std::max<size_t>((size_t)ns * og.count * 8, 8)));
+      P->bufs.push_back(colc);
+      launch_fold_table(tables, og, ns, src.data(), L, P->M, P->N, xr, xc, rowc, colc, stream);
+      t.count[k] = og.count;
+      t.nshuf[k] = ns;
+      t.rowc[k] = rowc;
+      t.colc[k] = colc;
+    }
+    int total = 1;
+    for (auto& l : per_group) total *= (int)l.size();
+    t.ncombo = total;
+    for (int c = 0; c < total; ++c) {
+      int rem = c, sign = 1;
+      for (size_t k = 0; k < go.size(); ++k) {
+        int nq = (int)per_group[k].size();
+        int pick = rem % nq;
+        rem /= nq;
+        t.combo[c][k] = (int8_t)pick;
+        sign *= per_group[k][pick].second;
+      }
+      t.csign[c] = (int8_t)sign;
+    }
+    P->f_tab_ok = true;
+  }
   P->prec = prec;
   plans_[key] = P;
   return P;
@@ -697,10 +854,16 @@ void Engine::execute(const Plan& p, double scale) {
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
     if (!p.a_direct) {
       void* a = workspace(0, (size_t)Msz * 8);
-      launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, nullptr, Prec::FP64, true, stream);
+      if (p.a_tab_ok)
+        launch_expand_tab(p.a_tab, p.A->d, a, nullptr, Prec::FP64, stream);
+      else
+        launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, nullptr, Prec::FP64, true, stream);
       X = a;
     }
-    launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, Prec::FP64, p.out->d, p.alpha * scale, stream);
+    if (p.f_tab_ok)
+      launch_fold_tab(p.f_tab, X, Prec::FP64, p.out->d, p.alpha * scale, p.odims.size, stream);
+    else
+      launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, Prec::FP64, p.out->d, p.alpha * scale, stream);
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
@@ -715,7 +878,10 @@ void Engine::execute(const Plan& p, double scale) {
     void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
     hipEvent_t e0 = profile ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, alo, prec, true, stream);
+    if (p.a_tab_ok)
+      launch_expand_tab(p.a_tab, p.A->d, a, alo, prec, stream);
+    else
+      launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, alo, prec, true, stream);
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
@@ -733,7 +899,10 @@ void Engine::execute(const Plan& p, double scale) {
       void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
       hipEvent_t e0 = profile ? event() : nullptr;
       if (e0) FNO_HIP(hipEventRecord(e0, stream));
-      launch_expand(tables, p.bd, p.K, p.N, p.B->d, b, blo, prec, true, stream);
+      if (p.b_tab_ok)
+        launch_expand_tab(p.b_tab, p.B->d, b, blo, prec, stream);
+      else
+        launch_expand(tables, p.bd, p.K, p.N, p.B->d, b, blo, prec, true, stream);
       if (e0) {
         hipEvent_t e1 = event();
         FNO_HIP(hipEventRecord(e1, stream));
@@ -761,6 +930,8 @@ void Engine::execute(const Plan& p, double scale) {
   g.b_nfast = p.b_nfast;
   g.tile = -1;
   auto timed_gemm = [&]() {
+    g.split = gemm_split_factor(g);
+    if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
     hipEvent_t e0 = profile ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
     launch_gemm(g, stream);
@@ -788,8 +959,12 @@ void Engine::execute(const Plan& p, double scale) {
     timed_gemm();
     hipEvent_t e0 = profile ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d,
-                p.alpha * scale, stream);
+    if (p.f_tab_ok)
+      launch_fold_tab(p.f_tab, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d, p.alpha * scale,
+                      p.odims.size, stream);
+    else
+      launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32,
+                  p.out->d, p.alpha * scale, stream);
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));

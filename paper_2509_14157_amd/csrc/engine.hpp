@@ -120,7 +120,7 @@ class Engine {
   std::string profile_report();  // JSON aggregate per kernel label; clears the records
 
   // workspace sizes (bytes) currently held
-  size_t workspace_bytes() const { return ws_bytes_[0] + ws_bytes_[1] + ws_bytes_[2] + ws_bytes_[3] + ws_bytes_[4]; }
+  size_t workspace_bytes() const { return ws_bytes_[0] + ws_bytes_[1] + ws_bytes_[2] + ws_bytes_[3] + ws_bytes_[4] + ws_bytes_[5]; }
   void* workspace(int slot, size_t bytes);
 
   // device buffers for tables
@@ -128,8 +128,8 @@ class Engine {
   struct Plan;
   std::map<std::string, std::unique_ptr<Tensor>> reg_;
   std::map<std::string, std::shared_ptr<Plan>> plans_;
-  void* ws_[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  size_t ws_bytes_[5] = {0, 0, 0, 0, 0};
+  void* ws_[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t ws_bytes_[6] = {0, 0, 0, 0, 0, 0};
   uint32_t* d_binom_ = nullptr;
   uint8_t* d_dec_[kMaxGroup + 1] = {};
   struct ProfRec {

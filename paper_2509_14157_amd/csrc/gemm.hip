@@ -11,6 +11,8 @@
 // with FP32 accumulation.
 #include <hip/hip_bf16.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace fno {
@@ -42,8 +44,16 @@ __device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
 __global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta) {
+                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                      int64_t kchunk, int64_t cz) {
   constexpr int BK = 16;
+  {  // split-K: this z-slice owns K range [z*kchunk, z*kchunk + kchunk)
+    const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+    A += AK ? k0 : k0 * lda;
+    B += BN_FAST ? k0 * ldb : k0;
+    C += (int64_t)blockIdx.z * cz;
+    K = (K - k0 < kchunk) ? K - k0 : kchunk;
+  }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int A_PER = BM * BK / 256;  // elements each thread stages
@@ -181,8 +191,18 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
                                                           const __bf16* __restrict__ Bh,
                                                           const __bf16* __restrict__ Bl, int64_t ldb,
                                                           float* __restrict__ C, int64_t ldc, float alpha,
-                                                          float beta) {
+                                                          float beta, int64_t kchunk, int64_t cz) {
   constexpr int BK = 32;
+  {
+    const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+    const int64_t ao = AK ? k0 : k0 * lda, bo = BN_FAST ? k0 * ldb : k0;
+    Ah += ao;
+    Al += ao;
+    Bh += bo;
+    Bl += bo;
+    C += (int64_t)blockIdx.z * cz;
+    K = (K - k0 < kchunk) ? K - k0 : kchunk;
+  }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int A_PER = BM * BK / 256;
@@ -350,43 +370,86 @@ static int default_tile(const GemmArgs& g) {
   return 0;
 }
 
+// reduction of split-K partials: C = alpha * sum_z P[z] + beta * C
+template <typename T>
+__global__ void __launch_bounds__(256) splitk_reduce_kernel(const T* __restrict__ P, int split, int64_t M, int64_t N,
+                                                            T* __restrict__ C, int64_t ldc, T alpha, T beta) {
+  const int64_t total = M * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    T s = 0;
+    for (int z = 0; z < split; ++z) s += P[(int64_t)z * total + i];
+    const int64_t r = i / N, c = i - r * N;
+    T v = alpha * s;
+    if (beta != (T)0) v += beta * C[r * ldc + c];
+    C[r * ldc + c] = v;
+  }
+}
+
 template <typename T, int BM, int BN>
 static void launch_k4(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  const int split = g.split > 1 ? g.split : 1;
+  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 15) / 16) * 16 : (g.K > 0 ? g.K : 1);
+  const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
-  T* C = (T*)g.C;
-  T al = (T)g.alpha, be = (T)g.beta;
+  T* C = split > 1 ? (T*)g.ws : (T*)g.C;
+  const int64_t ldc = split > 1 ? g.N : g.ldc;
+  const int64_t cz = split > 1 ? g.M * g.N : 0;
+  T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
   if (g.a_kfast && g.b_nfast)
-    gemm_k4_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+    gemm_k4_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
+                                                               kchunk, cz);
   else if (g.a_kfast)
-    gemm_k4_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+    gemm_k4_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
+                                                                kchunk, cz);
   else if (g.b_nfast)
-    gemm_k4_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al, be);
+    gemm_k4_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
+                                                                kchunk, cz);
   else
-    gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, g.ldc, al,
-                                                                  be);
+    gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
+                                                                 be, kchunk, cz);
+  if (split > 1) {
+    int64_t total = g.M * g.N;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    splitk_reduce_kernel<T><<<dim3((unsigned)blocks), 256, 0, s>>>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc,
+                                                                   (T)g.alpha, (T)g.beta);
+  }
 }
 
 template <int BM, int BN>
 static void launch_b3(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM));
+  const int split = g.split > 1 ? g.split : 1;
+  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 31) / 32) * 32 : (g.K > 0 ? g.K : 1);
+  const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
   const __bf16 *Ah = (const __bf16*)g.A, *Al = (const __bf16*)g.A_lo;
   const __bf16 *Bh = (const __bf16*)g.B, *Bl = (const __bf16*)g.B_lo;
-  float* C = (float*)g.C;
-  float al = (float)g.alpha, be = (float)g.beta;
+  float* C = split > 1 ? (float*)g.ws : (float*)g.C;
+  const int64_t ldc = split > 1 ? g.N : g.ldc;
+  const int64_t cz = split > 1 ? g.M * g.N : 0;
+  float al = split > 1 ? 1.0f : (float)g.alpha, be = split > 1 ? 0.0f : (float)g.beta;
   if (g.a_kfast && g.b_nfast)
     gemm_bf16x3_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                               g.ldc, al, be);
+                                                               ldc, al, be, kchunk, cz);
   else if (g.a_kfast)
     gemm_bf16x3_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                g.ldc, al, be);
+                                                                ldc, al, be, kchunk, cz);
   else if (g.b_nfast)
     gemm_bf16x3_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                g.ldc, al, be);
+                                                                ldc, al, be, kchunk, cz);
   else
     gemm_bf16x3_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                 g.ldc, al, be);
+                                                                 ldc, al, be, kchunk, cz);
+  if (split > 1) {
+    int64_t total = g.M * g.N;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    splitk_reduce_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>((const float*)g.ws, nz, g.M, g.N,
+                                                                       (float*)g.C, g.ldc, (float)g.alpha,
+                                                                       (float)g.beta);
+  }
 }
 
 template <int BM, int BN>
@@ -397,6 +460,21 @@ static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
     launch_k4<float, BM, BN>(g, s);
   else
     launch_b3<BM, BN>(g, s);
+}
+
+int gemm_split_factor(const GemmArgs& g) {
+  // enough workgroups to fill 256 CUs a few times over; chunks of >= 128 k
+  const int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
+  const int64_t tiles = ((g.M + kTiles[t].bm - 1) / kTiles[t].bm) * ((g.N + kTiles[t].bn - 1) / kTiles[t].bn);
+  if (tiles >= 512 || g.K < 512) return 1;
+  int64_t s = (1024 + tiles - 1) / tiles;
+  s = std::min<int64_t>(s, g.K / 128);
+  s = std::min<int64_t>(s, 256);
+  return s < 2 ? 1 : (int)s;
+}
+
+size_t gemm_split_bytes(const GemmArgs& g, int split) {
+  return (size_t)split * (size_t)(g.M * g.N) * (g.prec == Prec::FP64 ? 8 : 4);
 }
 
 std::string gemm_label(const GemmArgs& g) {

@@ -320,3 +320,287 @@ void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, i
 }
 
 }  // namespace fno
+
+namespace fno {
+
+// ---------------------------------------------------------------- plan tables
+__global__ void __launch_bounds__(256) dim_table_kernel(IndexTables tb, OperandDesc op, MatDim dims, unsigned mask,
+                                                        int64_t* __restrict__ off, int8_t* __restrict__ sign) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dims.size;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int val[kMaxLetters];
+    decode_dim(tb, dims, i, val);
+    int64_t o = op.base;
+    int sg = 1;
+    for (int q = 0; q < op.ngroups; ++q) {
+      if (!((mask >> q) & 1u)) continue;
+      const GroupDesc& G = op.grp[q];
+      if (G.g == 1) {
+        o += (int64_t)(val[G.letter[0]] + G.off) * G.stride;
+        continue;
+      }
+      int x[kMaxGroup];
+      for (int s = 0; s < G.g; ++s) x[s] = val[G.letter[s]];
+      for (int a = 1; a < G.g; ++a) {
+        int v = x[a], b = a - 1;
+        while (b >= 0 && x[b] > v) {
+          x[b + 1] = x[b];
+          --b;
+          sg = -sg;
+        }
+        x[b + 1] = v;
+      }
+      bool rep = false;
+      for (int a = 1; a < G.g; ++a) rep |= (x[a] == x[a - 1]);
+      if (rep) {
+        sg = 0;
+        continue;
+      }
+      o += colex_encode(tb, x, G.g) * G.stride;
+    }
+    off[i] = o;
+    sign[i] = (int8_t)sg;
+  }
+}
+
+void launch_dim_table(const IndexTables& tb, const OperandDesc& op, const MatDim& dims, unsigned group_mask,
+                      int64_t* off, int8_t* sign, hipStream_t s) {
+  if (dims.size == 0) return;
+  int64_t blocks = std::min<int64_t>((dims.size + 255) / 256, 16384);
+  dim_table_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(tb, op, dims, group_mask, off, sign);
+  FNO_HIP(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(256) sub_index_kernel(MatDim dims, unsigned dg_mask, int32_t* __restrict__ sub) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dims.size;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t idx = i, r = 0, mult = 1;
+    for (int q = dims.ngroups - 1; q >= 0; --q) {
+      int64_t t = idx % dims.grp[q].count;
+      idx /= dims.grp[q].count;
+      if ((dg_mask >> q) & 1u) {
+        r += t * mult;
+        mult *= dims.grp[q].count;
+      }
+    }
+    sub[i] = (int32_t)r;
+  }
+}
+
+void launch_sub_index(const IndexTables&, const MatDim& dims, unsigned dg_mask, int32_t* sub, hipStream_t s) {
+  if (dims.size == 0) return;
+  int64_t blocks = std::min<int64_t>((dims.size + 255) / 256, 16384);
+  sub_index_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(dims, dg_mask, sub);
+  FNO_HIP(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(256) mixed_table_kernel(IndexTables tb, OperandDesc op, int grp, MatDim pr,
+                                                          MatDim pc, int64_t* __restrict__ off,
+                                                          int8_t* __restrict__ sign) {
+  const int64_t total = pr.size * pc.size;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int val[kMaxLetters];
+    decode_dim(tb, pr, i / pc.size, val);
+    decode_dim(tb, pc, i % pc.size, val);
+    const GroupDesc& G = op.grp[grp];
+    int x[kMaxGroup];
+    int sg = 1;
+    for (int s = 0; s < G.g; ++s) x[s] = val[G.letter[s]];
+    for (int a = 1; a < G.g; ++a) {
+      int v = x[a], b = a - 1;
+      while (b >= 0 && x[b] > v) {
+        x[b + 1] = x[b];
+        --b;
+        sg = -sg;
+      }
+      x[b + 1] = v;
+    }
+    bool rep = false;
+    for (int a = 1; a < G.g; ++a) rep |= (x[a] == x[a - 1]);
+    off[i] = rep ? 0 : colex_encode(tb, x, G.g) * G.stride;
+    sign[i] = rep ? 0 : (int8_t)sg;
+  }
+}
+
+void launch_mixed_table(const IndexTables& tb, const OperandDesc& op, int grp, const MatDim& part_r,
+                        const MatDim& part_c, int64_t* off, int8_t* sign, hipStream_t s) {
+  int64_t total = part_r.size * part_c.size;
+  if (total == 0) return;
+  int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+  mixed_table_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(tb, op, grp, part_r, part_c, off, sign);
+  FNO_HIP(hipGetLastError());
+}
+
+struct ShufSrc {
+  int8_t src[kMaxCombos][kMaxLetters];
+};
+
+__global__ void __launch_bounds__(256) fold_table_kernel(IndexTables tb, DimGroup og, int nshuf, ShufSrc sh,
+                                                         int nletters, MatDim xr, MatDim xc, unsigned xr_mask,
+                                                         unsigned xc_mask, int64_t* __restrict__ rowc,
+                                                         int64_t* __restrict__ colc) {
+  const int64_t total = og.count * nshuf;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int s = (int)(i / og.count);
+    const int64_t u = i % og.count;
+    int val[kMaxLetters];
+    for (int l = 0; l < kMaxLetters; ++l) val[l] = 0;
+    int x[kMaxGroup];
+    colex_decode(tb, u, og.g, x);
+    for (int t = 0; t < og.g; ++t) val[og.letter[t]] = x[t];
+    int pv[kMaxLetters];
+    for (int l = 0; l < nletters; ++l) pv[l] = val[sh.src[s][l]];
+    // strides of the X row / column DimGroups
+    int64_t r = 0, mult = 1;
+    for (int q = xr.ngroups - 1; q >= 0; --q) {
+      const DimGroup& G = xr.grp[q];
+      if ((xr_mask >> q) & 1u) {
+        int y[kMaxGroup];
+        for (int t = 0; t < G.g; ++t) y[t] = pv[G.letter[t]];
+        r += colex_encode(tb, y, G.g) * mult;
+      }
+      mult *= G.count;
+    }
+    int64_t c = 0;
+    mult = 1;
+    for (int q = xc.ngroups - 1; q >= 0; --q) {
+      const DimGroup& G = xc.grp[q];
+      if ((xc_mask >> q) & 1u) {
+        int y[kMaxGroup];
+        for (int t = 0; t < G.g; ++t) y[t] = pv[G.letter[t]];
+        c += colex_encode(tb, y, G.g) * mult;
+      }
+      mult *= G.count;
+    }
+    rowc[i] = r;
+    colc[i] = c;
+  }
+}
+
+void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, const int8_t* shuf_src, int nletters,
+                       const MatDim& xrows, const MatDim& xcols, unsigned xr_mask, unsigned xc_mask, int64_t* rowc,
+                       int64_t* colc, hipStream_t s) {
+  ShufSrc sh{};
+  for (int k = 0; k < nshuf; ++k)
+    for (int l = 0; l < kMaxLetters; ++l) sh.src[k][l] = shuf_src[k * kMaxLetters + l];
+  int64_t total = og.count * nshuf;
+  if (total == 0) return;
+  int64_t blocks = std::min<int64_t>((total + 255) / 256, 16384);
+  fold_table_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(tb, og, nshuf, sh, nletters, xrows, xcols, xr_mask,
+                                                           xc_mask, rowc, colc);
+  FNO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------- hot paths
+// Each thread owns one column c (its table entries stay in registers) and
+// walks a strided set of rows; the row entries are uniform per iteration.
+template <typename Out>
+__global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const double* __restrict__ src,
+                                                         Out* __restrict__ dst) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t.cols) return;
+  const int64_t co = t.col_off[c];
+  const int cs = t.col_sign[c];
+  int32_t csub0 = 0, csub1 = 0;
+  if (t.nmixed > 0) csub0 = t.col_sub[0][c];
+  if (t.nmixed > 1) csub1 = t.col_sub[1][c];
+  for (int64_t r = blockIdx.y; r < t.rows; r += gridDim.y) {
+    int64_t o = t.row_off[r] + co;
+    int s = t.row_sign[r] * cs;
+    if (t.nmixed > 0) {
+      const int64_t k = (int64_t)t.row_sub[0][r] * t.ncsub[0] + csub0;
+      o += t.tab_off[0][k];
+      s *= t.tab_sign[0][k];
+    }
+    if (t.nmixed > 1) {
+      const int64_t k = (int64_t)t.row_sub[1][r] * t.ncsub[1] + csub1;
+      o += t.tab_off[1][k];
+      s *= t.tab_sign[1][k];
+    }
+    const double v = s ? s * src[o] : 0.0;
+    dst[r * t.cols + c] = (Out)v;
+  }
+}
+
+__global__ void __launch_bounds__(256) expand_tab_bf16_kernel(ExpandTab t, const double* __restrict__ src,
+                                                              __hip_bfloat16* __restrict__ hi,
+                                                              __hip_bfloat16* __restrict__ lo) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t.cols) return;
+  const int64_t co = t.col_off[c];
+  const int cs = t.col_sign[c];
+  int32_t csub0 = 0, csub1 = 0;
+  if (t.nmixed > 0) csub0 = t.col_sub[0][c];
+  if (t.nmixed > 1) csub1 = t.col_sub[1][c];
+  for (int64_t r = blockIdx.y; r < t.rows; r += gridDim.y) {
+    int64_t o = t.row_off[r] + co;
+    int s = t.row_sign[r] * cs;
+    if (t.nmixed > 0) {
+      const int64_t k = (int64_t)t.row_sub[0][r] * t.ncsub[0] + csub0;
+      o += t.tab_off[0][k];
+      s *= t.tab_sign[0][k];
+    }
+    if (t.nmixed > 1) {
+      const int64_t k = (int64_t)t.row_sub[1][r] * t.ncsub[1] + csub1;
+      o += t.tab_off[1][k];
+      s *= t.tab_sign[1][k];
+    }
+    const float x = s ? (float)(s * src[o]) : 0.0f;
+    const __hip_bfloat16 h = __float2bfloat16(x);
+    hi[r * t.cols + c] = h;
+    lo[r * t.cols + c] = __float2bfloat16(x - __bfloat162float(h));
+  }
+}
+
+void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
+  if (t.rows == 0 || t.cols == 0) return;
+  const unsigned gx = (unsigned)((t.cols + 255) / 256);
+  // enough blocks in y to have ~8K blocks in flight
+  int64_t gy = std::max<int64_t>(1, std::min<int64_t>(t.rows, (8192 + gx - 1) / gx));
+  gy = std::min<int64_t>(gy, 65535);
+  dim3 grid(gx, (unsigned)gy);
+  if (prec == Prec::FP64)
+    expand_tab_kernel<double><<<grid, 256, 0, s>>>(t, src, (double*)dst);
+  else if (prec == Prec::FP32)
+    expand_tab_kernel<float><<<grid, 256, 0, s>>>(t, src, (float*)dst);
+  else
+    expand_tab_bf16_kernel<<<grid, 256, 0, s>>>(t, src, (__hip_bfloat16*)dst, (__hip_bfloat16*)dst_lo);
+  FNO_HIP(hipGetLastError());
+}
+
+template <typename XT>
+__global__ void __launch_bounds__(256) fold_tab_kernel(FoldTab t, const XT* __restrict__ X, double* __restrict__ out,
+                                                       double alpha, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t u[kMaxOutGroups];
+    int64_t idx = e;
+    for (int k = t.ngroups - 1; k >= 0; --k) {
+      u[k] = idx % t.count[k];
+      idx /= t.count[k];
+    }
+    double acc = 0.0;
+    for (int c = 0; c < t.ncombo; ++c) {
+      int64_t r = 0, col = 0;
+      for (int k = 0; k < t.ngroups; ++k) {
+        const int64_t j = (int64_t)t.combo[c][k] * t.count[k] + u[k];
+        r += t.rowc[k][j];
+        col += t.colc[k][j];
+      }
+      acc += t.csign[c] * (double)X[r * t.xcols + col];
+    }
+    out[e] += alpha * acc;
+  }
+}
+
+void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, double alpha, int64_t total,
+                     hipStream_t s) {
+  if (total == 0) return;
+  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  if (xprec == Prec::FP64)
+    fold_tab_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(t, (const double*)X, out, alpha, total);
+  else
+    fold_tab_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(t, (const float*)X, out, alpha, total);
+  FNO_HIP(hipGetLastError());
+}
+
+}  // namespace fno

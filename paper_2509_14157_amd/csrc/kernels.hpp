@@ -13,6 +13,26 @@ void launch_fold(const IndexTables& tb, const OperandDesc& outd, const MatDim& o
                  const MatDim& xcols, const FoldCombos& fc, const void* X, Prec xprec, double* out, double alpha,
                  hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+
+// table construction (run once per plan)
+// off[i], sign[i] for i < dims.size: contribution of the operand groups set in
+// group_mask, for letter values decoded from index i of `dims`.
+void launch_dim_table(const IndexTables& tb, const OperandDesc& op, const MatDim& dims, unsigned group_mask,
+                      int64_t* off, int8_t* sign, hipStream_t s);
+// sub[i] = mixed-radix index of the DimGroups of `dims` selected by dg_mask.
+void launch_sub_index(const IndexTables& tb, const MatDim& dims, unsigned dg_mask, int32_t* sub, hipStream_t s);
+// tab[rs * part_c.size + cs]: contribution of operand group `grp` for the
+// letters of row part rs and column part cs.
+void launch_mixed_table(const IndexTables& tb, const OperandDesc& op, int grp, const MatDim& part_r,
+                        const MatDim& part_c, int64_t* off, int8_t* sign, hipStream_t s);
+// fold tables of one output group: for each shuffle (src letters) and tuple u.
+void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, const int8_t* shuf_src, int nletters,
+                       const MatDim& xrows, const MatDim& xcols, unsigned xr_mask, unsigned xc_mask,
+                       int64_t* rowc, int64_t* colc, hipStream_t s);
+
+void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s);
+void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, double alpha, int64_t total,
+                     hipStream_t s);
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 void launch_denominators(const IndexTables& tb, const MatDim& dims, int nh, const double* eo, const double* ev,
                          double* out, hipStream_t s);
@@ -44,7 +64,16 @@ struct GemmArgs {
   int64_t ldc;
   double alpha, beta;
   int tile;   // tile configuration index (autotuner), -1 = default
+  // split-K: the K range is cut into `split` chunks whose partial products go
+  // to `ws` (split * M * N elements of the accumulator type) and are summed
+  // in a fixed order by a second kernel (deterministic)
+  int split = 1;
+  void* ws = nullptr;
 };
+// Number of K chunks worth using for this shape (1 = no split) and the
+// workspace bytes it needs.
+int gemm_split_factor(const GemmArgs& g);
+size_t gemm_split_bytes(const GemmArgs& g, int split);
 void launch_gemm(const GemmArgs& g, hipStream_t s);
 // Name of the kernel instantiation launch_gemm would use (as tools demangle it).
 std::string gemm_label(const GemmArgs& g);

@@ -59,6 +59,40 @@ struct FoldCombos {
   int8_t sign[kMaxCombos];
 };
 
+// Table-driven operand expansion: offset(r, c) = row_off[r] + col_off[c]
+// + sum_m tab_m[row_sub_m[r] * ncsub_m + col_sub_m[c]], and the product of
+// the matching signs (0 marks a repeated index of an antisymmetric group).
+constexpr int kMaxMixed = 2;
+struct ExpandTab {
+  int64_t rows, cols;
+  const int64_t* row_off;
+  const int8_t* row_sign;
+  const int64_t* col_off;
+  const int8_t* col_sign;
+  int nmixed;
+  int64_t ncsub[kMaxMixed];
+  const int32_t* row_sub[kMaxMixed];
+  const int32_t* col_sub[kMaxMixed];
+  const int64_t* tab_off[kMaxMixed];
+  const int8_t* tab_sign[kMaxMixed];
+};
+
+// Table-driven fold over a whole packed output: element e = mixed-radix
+// tuple indices u_k of the output groups; each coset representative c picks
+// one shuffle s_k per group; X row/col = sum_k rowc_k[s_k][u_k] / colc_k.
+constexpr int kMaxOutGroups = 4;
+struct FoldTab {
+  int ngroups;
+  int64_t count[kMaxOutGroups];     // tuples per output group
+  int nshuf[kMaxOutGroups];
+  const int64_t* rowc[kMaxOutGroups];   // [s * count + u]
+  const int64_t* colc[kMaxOutGroups];
+  int ncombo;
+  int8_t combo[kMaxCombos][kMaxOutGroups];  // shuffle index per group
+  int8_t csign[kMaxCombos];                 // sign of the coset representative
+  int64_t xcols;
+};
+
 #ifdef __HIPCC__
 __device__ __forceinline__ int64_t colex_encode(const IndexTables& tb, const int* x, int g) {
   int64_t r = 0;
