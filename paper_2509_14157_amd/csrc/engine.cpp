@@ -112,12 +112,11 @@ std::string Engine::profile_report() {
     a.ms += ms;
     a.flops += r.flops;
     a.bytes += r.bytes;
-    if (r.flops > 0) {
-      Agg& t = per_term[r.spec + " @ " + r.label];
-      t.n++;
-      t.ms += ms;
-      t.flops += r.flops;
-    }
+    Agg& t = per_term[r.spec + " @ " + r.label];
+    t.n++;
+    t.ms += ms;
+    t.flops += r.flops;
+    t.bytes += r.bytes;
   }
   auto esc = [](const std::string& s) {
     std::string o;
@@ -140,8 +139,8 @@ std::string Engine::profile_report() {
   first = true;
   for (auto& kv : per_term) {
     char buf[256];
-    snprintf(buf, sizeof(buf), "\"launches\": %lld, \"total_ms\": %.6f, \"flops\": %.6e}",
-             (long long)kv.second.n, kv.second.ms, kv.second.flops);
+    snprintf(buf, sizeof(buf), "\"launches\": %lld, \"total_ms\": %.6f, \"flops\": %.6e, \"bytes\": %.6e}",
+             (long long)kv.second.n, kv.second.ms, kv.second.flops, kv.second.bytes);
     js += std::string(first ? "" : ", ") + "{\"term\": \"" + esc(kv.first) + "\", " + buf;
     first = false;
   }
@@ -867,7 +866,8 @@ void Engine::execute(const Plan& p, double scale) {
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
-      prof_mark("fno::copy_fold", p.spec, 0, 16.0 * (double)p.odims.size, e0, e1);
+      prof_mark(p.f_tab_ok ? "fno::copy (expand_tab + fold_tab)" : "fno::copy (expand + fold)", p.spec, 0,
+                16.0 * (double)p.odims.size, e0, e1);
     }
     return;
   }
@@ -885,7 +885,7 @@ void Engine::execute(const Plan& p, double scale) {
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
-      prof_mark(prec == Prec::FP64 ? "fno::expand_kernel<double>" : "fno::expand_kernel<lowp>", p.spec, 0,
+      prof_mark(p.a_tab_ok ? "fno::expand_tab" : "fno::expand_kernel", p.spec, 0,
                 (double)(Msz * Ksz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
     }
     A = a;
@@ -906,7 +906,7 @@ void Engine::execute(const Plan& p, double scale) {
       if (e0) {
         hipEvent_t e1 = event();
         FNO_HIP(hipEventRecord(e1, stream));
-        prof_mark(prec == Prec::FP64 ? "fno::expand_kernel<double>" : "fno::expand_kernel<lowp>", p.spec, 0,
+        prof_mark(p.b_tab_ok ? "fno::expand_tab" : "fno::expand_kernel", p.spec, 0,
                   (double)(Ksz * Nsz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
       }
       B = b;
@@ -968,7 +968,7 @@ void Engine::execute(const Plan& p, double scale) {
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
-      prof_mark(prec == Prec::FP64 ? "fno::fold_kernel<double>" : "fno::fold_kernel<float>", p.spec, 0,
+      prof_mark(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel", p.spec, 0,
                 (double)p.odims.size * (16.0 + (double)p.fc.ncombo * (double)xsz), e0, e1);
     }
   }

@@ -552,8 +552,49 @@ __global__ void __launch_bounds__(256) expand_tab_bf16_kernel(ExpandTab t, const
   }
 }
 
+// Narrow matrices (few columns): one thread per element over the flat index.
+template <int MODE>  // 0 = FP64, 1 = FP32, 2 = split-BF16
+__global__ void __launch_bounds__(256) expand_tab_flat_kernel(ExpandTab t, const double* __restrict__ src, void* dst,
+                                                              void* dst_lo) {
+  const int64_t total = t.rows * t.cols;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t.cols == 1 ? i : i / t.cols;
+    const int64_t c = i - r * t.cols;
+    int64_t o = t.row_off[r] + t.col_off[c];
+    int s = t.row_sign[r] * t.col_sign[c];
+    for (int m = 0; m < t.nmixed; ++m) {
+      const int64_t k = (int64_t)t.row_sub[m][r] * t.ncsub[m] + t.col_sub[m][c];
+      o += t.tab_off[m][k];
+      s *= t.tab_sign[m][k];
+    }
+    const double v = s ? s * src[o] : 0.0;
+    if (MODE == 0) {
+      ((double*)dst)[i] = v;
+    } else if (MODE == 1) {
+      ((float*)dst)[i] = (float)v;
+    } else {
+      const float x = (float)v;
+      const __hip_bfloat16 h = __float2bfloat16(x);
+      ((__hip_bfloat16*)dst)[i] = h;
+      ((__hip_bfloat16*)dst_lo)[i] = __float2bfloat16(x - __bfloat162float(h));
+    }
+  }
+}
+
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
   if (t.rows == 0 || t.cols == 0) return;
+  if (t.cols < 128) {
+    const int64_t total = t.rows * t.cols;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    if (prec == Prec::FP64)
+      expand_tab_flat_kernel<0><<<dim3((unsigned)blocks), 256, 0, s>>>(t, src, dst, dst_lo);
+    else if (prec == Prec::FP32)
+      expand_tab_flat_kernel<1><<<dim3((unsigned)blocks), 256, 0, s>>>(t, src, dst, dst_lo);
+    else
+      expand_tab_flat_kernel<2><<<dim3((unsigned)blocks), 256, 0, s>>>(t, src, dst, dst_lo);
+    FNO_HIP(hipGetLastError());
+    return;
+  }
   const unsigned gx = (unsigned)((t.cols + 255) / 256);
   // enough blocks in y to have ~8K blocks in flight
   int64_t gy = std::max<int64_t>(1, std::min<int64_t>(t.rows, (8192 + gx - 1) / gx));
