@@ -207,6 +207,20 @@ def eom_sigma(fock, eri, nocc, amps, kind, rblocks, mu_blocks=None):
     return out
 
 
+def eom_sigma_element(fock, eri, nocc, amps, kind, rblocks, mu, index) -> float:
+    """One element of sigma_mu (unmerged classes, externals fixed; amplitudes may be lazy arrays)."""
+    _, blocks = EOM_SPACES[kind]
+    T = _tensors(fock, eri, nocc, amps)
+    val = 0.0
+    for nu in blocks:
+        if nu not in rblocks:
+            continue
+        T.amps[("r",) + nu] = rblocks[nu]
+        val += float(wick.evaluate(wick.eom_terms(mu, nu), T, None, fixed=tuple(index)))
+        del T.amps[("r",) + nu]
+    return val
+
+
 def eom_diagonal(fock, nocc, kind):
     """Zeroth-order diagonal sum f_particles - sum f_holes for each R block."""
     _, blocks = EOM_SPACES[kind]
@@ -263,7 +277,8 @@ def davidson(fock, eri, nocc, amps, kind, nroots, max_iter=60, max_sub=None, e_t
     """Block Davidson for the lowest right EOM eigenpairs (real parts).
 
     Guesses: unit vectors on the lowest zeroth-order diagonal entries of the
-    principal (first) block.  Preconditioner (theta - D)^-1 with D the
+    principal (first) block, continued into the other blocks (lowest diagonal
+    first) when the principal block has fewer entries than roots.  Preconditioner (theta - D)^-1 with D the
     zeroth-order diagonal over all blocks.  Orthonormalisation: classical
     Gram-Schmidt applied twice.
     """
@@ -274,7 +289,9 @@ def davidson(fock, eri, nocc, amps, kind, nroots, max_iter=60, max_sub=None, e_t
     max_sub = max_sub or 8 * nroots
     nguess = nguess or nroots
     first = sp.sizes[blocks[0]]
-    order = np.argsort(diag[:first], kind="stable")[:nguess]
+    order = list(np.argsort(diag[:first], kind="stable"))
+    order += [first + int(j) for j in np.argsort(diag[first:], kind="stable")]
+    order = order[:nguess]
     V = np.zeros((sp.dim, 0))
     for j in order:
         e = np.zeros(sp.dim)

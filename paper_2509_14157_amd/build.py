@@ -37,6 +37,9 @@ def _compile(src: str) -> str:
 
 
 def build(verbose: bool = False) -> str:
+    # EOM sigma tables are generated from the ground-state tables
+    from .codegen import eom_jvp
+    eom_jvp.main(("IP", "EA"))
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))

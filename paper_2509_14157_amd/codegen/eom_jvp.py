@@ -1,0 +1,371 @@
+"""Generate EOM-CCSDT sigma-vector term tables from the ground-state CCSDT tables.
+
+Principle.  Add non-interacting continuum spin-orbitals to the orbital
+space: one virtual x for IP, one occupied x for EA, two virtual x<y for DIP,
+two occupied for DEA.  Every amplitude that carries all of the continuum
+labels exactly once is an EOM amplitude (IP: r_i = t_i^x, r_ij^a = t_ij^ax,
+r_ijk^ab = t_ijk^abx; EA: r^a = t_x^a, ...).  Because the continuum orbitals
+have no integrals, the CC residual restricted to the blocks that carry every
+continuum label once is linear in those amplitudes, and equals
+<mu|[H-bar, R]|0>: the EOM sigma vector (eqs 1-4 with eq 5).  Differentiating
+the ground-state residual terms in that direction gives the sigma terms.
+
+Mechanics.  For every tensor of the ground-state tables, its "R-blocks" are
+the blocks in which the continuum labels sit in antisymmetric groups of the
+right index space; within a group they are moved to the end (x before y),
+which defines the layout of the block tensor (the group loses those slots).
+A bilinear term Out += a A B contributes to an R-block of Out through the
+R-block of A or of B: the continuum labels land on output letters of that
+factor.  Within a sub-block (a factor group intersected with an output
+group) only the trailing letters can carry them (the others are fixed by
+antisymmetry), and the sign is that of moving those letters to the end of
+their group, in the output and in the factor.  Summation letters never carry
+a continuum label (both factors would have to be first order).
+
+The T1 dressing contributes when R has a singles part (IP, EA): X and Y gain
+a continuum row/column, which makes the dressed integrals and Fock matrix
+carry first-order blocks:
+  IP: dGd[p,x,r,s] = -sum_m r_m Gd[p,m,r,s],  dFd[x,q] = -sum_m r_m Fd[m,q];
+  EA: dGd[p,q,r,x] = +sum_a r^a Gd[p,q,r,a],  dFd[p,x] = +sum_a r^a Fd[p,a].
+
+Usage: python -m paper_2509_14157_amd.codegen.eom_jvp  (writes csrc/eom_*_terms.inc)
+"""
+from __future__ import annotations
+
+import itertools
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(os.path.dirname(HERE), "csrc")
+
+TERM = re.compile(r"^\s*(\w+)\[(\w*)\]\s*([+-])=\s*(?:([0-9./-]+)\s*\*\s*)?(\w+)\[(\w*)\]"
+                  r"(?:\s*\*\s*(\w+)\[(\w*)\])?\s*$")
+
+VARIANTS = {
+    # name: (continuum labels, their index space, R blocks as (ground-state amplitude, (nh, np)))
+    "IP": (("x",), "v", (("T1", (1, 0)), ("T2", (2, 1)), ("T3", (3, 2)))),
+    "EA": (("x",), "o", (("T1", (0, 1)), ("T2", (1, 2)), ("T3", (2, 3)))),
+    "DIP": (("x", "y"), "v", (("T2", (2, 0)), ("T3", (3, 1)))),
+    "DEA": (("x", "y"), "o", (("T2", (0, 2)), ("T3", (1, 3)))),
+}
+
+
+def read_tables(path):
+    src = open(path).read()
+    tabs = {}
+    for m in re.finditer(r"static const char\* const (\w+)\[\] = \{(.*?)\};", src, re.S):
+        body = re.sub(r"//[^\n]*", "", m.group(2))
+        tabs[m.group(1)] = re.findall(r'"([^"]*)"', body)
+    return tabs
+
+
+class Tensor:
+    """Slot spaces plus an antisymmetry partition (list of slot lists, slot order)."""
+
+    def __init__(self, name, spaces, groups, packed=True):
+        self.name = name
+        self.spaces = list(spaces)        # per slot: 'o' / 'v' / 'n'
+        self.groups = [list(g) for g in groups]
+        self.packed = packed              # storage packs the groups
+
+    def spec(self):
+        # storage spec of a packed tensor (groups are contiguous slot runs)
+        return ",".join("".join(self.spaces[s] for s in g) for g in self.groups)
+
+
+def parse_decl(d):
+    name, spec = [x.strip() for x in d.split(":")]
+    spaces, groups, s = [], [], 0
+    for tok in [t for t in spec.split(",") if t]:
+        groups.append(list(range(s, s + len(tok))))
+        spaces += list(tok)
+        s += len(tok)
+    return Tensor(name, spaces, groups)
+
+
+def parse_view(v):
+    name, rest = [x.strip() for x in v.split("=")]
+    par, sp = re.match(r"(\w+)\((.*)\)", rest).groups()
+    spaces = [c.strip() for c in sp.split(",")]
+    return name, par, spaces
+
+
+def dense_sym_groups(spaces, pairs):
+    """Antisymmetry of a view of a dense pair-antisymmetric tensor: a pair survives if both slots share a space."""
+    groups = []
+    for a, b in pairs:
+        if spaces[a] == spaces[b]:
+            groups.append([a, b])
+        else:
+            groups += [[a], [b]]
+    return groups
+
+
+def perm_parity(seq):
+    inv = 0
+    for i in range(len(seq)):
+        for j in range(i + 1, len(seq)):
+            if seq[i] > seq[j]:
+                inv += 1
+    return -1 if inv & 1 else 1
+
+
+def move_to_end_sign(group_letters, moved):
+    """Sign of reordering a group's letters so that `moved` (in that order) come last."""
+    rest = [l for l in group_letters if l not in moved]
+    target = rest + list(moved)
+    pos = {l: i for i, l in enumerate(group_letters)}
+    return perm_parity([pos[l] for l in target])
+
+
+class Generator:
+    def __init__(self, variant, cc_tables):
+        self.variant = variant
+        self.labels, self.space, self.rblocks = VARIANTS[variant]
+        self.t = cc_tables
+        self.tensors = {}
+        self.out_terms = []      # generated term strings
+        self.decls = {}          # R-block tensor name -> spec
+        self.views = []          # auxiliary views (strings)
+        self.nonzero = set()     # R-block tensors known to be nonzero
+        self.zero_list = []      # R-block tensors to clear before a sigma evaluation
+        for d in cc_tables["kCCDecl"]:
+            t = parse_decl(d)
+            self.tensors[t.name] = t
+        # dressed / bare integrals
+        self.tensors["Gd"] = Tensor("Gd", "nnnn", [[0, 1], [2, 3]], packed=False)
+        self.tensors["Fd"] = Tensor("Fd", "nn", [[0], [1]], packed=False)
+        self.view_parent = {}
+        for v in cc_tables["kCCViews"]:
+            name, par, spaces = parse_view(v)
+            if par in ("G", "F0"):
+                continue  # undressed blocks only enter the energy
+            groups = dense_sym_groups(spaces, [(0, 1), (2, 3)]) if par == "Gd" else [[0], [1]]
+            self.tensors[name] = Tensor(name, spaces, groups, packed=False)
+            self.view_parent[name] = (par, spaces)
+
+    # ---------------------------------------------------------- R-blocks
+    def assignments(self, t: Tensor):
+        """All placements of the continuum labels into t's groups of the right space."""
+        cand = [gi for gi, g in enumerate(t.groups) if t.spaces[g[0]] == self.space]
+        out = []
+        if len(self.labels) == 1:
+            for g in cand:
+                out.append((g,))
+        else:
+            for gx in cand:
+                for gy in cand:
+                    if gx == gy and len(t.groups[gx]) < 2:
+                        continue
+                    out.append((gx, gy))
+        return out
+
+    def block_name(self, t: Tensor, asg):
+        return f"{t.name}_{self.variant}{''.join(str(g) for g in asg)}"
+
+    def block_tensor(self, t: Tensor, asg):
+        """Declaration of the R-block: each group loses the slots its labels occupy."""
+        spaces, groups, s = [], [], 0
+        count = {g: asg.count(g) for g in asg}
+        for gi, g in enumerate(t.groups):
+            keep = len(g) - count.get(gi, 0)
+            if keep == 0:
+                continue
+            groups.append(list(range(s, s + keep)))
+            spaces += [t.spaces[g[0]]] * keep
+            s += keep
+        name = self.block_name(t, asg)
+        # blocks are stored packed by their antisymmetric groups (for blocks of
+        # dense integral views this keeps the pair antisymmetry explicit)
+        self.decls[name] = ",".join("".join(spaces[x] for x in g) for g in groups)
+        return name
+
+    # ---------------------------------------------------------- dressing blocks
+    def view_blocks(self):
+        """First-order blocks of the dressed-integral views (IP / EA only).
+
+        The label sits at the last slot k of its group; the block equals
+        -sum_m r_m V[.., m at k, ..] (IP) or +sum_a r^a V[.., a at k, ..] (EA),
+        i.e. the view with slot k's space replaced by the summed one.
+        """
+        if len(self.labels) != 1:
+            return
+        rin = self.input_name("T1")
+        summed = "o" if self.space == "v" else "v"
+        coef = -1 if self.space == "v" else 1
+        for name, (par, spaces) in self.view_parent.items():
+            t = self.tensors[name]
+            allowed = ({"Gd": (0, 1), "Fd": (0,)} if self.space == "v" else {"Gd": (2, 3), "Fd": (1,)})[par]
+            for asg in self.assignments(t):
+                k = t.groups[asg[0]][-1]
+                if k not in allowed:
+                    continue
+                bname = self.block_tensor(t, asg)
+                letters = "pqrs"[:len(spaces)]
+                src_spaces = list(spaces)
+                src_spaces[k] = summed
+                src = f"{par}S_{''.join(src_spaces)}"
+                vdef = f"{src} = {par}({','.join(src_spaces)})"
+                if vdef not in self.views:
+                    self.views.append(vdef)
+                out_letters = "".join(letters[j] for j in range(len(spaces)) if j != k)
+                src_letters = letters[:k] + "z" + letters[k + 1:]
+                op = "+=" if coef > 0 else "-="
+                self.out_terms.append(f"{bname}[{out_letters}] {op} 1 * {rin}[z] * {src}[{src_letters}]")
+                self.nonzero.add(bname)
+                self.zero_list.append(bname)
+
+    def input_name(self, amp):
+        for a, (nh, np_) in self.rblocks:
+            if a == amp:
+                t = self.tensors[amp]
+                asg = self.assignments(t)
+                assert len(asg) == 1, (amp, asg)
+                return self.block_name(t, asg[0])
+        return None
+
+    # ---------------------------------------------------------- term JVP
+    def jvp(self, spec):
+        m = TERM.match(spec)
+        assert m, spec
+        out, lo, sg, coef, A, la, B, lb = m.groups()
+        c = float(eval(coef)) if coef else 1.0
+        if sg == "-":
+            c = -c
+        To = self.tensors[out]
+        factors = [(A, la)] + ([(B, lb)] if B else [])
+
+        def letter_groups(t, letters):
+            return [[letters[s] for s in g] for g in t.groups]
+
+        go = letter_groups(To, lo)
+        ospace = [To.spaces[g[0]] for g in To.groups]
+        for fi, (F, lf) in enumerate(factors):
+            TF = self.tensors[F]
+            gf = letter_groups(TF, lf)
+            fspace = [TF.spaces[g[0]] for g in TF.groups]
+            other = factors[1 - fi] if len(factors) == 2 else None
+            # (factor group, output group) sub-blocks that can carry a label
+            subs = [(h, g) for h in range(len(gf)) for g in range(len(go))
+                    if fspace[h] == self.space and ospace[g] == self.space
+                    and any(l in go[g] for l in gf[h])]
+            for choice in itertools.product(subs, repeat=len(self.labels)):
+                carried = []
+                ok = True
+                for i, (h, g) in enumerate(choice):
+                    sub = [l for l in gf[h] if l in go[g]]
+                    same = [j for j, cj in enumerate(choice) if cj == (h, g)]
+                    if len(sub) < len(same):
+                        ok = False
+                        break
+                    # labels sharing a sub-block take its trailing letters in label order
+                    carried.append(sub[len(sub) - len(same) + same.index(i)])
+                if not ok or len(set(carried)) != len(carried):
+                    continue
+                fasg = tuple(h for h, _ in choice)
+                oasg = tuple(g for _, g in choice)
+                fname = self.block_name(TF, fasg)
+                if fname not in self.nonzero:
+                    continue
+                sgn = 1
+                for g in set(oasg):
+                    sgn *= move_to_end_sign(go[g], [carried[j] for j in range(len(carried)) if oasg[j] == g])
+                for h in set(fasg):
+                    sgn *= move_to_end_sign(gf[h], [carried[j] for j in range(len(carried)) if fasg[j] == h])
+                oname = self.block_tensor(To, oasg)
+                new_lo = "".join(l for l in lo if l not in carried)
+                new_lf = "".join(l for l in lf if l not in carried)
+                cn = c * sgn
+                op = "+=" if cn > 0 else "-="
+                mag = "%g" % abs(cn)
+                if other is None:
+                    term = f"{oname}[{new_lo}] {op} {mag} * {fname}[{new_lf}]"
+                elif fi == 0:
+                    term = f"{oname}[{new_lo}] {op} {mag} * {fname}[{new_lf}] * {other[0]}[{other[1]}]"
+                else:
+                    term = f"{oname}[{new_lo}] {op} {mag} * {other[0]}[{other[1]}] * {fname}[{new_lf}]"
+                self.out_terms.append(term)
+                if oname not in self.nonzero:
+                    self.nonzero.add(oname)
+                    self.zero_list.append(oname)
+
+    @staticmethod
+    def ok_order(oasg):
+        return True
+
+    def generate(self):
+        self.view_blocks()
+        for amp, _ in self.rblocks:
+            self.nonzero.add(self.input_name(amp))
+            t = self.tensors[amp]
+            self.block_tensor(t, self.assignments(t)[0])
+        for blk in ("kCCInter2", "kCCR1", "kCCR2", "kCCInter3", "kCCR3"):
+            for spec in self.t[blk]:
+                self.jvp(spec)
+        outputs = []
+        for amp, _ in self.rblocks:
+            res = "R" + amp[1:]
+            t = self.tensors[res]
+            name = self.block_name(t, self.assignments(t)[0])
+            outputs.append(name)
+        return outputs
+
+
+def emit(variant, gen: Generator, outputs):
+    v = variant
+    lines = [f"// Generated by paper_2509_14157_amd/codegen/eom_jvp.py from ccsdt_terms.inc: do not edit.",
+             f"// {v}-EOM-CCSDT sigma = derivative of the CCSDT residual along R placed in the",
+             f"// continuum blocks (see the generator for the derivation).", ""]
+    inputs = [gen.input_name(a) for a, _ in gen.rblocks]
+    blocks = [nhp for _, nhp in gen.rblocks]
+    lines.append(f"static const char* const kEom{v}Decl[] = {{")
+    for name in sorted(gen.decls):
+        lines.append(f'    "{name} : {gen.decls[name]}",')
+    lines.append("};")
+    lines.append(f"static const char* const kEom{v}Views[] = {{")
+    for vw in gen.views:
+        lines.append(f'    "{vw}",')
+    if not gen.views:
+        lines.append('    "",')
+    lines.append("};")
+    lines.append(f"// R-vector blocks in order (holes, particles) and their tensors")
+    lines.append(f"static const int kEom{v}Blocks[][2] = {{" + ", ".join(f"{{{a}, {b}}}" for a, b in blocks) + "};")
+    # EOM amplitude = sign * continuum-block amplitude: moving the continuum
+    # operator to the end of the excitation string passes the particle
+    # creators (virtual label) or the hole annihilators (occupied label)
+    signs = []
+    for nh, np_ in blocks:
+        n_pass = np_ if gen.space == "v" else nh
+        if len(gen.labels) == 2:
+            # two labels: each passes the same operators
+            n_pass *= 2
+        signs.append(-1 if n_pass % 2 else 1)
+    lines.append(f"static const int kEom{v}Sign[] = {{" + ", ".join(str(x) for x in signs) + "};")
+    lines.append(f"static const char* const kEom{v}In[] = {{" + ", ".join(f'"{x}"' for x in inputs) + "};")
+    lines.append(f"static const char* const kEom{v}Out[] = {{" + ", ".join(f'"{x}"' for x in outputs) + "};")
+    lines.append(f"static const char* const kEom{v}Zero[] = {{")
+    for z in gen.zero_list:
+        lines.append(f'    "{z}",')
+    lines.append("};")
+    lines.append(f"static const char* const kEom{v}Terms[] = {{")
+    for t in gen.out_terms:
+        lines.append(f'    "{t}",')
+    lines.append("};")
+    return "\n".join(lines) + "\n"
+
+
+def main(variants=("IP", "EA")):
+    tabs = read_tables(os.path.join(CSRC, "ccsdt_terms.inc"))
+    for v in variants:
+        g = Generator(v, tabs)
+        outs = g.generate()
+        path = os.path.join(CSRC, f"eom_{v.lower()}_terms.inc")
+        with open(path, "w") as f:
+            f.write(emit(v, g, outs))
+        print(path, len(g.out_terms), "terms")
+
+
+if __name__ == "__main__":
+    main(tuple(sys.argv[1:]) or ("IP", "EA"))

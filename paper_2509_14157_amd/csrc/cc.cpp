@@ -79,7 +79,7 @@ void Context::setup_cc() {
   amp_ = alloc(nt_);
   res_ = alloc(nt_);
   den_ = alloc(nt_);
-  scratch_ = alloc(64 * 1024);
+  scratch_ = alloc(256 * 1024);  // per-block partial sums of up to 512 dot products
   dscal_ = alloc(1024);
   for (int k = 0; k < 3; ++k) {
     e.create("T" + tblocks_[k].name, specs[k], sz_, amp_ + tblocks_[k].offset);

@@ -66,6 +66,7 @@ class Context {
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
 
   double last_triples_flops = 0, last_all_flops = 0;
+  struct EomSpace;  // per-variant layout and tensors (eom_space.hpp)
   int debug_gemm(Prec p, int tile, int64_t M, int64_t N, int64_t K, bool a_kfast, bool b_nfast, double alpha,
                  double beta, const double* A, const double* B, double* Cm);
 
@@ -89,7 +90,6 @@ class Context {
   std::vector<double*> owned_;
 
   // EOM state
-  struct EomSpace;
   std::unique_ptr<EomSpace> eom_;
   void setup_eom(int kind);
 

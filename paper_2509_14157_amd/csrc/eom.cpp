@@ -1,14 +1,361 @@
-// EOM-CCSDT sigma vectors and block Davidson (IP, DIP, EA, DEA).
+// EOM-CCSDT sigma vectors (IP, EA, DIP, DEA) and the block Davidson solver.
+//
+// sigma = <mu| [H-bar, R] |0> over the R space of the variant (eqs 1-4); the
+// term tables come from the ground-state residual by differentiation along
+// R placed in continuum-orbital blocks (see codegen/eom_jvp.py).  The
+// ground-state intermediates (dressed integrals, F3_*, W3_*, ...) are built
+// once at the converged amplitudes and reused by every sigma evaluation.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+
 #include "eom_space.hpp"
+#include "linalg.hpp"
 
 namespace fno {
 
+#include "eom_ea_terms.inc"
+#include "eom_ip_terms.inc"
 
-size_t Context::eom_size(int) { throw Error(kEINVAL, "EOM not available in this build"); }
-void Context::eom_sigma(int, Prec, const double*, double*, size_t) {
-  throw Error(kEINVAL, "EOM not available in this build");
+namespace {
+template <typename T, size_t N>
+constexpr int count(const T (&)[N]) {
+  return (int)N;
 }
-int Context::eom(int, const EOMOptions&, EOMResult&) { throw Error(kEINVAL, "EOM not available in this build"); }
-void Context::setup_eom(int) {}
+
+std::pair<std::string, std::string> split_decl2(const char* d) {
+  std::string s(d);
+  size_t c = s.find(':');
+  auto trim = [](std::string x) {
+    size_t a = x.find_first_not_of(' '), b = x.find_last_not_of(' ');
+    return a == std::string::npos ? std::string() : x.substr(a, b - a + 1);
+  };
+  return {trim(s.substr(0, c)), trim(s.substr(c + 1))};
+}
+
+#define FNO_EOM_TABLES(V)                                                                                      \
+  EomTables{kEom##V##Decl,  count(kEom##V##Decl), kEom##V##Views,  count(kEom##V##Views), kEom##V##Blocks,   \
+            kEom##V##Sign,  kEom##V##In,          kEom##V##Out,    count(kEom##V##In),    kEom##V##Zero,     \
+            count(kEom##V##Zero), kEom##V##Terms, count(kEom##V##Terms)}
+
+EomTables tables_for(int kind) {
+  switch (kind) {
+    case 1: return FNO_EOM_TABLES(IP);
+    case 3: return FNO_EOM_TABLES(EA);
+    default: throw Error(kEINVAL, "this EOM variant is not available");
+  }
+}
+
+}  // namespace
+
+void Context::setup_eom(int kind) {
+  FNO_REQUIRE(cc_ready, kESTATE, "EOM needs ground-state amplitudes");
+  if (eom_ && eom_->kind == kind && eom_->ready) return;
+  Engine& e = *eng;
+  auto sp = std::make_unique<EomSpace>();
+  sp->kind = kind;
+  sp->tab = tables_for(kind);
+  const EomTables& t = sp->tab;
+  for (int i = 0; i < t.ndecl; ++i) {
+    auto d = split_decl2(t.decl[i]);
+    if (!e.has(d.first)) e.create(d.first, d.second, sz_);
+  }
+  for (int i = 0; i < t.nviews; ++i) {
+    std::string s(t.views[i]);
+    if (s.empty()) continue;
+    size_t eq = s.find('='), lp = s.find('('), rp = s.find(')');
+    std::string name = s.substr(0, eq), par = s.substr(eq + 1, lp - eq - 1);
+    name.erase(std::remove(name.begin(), name.end(), ' '), name.end());
+    par.erase(std::remove(par.begin(), par.end(), ' '), par.end());
+    std::vector<std::pair<int, int>> rng;
+    for (char c : s.substr(lp + 1, rp - lp - 1)) {
+      if (c == 'o') rng.push_back({0, nocc});
+      if (c == 'v') rng.push_back({nocc, nvir});
+      if (c == 'n') rng.push_back({0, nocc + nvir});
+    }
+    e.view(name, e.get(par), rng);
+  }
+  // R-vector layout: packed blocks in rank order
+  sp->dim = 0;
+  for (int b = 0; b < t.nblocks; ++b) {
+    Block B;
+    B.nh = t.blocks[b][0];
+    B.np = t.blocks[b][1];
+    B.name = t.in[b];
+    B.size = (int64_t)binom_host(nocc, B.nh) * (int64_t)binom_host(nvir, B.np);
+    FNO_REQUIRE(B.size == e.get(t.in[b])->elems && B.size == e.get(t.out[b])->elems, kEDEVICE,
+                "EOM block layout mismatch");
+    B.offset = sp->dim;
+    sp->dim += B.size;
+    sp->blocks.push_back(B);
+  }
+  // zeroth-order diagonal: sum e_particles - sum e_holes
+  sp->diag = alloc(sp->dim);
+  const int n = nocc + nvir;
+  std::vector<double> eo(nocc), ev(nvir);
+  for (int i = 0; i < nocc; ++i) eo[i] = fock[(size_t)i * n + i];
+  for (int a = 0; a < nvir; ++a) ev[a] = fock[(size_t)(nocc + a) * n + (nocc + a)];
+  double* d_e = alloc(n);
+  FNO_HIP(hipMemcpy(d_e, eo.data(), nocc * sizeof(double), hipMemcpyHostToDevice));
+  FNO_HIP(hipMemcpy(d_e + nocc, ev.data(), nvir * sizeof(double), hipMemcpyHostToDevice));
+  for (auto& B : sp->blocks) {
+    MatDim md{};
+    int q = 0;
+    if (B.nh > 0) {
+      md.grp[q].g = B.nh;
+      md.grp[q].n = nocc;
+      md.grp[q].count = (int64_t)binom_host(nocc, B.nh);
+      for (int s = 0; s < B.nh; ++s) md.grp[q].letter[s] = (int8_t)s;
+      ++q;
+    }
+    if (B.np > 0) {
+      md.grp[q].g = B.np;
+      md.grp[q].n = nvir;
+      md.grp[q].count = (int64_t)binom_host(nvir, B.np);
+      for (int s = 0; s < B.np; ++s) md.grp[q].letter[s] = (int8_t)(B.nh + s);
+      ++q;
+    }
+    md.ngroups = q;
+    md.size = B.size;
+    launch_denominators(e.tables, md, B.nh, d_e, d_e + nocc, sp->diag + B.offset, e.stream);
+    launch_axpby(sp->diag + B.offset, sp->diag + B.offset, -1.0, 0.0, B.size, e.stream);
+  }
+  // ground-state intermediates at the current amplitudes
+  residual();
+  sp->ready = true;
+  eom_ = std::move(sp);
+}
+
+size_t Context::eom_size(int kind) {
+  FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
+  const EomTables t = tables_for(kind);
+  int64_t d = 0;
+  for (int b = 0; b < t.nblocks; ++b)
+    d += (int64_t)binom_host(nocc, t.blocks[b][0]) * (int64_t)binom_host(nvir, t.blocks[b][1]);
+  return (size_t)d;
+}
+
+// sigma = (H-bar - E_CC) R on device vectors (packed R layout)
+static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double* r, double* sigma, Prec prec) {
+  const EomTables& t = sp.tab;
+  for (int b = 0; b < t.nblocks; ++b)
+    launch_axpby(e.get(t.in[b])->d, r + sp.blocks[b].offset, (double)t.sign[b], 0.0, sp.blocks[b].size, e.stream);
+  for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
+  e.stats.clear();
+  e.record = true;
+  for (int i = 0; i < t.nterms; ++i) {
+    std::string s(t.terms[i]);
+    // contractions that read or write the R3 block run in the requested precision
+    bool tri = false;
+    for (int b = 0; b < t.nblocks; ++b)
+      if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
+        tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
+        tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
+      }
+    e.prec = tri ? prec : Prec::FP64;
+    e.term(s);
+  }
+  e.prec = Prec::FP64;
+  e.record = false;
+  for (int b = 0; b < t.nblocks; ++b)
+    launch_axpby(sigma + sp.blocks[b].offset, e.get(t.out[b])->d, (double)t.sign[b], 0.0, sp.blocks[b].size,
+                 e.stream);
+  double tri = 0, all = 0;
+  for (auto& st : e.stats) {
+    all += st.flops;
+    for (int b = 0; b < t.nblocks; ++b)
+      if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
+          (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
+           st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
+        tri += st.flops;
+        break;
+      }
+  }
+  c.last_triples_flops = tri;
+  c.last_all_flops = all;
+}
+
+void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len) {
+  FNO_REQUIRE(cc_ready, kESTATE, "EOM sigma needs amplitudes (fno_ccsdt or fno_set_amplitudes)");
+  FNO_REQUIRE(len == eom_size(kind), kEINVAL, "R vector length mismatch");
+  if (eom_) eom_->ready = eom_->ready && eom_->kind == kind;
+  // amplitudes may have been changed through fno_set_amplitudes: rebuild the intermediates
+  eom_.reset();
+  setup_eom(kind);
+  Engine& e = *eng;
+  double* dr = alloc((int64_t)len);
+  double* ds = alloc((int64_t)len);
+  FNO_HIP(hipMemcpy(dr, r, len * sizeof(double), hipMemcpyHostToDevice));
+  eom_apply(*this, e, *eom_, dr, ds, p);
+  FNO_HIP(hipMemcpy(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost));
+  FNO_HIP(hipFree(dr));
+  FNO_HIP(hipFree(ds));
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), dr), owned_.end());
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), ds), owned_.end());
+}
+
+// Block Davidson for the lowest right eigenpairs (by real part) of the
+// nonsymmetric EOM matrix.  Subspace vectors and sigma vectors live on the
+// device; the small projected matrix G = V^T S is diagonalised on the host.
+int Context::eom(int kind, const EOMOptions& opt, EOMResult& res) {
+  FNO_REQUIRE(cc_done, kESTATE, "fno_eom needs a converged fno_ccsdt first");
+  FNO_REQUIRE(opt.nroots >= 1 && opt.max_iter >= 1, kEINVAL, "bad EOM options");
+  eom_.reset();
+  setup_eom(kind);
+  EomSpace& sp = *eom_;
+  Engine& e = *eng;
+  const int64_t dim = sp.dim;
+  const int nroots = opt.nroots;
+  FNO_REQUIRE(nroots <= dim, kEINVAL, "more roots than the EOM space has states");
+  const int max_sub = std::min(std::max(opt.max_sub > 0 ? opt.max_sub : 8 * nroots, 2 * nroots), 512);
+  double* V = alloc((int64_t)max_sub * dim);
+  double* S = alloc((int64_t)max_sub * dim);
+  double* X = alloc((int64_t)nroots * dim);
+  double* W = alloc(dim);                 // work vector
+  double* dco = alloc(std::max(max_sub, nroots) + 8);
+  double* dots = alloc(std::max(max_sub, 1) + 8);
+  std::vector<double*> mine = {V, S, X, W, dco, dots};
+  auto release = [&]() {
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    for (double* p : mine) {
+      owned_.erase(std::remove(owned_.begin(), owned_.end(), p), owned_.end());
+      (void)hipFree(p);
+    }
+  };
+  auto vec = [&](double* base, int j) { return base + (int64_t)j * dim; };
+  auto dots_with = [&](const double* xs, int nvec, const double* y, std::vector<double>& out) {
+    out.assign(nvec, 0.0);
+    if (nvec == 0) return;
+    launch_dots(xs, dim, nvec, y, dim, scratch_, dots, e.stream);
+    FNO_HIP(hipMemcpyAsync(out.data(), dots, nvec * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  };
+  auto combine = [&](double* y, const double* xs, const std::vector<double>& c, double alpha, double beta) {
+    FNO_HIP(hipMemcpyAsync(dco, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
+    launch_combine(y, xs, dim, dco, (int)c.size(), alpha, beta, dim, e.stream);
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  };
+  // guesses: unit vectors on the lowest zeroth-order diagonal entries of the
+  // principal block, continued into the other blocks when it is too small
+  std::vector<double> dall(dim);
+  FNO_HIP(hipMemcpy(dall.data(), sp.diag, dim * sizeof(double), hipMemcpyDeviceToHost));
+  const int64_t n0 = sp.blocks[0].size;
+  std::vector<int64_t> order(dim);
+  for (int64_t i = 0; i < dim; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    const bool pa = a < n0, pb = b < n0;
+    if (pa != pb) return pa;
+    return dall[a] < dall[b];
+  });
+  int nv = 0;
+  for (int k = 0; k < nroots; ++k) {
+    launch_fill(vec(V, nv), 0.0, dim, e.stream);
+    double one = 1.0;
+    FNO_HIP(hipMemcpyAsync(vec(V, nv) + order[k], &one, sizeof(double), hipMemcpyHostToDevice, e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    ++nv;
+  }
+  int ns = 0;  // sigma vectors computed
+  std::vector<double> G((size_t)max_sub * max_sub, 0.0);
+  std::vector<double> theta(nroots, 0.0), theta_old(nroots, INFINITY), rn(nroots, INFINITY);
+  int it = 0, status = kENOCONV;
+  for (it = 1; it <= opt.max_iter; ++it) {
+    for (; ns < nv; ++ns) eom_apply(*this, e, sp, vec(V, ns), vec(S, ns), opt.prec);
+    // G[i][j] = v_i . s_j (all entries; the subspace is small)
+    for (int j = 0; j < nv; ++j) {
+      std::vector<double> col;
+      dots_with(V, nv, vec(S, j), col);
+      for (int i = 0; i < nv; ++i) G[(size_t)i * max_sub + j] = col[i];
+    }
+    std::vector<double> Gs((size_t)nv * nv);
+    for (int i = 0; i < nv; ++i)
+      for (int j = 0; j < nv; ++j) Gs[(size_t)i * nv + j] = G[(size_t)i * max_sub + j];
+    std::vector<double> wr, wi;
+    FNO_REQUIRE(nonsym_eigvals(nv, Gs, wr, wi), kENOCONV, "subspace eigenproblem failed");
+    std::vector<int> idx(nv);
+    for (int i = 0; i < nv; ++i) idx[i] = i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return wr[a] < wr[b]; });
+    // Ritz vectors and residuals
+    std::vector<std::vector<double>> Y(nroots);
+    for (int k = 0; k < nroots; ++k) {
+      theta[k] = wr[idx[k]];
+      inverse_iteration(nv, Gs, theta[k], Y[k]);
+      combine(vec(X, k), V, Y[k], 1.0, 0.0);
+      std::vector<double> nn;
+      dots_with(vec(X, k), 1, vec(X, k), nn);
+      const double nrm = std::sqrt(nn[0]);
+      for (double& y : Y[k]) y /= nrm;
+      launch_axpby(vec(X, k), vec(X, k), 1.0 / nrm, 0.0, dim, e.stream);
+    }
+    bool all_conv = true;
+    std::vector<bool> conv(nroots);
+    for (int k = 0; k < nroots; ++k) {
+      // W = S y - theta x
+      combine(W, S, Y[k], 1.0, 0.0);
+      launch_axpby(W, vec(X, k), -theta[k], 1.0, dim, e.stream);
+      std::vector<double> nn;
+      dots_with(W, 1, W, nn);
+      rn[k] = std::sqrt(nn[0]);
+      conv[k] = rn[k] < opt.r_tol && std::fabs(theta[k] - theta_old[k]) < opt.e_tol;
+      all_conv = all_conv && conv[k];
+      if (!std::isfinite(rn[k])) {
+        release();
+        throw Error(kENONFINITE, "non-finite EOM residual");
+      }
+    }
+    theta_old = theta;
+    if (all_conv) {
+      status = kOK;
+      break;
+    }
+    if (nv + nroots > max_sub) {
+      // collapse onto the orthonormalised Ritz vectors
+      int m = 0;
+      for (int k = 0; k < nroots; ++k) {
+        launch_axpby(vec(V, m), vec(X, k), 1.0, 0.0, dim, e.stream);
+        for (int pass = 0; pass < 2; ++pass) {
+          std::vector<double> c;
+          dots_with(V, m, vec(V, m), c);
+          if (m) combine(vec(V, m), V, c, -1.0, 1.0);
+        }
+        std::vector<double> nn;
+        dots_with(vec(V, m), 1, vec(V, m), nn);
+        if (std::sqrt(nn[0]) > 1e-10) {
+          launch_axpby(vec(V, m), vec(V, m), 1.0 / std::sqrt(nn[0]), 0.0, dim, e.stream);
+          ++m;
+        }
+      }
+      nv = m;
+      ns = 0;
+      continue;
+    }
+    // preconditioned residuals, orthogonalised twice (classical Gram-Schmidt)
+    for (int k = 0; k < nroots; ++k) {
+      if (rn[k] < opt.r_tol) continue;
+      if (nv >= max_sub) break;
+      combine(W, S, Y[k], 1.0, 0.0);
+      launch_axpby(W, vec(X, k), -theta[k], 1.0, dim, e.stream);
+      launch_precond(vec(V, nv), W, sp.diag, theta[k], dim, e.stream);
+      for (int pass = 0; pass < 2; ++pass) {
+        std::vector<double> c;
+        dots_with(V, nv, vec(V, nv), c);
+        combine(vec(V, nv), V, c, -1.0, 1.0);
+      }
+      std::vector<double> nn;
+      dots_with(vec(V, nv), 1, vec(V, nv), nn);
+      const double nrm = std::sqrt(nn[0]);
+      if (nrm > 1e-10) {
+        launch_axpby(vec(V, nv), vec(V, nv), 1.0 / nrm, 0.0, dim, e.stream);
+        ++nv;
+      }
+    }
+  }
+  res.omega = theta;
+  res.res_norm = rn;
+  res.iters = std::min(it, opt.max_iter);
+  res.converged = status == kOK;
+  release();
+  return status;
+}
 
 }  // namespace fno

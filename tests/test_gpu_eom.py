@@ -1,0 +1,135 @@
+"""GPU parity of the EOM-CCSDT sigma vectors and roots against the CPU oracle.
+
+Sigma elements: FP64 to 1e-11 relative to the largest element.  Roots: 1e-8
+Eh against the oracle (dense or Davidson), exact FCI where the operator space
+is complete (IP with 3 electrons, EA with 2).  Mixed precision: 1e-5 Eh.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from synthetic import make_hamiltonian, config_hamiltonian
+from oracle import cc, det, fno, wick
+from tests.helpers import random_amps, random_antisym
+from tests.packing import pack, LazyAntisym
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2509_14157_amd as P
+    return P
+
+
+def _ctx(P, fock, eri, nocc):
+    c = P.Context(0)
+    c.load_hamiltonian(fock, eri, nocc)
+    return c
+
+
+def _set(c, amps):
+    c.set_amplitudes(1, amps[1].ravel())
+    c.set_amplitudes(2, pack(amps[2], 2, 2))
+    c.set_amplitudes(3, pack(amps[3], 3, 3))
+
+
+@pytest.mark.parametrize("kind,o,v,seed", [("IP", 3, 5, 1), ("EA", 3, 5, 2), ("IP", 5, 9, 3), ("EA", 4, 10, 4),
+                                           ("IP", 6, 7, 5), ("EA", 2, 12, 6)])
+def test_sigma_matches_oracle(P, kind, o, v, seed):
+    print(f"sigma parity {kind} o={o} v={v}", flush=True)
+    h = make_hamiltonian(o, v, seed)
+    rng = np.random.default_rng(seed)
+    amps = random_amps(rng, o, v)
+    _, blocks = wick.EOM_SPACES[kind]
+    rb = {b: random_antisym(rng, o, v, b[0], b[1], 1.0) for b in blocks}
+    r = np.concatenate([pack(rb[b], *b) for b in blocks])
+    with _ctx(P, h.fock, h.eri, o) as c:
+        _set(c, amps)
+        assert c.eom_size(kind) == r.size
+        sig = c.eom_sigma(kind, r)
+    ref = cc.eom_sigma(h.fock, h.eri, o, amps, kind, rb)
+    refv = np.concatenate([pack(ref[b], *b) for b in blocks])
+    assert np.abs(sig - refv).max() < 1e-11 * max(1.0, np.abs(refv).max())
+
+
+def test_ip_exact_for_three_electrons(P):
+    h = make_hamiltonian(3, 5, 21)
+    with _ctx(P, h.fock, h.eri, 3) as c:
+        c.ccsdt(r_tol=1e-11, e_tol=1e-13)
+        r = c.eom("IP", nroots=4, r_tol=1e-9, e_tol=1e-11)
+    assert r["converged"]
+    fci = det.DetModel(h.fock, h.eri, 3).fci(2)[:4]
+    assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
+
+
+def test_ea_exact_for_two_electrons(P):
+    h = make_hamiltonian(2, 6, 22)
+    with _ctx(P, h.fock, h.eri, 2) as c:
+        c.ccsdt(r_tol=1e-11, e_tol=1e-13)
+        r = c.eom("EA", nroots=4, r_tol=1e-9, e_tol=1e-11)
+    assert r["converged"]
+    fci = det.DetModel(h.fock, h.eri, 2).fci(3)[:4]
+    assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
+
+
+@pytest.mark.parametrize("kind", ["IP", "EA"])
+def test_roots_match_oracle(P, kind):
+    h = make_hamiltonian(4, 8, 31)
+    ref = cc.solve_ccsdt(h.fock, h.eri, 4, r_tol=1e-10, e_tol=1e-12)
+    d = cc.davidson(h.fock, h.eri, 4, ref["amps"], kind, 3, r_tol=1e-8, e_tol=1e-11)
+    assert d["converged"]
+    w = np.sort(d["omega"])
+    with _ctx(P, h.fock, h.eri, 4) as c:
+        g = c.ccsdt(r_tol=1e-10, e_tol=1e-12)
+        r = c.eom(kind, nroots=3, r_tol=1e-8, e_tol=1e-10)
+    assert r["converged"]
+    assert abs(g["e_tot"] - ref["e_tot"]) < 1e-8
+    assert np.abs(np.sort(r["omega"]) - w).max() < 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_roots(P, prec):
+    h = make_hamiltonian(4, 10, 33)
+    with _ctx(P, h.fock, h.eri, 4) as c:
+        c.ccsdt(r_tol=1e-10, e_tol=1e-12)
+        r64 = c.eom("EA", nroots=3, r_tol=1e-7, e_tol=1e-10)
+        r = c.eom("EA", nroots=3, r_tol=1e-5, e_tol=1e-8, prec=prec, allow_noconv=True)
+    assert np.abs(np.sort(r["omega"]) - np.sort(r64["omega"])).max() < 1e-5
+
+
+@pytest.mark.parametrize("kind", ["IP", "EA"])
+def test_full_size_sampled_sigma(P, kind):
+    """o=12, v=48 after FNO (80 virtuals kept to 48): sampled sigma elements vs the oracle."""
+    h = config_hamiltonian("C3")
+    tr = fno.truncate(h.fock, h.eri, 12, nvir_keep=48)
+    o, v = 12, 48
+    rng = np.random.default_rng(17)
+    t1 = rng.normal(0, 0.01, (o, v))
+    t2p = rng.normal(0, 0.01, math.comb(o, 2) * math.comb(v, 2))
+    t3p = rng.normal(0, 0.002, math.comb(o, 3) * math.comb(v, 3))
+    _, blocks = wick.EOM_SPACES[kind]
+    rvec = [rng.normal(0, 1.0, math.comb(o, b[0]) * math.comb(v, b[1])) for b in blocks]
+    with _ctx(P, h.fock, h.eri, 12) as c:
+        kept, _, _ = c.truncate(1.0, 48)
+        assert kept == 48
+        c.set_amplitudes(1, t1.ravel())
+        c.set_amplitudes(2, t2p)
+        c.set_amplitudes(3, t3p)
+        sig = c.eom_sigma(kind, np.concatenate(rvec))
+    amps = {1: t1, 2: LazyAntisym(t2p, o, v, 2, 2)[:, :, :, :], 3: LazyAntisym(t3p, o, v, 3, 3)}
+    rb = {b: LazyAntisym(x, o, v, *b)[(slice(None),) * (b[0] + b[1])] for b, x in zip(blocks, rvec)}
+    offs = np.cumsum([0] + [x.size for x in rvec])
+    big = blocks[2]
+    S3 = LazyAntisym(sig[offs[2]:offs[3]], o, v, *big)
+    picks = [tuple(range(big[0])) + tuple(range(big[1])),
+             tuple(range(o - big[0], o)) + tuple(range(v - big[1], v)),
+             tuple(range(2, 2 + 3 * big[0], 3)) + tuple(range(5, 5 + 11 * big[1], 11))]
+    for idx in picks:
+        ref = cc.eom_sigma_element(tr["fock"], tr["eri"], o, amps, kind, rb, big, idx)
+        assert abs(S3[idx] - ref) < 1e-10 * max(1.0, abs(ref)), idx
+    S1 = LazyAntisym(sig[offs[0]:offs[1]], o, v, *blocks[0])
+    idx1 = tuple([1] * 0 + list(range(blocks[0][0]))) + tuple(range(blocks[0][1]))
+    ref1 = cc.eom_sigma_element(tr["fock"], tr["eri"], o, amps, kind, rb, blocks[0], idx1)
+    assert abs(S1[idx1] - ref1) < 1e-10 * max(1.0, abs(ref1))
