@@ -39,7 +39,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     # EOM sigma tables are generated from the ground-state tables
     from .codegen import eom_jvp
-    eom_jvp.main(("IP", "EA"))
+    eom_jvp.main(("IP", "EA", "DIP", "DEA"))
     os.makedirs(OBJ, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
         objs = list(ex.map(_compile, SOURCES))

@@ -28,6 +28,10 @@ carry first-order blocks:
   IP: dGd[p,x,r,s] = -sum_m r_m Gd[p,m,r,s],  dFd[x,q] = -sum_m r_m Fd[m,q];
   EA: dGd[p,q,r,x] = +sum_a r^a Gd[p,q,r,a],  dFd[p,x] = +sum_a r^a Fd[p,a].
 
+The DIP and DEA R operators reach rank four (4h2p, 4p2h); their quadruples
+projection comes from the linearized table in csrc/eom_quad_terms.inc, whose
+direction blocks receive the continuum labels the same way.
+
 Usage: python -m paper_2509_14157_amd.codegen.eom_jvp  (writes csrc/eom_*_terms.inc)
 """
 from __future__ import annotations
@@ -47,9 +51,14 @@ VARIANTS = {
     # name: (continuum labels, their index space, R blocks as (ground-state amplitude, (nh, np)))
     "IP": (("x",), "v", (("T1", (1, 0)), ("T2", (2, 1)), ("T3", (3, 2)))),
     "EA": (("x",), "o", (("T1", (0, 1)), ("T2", (1, 2)), ("T3", (2, 3)))),
-    "DIP": (("x", "y"), "v", (("T2", (2, 0)), ("T3", (3, 1)))),
-    "DEA": (("x", "y"), "o", (("T2", (0, 2)), ("T3", (1, 3)))),
+    "DIP": (("x", "y"), "v", (("T2", (2, 0)), ("T3", (3, 1)), ("T4", (4, 2)))),
+    "DEA": (("x", "y"), "o", (("T2", (0, 2)), ("T3", (1, 3)), ("T4", (2, 4)))),
 }
+
+# The quadruples projection enters only through its linearization (a
+# hand-written table): direction and image names map onto the amplitude and
+# residual tensors whose continuum blocks they are.
+QUAD_ALIAS = {"D2": "T2", "D3": "T3", "D4": "T4", "S2": "R2", "S3": "R3", "S4": "R4"}
 
 
 def read_tables(path):
@@ -121,10 +130,13 @@ def move_to_end_sign(group_letters, moved):
 
 
 class Generator:
-    def __init__(self, variant, cc_tables):
+    def __init__(self, variant, cc_tables, quad_tables=None):
         self.variant = variant
         self.labels, self.space, self.rblocks = VARIANTS[variant]
         self.t = cc_tables
+        self.q = quad_tables if any(a == "T4" for a, _ in self.rblocks) else None
+        self.prim_decls = {}     # T-only intermediates of the quadruples table that the terms use
+        self.prep = []           # their defining terms
         self.tensors = {}
         self.out_terms = []      # generated term strings
         self.decls = {}          # R-block tensor name -> spec
@@ -134,6 +146,16 @@ class Generator:
         for d in cc_tables["kCCDecl"]:
             t = parse_decl(d)
             self.tensors[t.name] = t
+        self.qdecl = {}
+        if self.q is not None:
+            for d in ("T4 : oooo,vvvv", "R4 : oooo,vvvv"):
+                t = parse_decl(d)
+                self.tensors[t.name] = t
+            for d in self.q["kQDecl"]:
+                t = parse_decl(d)
+                self.qdecl[t.name] = d
+                if t.name not in QUAD_ALIAS:
+                    self.tensors[t.name] = t
         # dressed / bare integrals
         self.tensors["Gd"] = Tensor("Gd", "nnnn", [[0, 1], [2, 3]], packed=False)
         self.tensors["Fd"] = Tensor("Fd", "nn", [[0], [1]], packed=False)
@@ -227,15 +249,28 @@ class Generator:
         return None
 
     # ---------------------------------------------------------- term JVP
-    def jvp(self, spec):
+    def jvp(self, spec, linear=False):
+        """Sigma terms of one table term.
+
+        linear=False: a ground-state term, differentiated through every factor.
+        linear=True: a term of the linearized quadruples table; only the
+        direction (D2, D3, D4) and the first-order intermediates (d*) carry
+        the continuum labels, the other factor is a T-only tensor.
+        """
         m = TERM.match(spec)
         assert m, spec
         out, lo, sg, coef, A, la, B, lb = m.groups()
         c = float(eval(coef)) if coef else 1.0
         if sg == "-":
             c = -c
+        out = QUAD_ALIAS.get(out, out)
         To = self.tensors[out]
         factors = [(A, la)] + ([(B, lb)] if B else [])
+        carriers = None
+        if linear:
+            carriers = [fi for fi, (F, _) in enumerate(factors) if F in ("D2", "D3", "D4") or F.startswith("d")]
+            assert len(carriers) == 1, spec
+            factors = [(QUAD_ALIAS.get(F, F), lf) for F, lf in factors]
 
         def letter_groups(t, letters):
             return [[letters[s] for s in g] for g in t.groups]
@@ -243,6 +278,8 @@ class Generator:
         go = letter_groups(To, lo)
         ospace = [To.spaces[g[0]] for g in To.groups]
         for fi, (F, lf) in enumerate(factors):
+            if carriers is not None and fi not in carriers:
+                continue
             TF = self.tensors[F]
             gf = letter_groups(TF, lf)
             fspace = [TF.spaces[g[0]] for g in TF.groups]
@@ -291,9 +328,18 @@ class Generator:
                     self.nonzero.add(oname)
                     self.zero_list.append(oname)
 
-    @staticmethod
-    def ok_order(oasg):
-        return True
+    def collect_prep(self):
+        """T-only quadruples intermediates referenced by the generated terms, and their definitions."""
+        used = set()
+        for term in self.out_terms:
+            used.update(re.findall(r"(\w+)\[", term))
+        prim = [n for n in self.qdecl if n not in QUAD_ALIAS and not n.startswith("d")]
+        need = [n for n in prim if n in used]
+        for n in need:
+            self.prim_decls[n] = self.qdecl[n].split(":")[1].strip()
+        for spec in self.q["kQPrep"]:
+            if TERM.match(spec).group(1) in need:
+                self.prep.append(spec)
 
     def generate(self):
         self.view_blocks()
@@ -304,6 +350,10 @@ class Generator:
         for blk in ("kCCInter2", "kCCR1", "kCCR2", "kCCInter3", "kCCR3"):
             for spec in self.t[blk]:
                 self.jvp(spec)
+        if self.q is not None:
+            for spec in self.q["kQTerms"]:
+                self.jvp(spec, linear=True)
+            self.collect_prep()
         outputs = []
         for amp, _ in self.rblocks:
             res = "R" + amp[1:]
@@ -353,13 +403,27 @@ def emit(variant, gen: Generator, outputs):
     for t in gen.out_terms:
         lines.append(f'    "{t}",')
     lines.append("};")
+    lines.append(f"// T-only intermediates built once per set of amplitudes")
+    lines.append(f"static const char* const kEom{v}PrimDecl[] = {{")
+    for name in gen.prim_decls:
+        lines.append(f'    "{name} : {gen.prim_decls[name]}",')
+    if not gen.prim_decls:
+        lines.append('    "",')
+    lines.append("};")
+    lines.append(f"static const char* const kEom{v}Prep[] = {{")
+    for t in gen.prep:
+        lines.append(f'    "{t}",')
+    if not gen.prep:
+        lines.append('    "",')
+    lines.append("};")
     return "\n".join(lines) + "\n"
 
 
-def main(variants=("IP", "EA")):
+def main(variants=("IP", "EA", "DIP", "DEA")):
     tabs = read_tables(os.path.join(CSRC, "ccsdt_terms.inc"))
+    quad = read_tables(os.path.join(CSRC, "eom_quad_terms.inc"))
     for v in variants:
-        g = Generator(v, tabs)
+        g = Generator(v, tabs, quad)
         outs = g.generate()
         path = os.path.join(CSRC, f"eom_{v.lower()}_terms.inc")
         with open(path, "w") as f:
@@ -368,4 +432,4 @@ def main(variants=("IP", "EA")):
 
 
 if __name__ == "__main__":
-    main(tuple(sys.argv[1:]) or ("IP", "EA"))
+    main(tuple(sys.argv[1:]) or ("IP", "EA", "DIP", "DEA"))

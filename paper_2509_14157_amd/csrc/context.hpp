@@ -92,6 +92,7 @@ class Context {
   // EOM state
   std::unique_ptr<EomSpace> eom_;
   void setup_eom(int kind);
+  void release_eom();
 
   double* alloc(int64_t n);
 };

@@ -14,6 +14,8 @@
 
 namespace fno {
 
+#include "eom_dea_terms.inc"
+#include "eom_dip_terms.inc"
 #include "eom_ea_terms.inc"
 #include "eom_ip_terms.inc"
 
@@ -33,33 +35,55 @@ std::pair<std::string, std::string> split_decl2(const char* d) {
   return {trim(s.substr(0, c)), trim(s.substr(c + 1))};
 }
 
-#define FNO_EOM_TABLES(V)                                                                                      \
-  EomTables{kEom##V##Decl,  count(kEom##V##Decl), kEom##V##Views,  count(kEom##V##Views), kEom##V##Blocks,   \
-            kEom##V##Sign,  kEom##V##In,          kEom##V##Out,    count(kEom##V##In),    kEom##V##Zero,     \
-            count(kEom##V##Zero), kEom##V##Terms, count(kEom##V##Terms)}
+#define FNO_EOM_TABLES(V)                                                                                   \
+  EomTables{kEom##V##Decl,     count(kEom##V##Decl),  kEom##V##Views,  count(kEom##V##Views),            \
+            kEom##V##Blocks,   kEom##V##Sign,         kEom##V##In,     kEom##V##Out,                     \
+            count(kEom##V##In), kEom##V##Zero,        count(kEom##V##Zero), kEom##V##Terms,              \
+            count(kEom##V##Terms), kEom##V##PrimDecl, count(kEom##V##PrimDecl), kEom##V##Prep,           \
+            count(kEom##V##Prep)}
 
 EomTables tables_for(int kind) {
   switch (kind) {
     case 1: return FNO_EOM_TABLES(IP);
+    case 2: return FNO_EOM_TABLES(DIP);
     case 3: return FNO_EOM_TABLES(EA);
-    default: throw Error(kEINVAL, "this EOM variant is not available");
+    case 4: return FNO_EOM_TABLES(DEA);
+    default: throw Error(kEINVAL, "unknown EOM variant");
   }
 }
 
 }  // namespace
 
+void Context::release_eom() {
+  if (!eom_) return;
+  Engine& e = *eng;
+  FNO_HIP(hipStreamSynchronize(e.stream));
+  for (auto& name : eom_->created) e.drop(name);
+  if (eom_->diag) {
+    owned_.erase(std::remove(owned_.begin(), owned_.end(), eom_->diag), owned_.end());
+    FNO_HIP(hipFree(eom_->diag));
+  }
+  eom_.reset();
+}
+
 void Context::setup_eom(int kind) {
   FNO_REQUIRE(cc_ready, kESTATE, "EOM needs ground-state amplitudes");
   if (eom_ && eom_->kind == kind && eom_->ready) return;
+  release_eom();
   Engine& e = *eng;
   auto sp = std::make_unique<EomSpace>();
   sp->kind = kind;
   sp->tab = tables_for(kind);
   const EomTables& t = sp->tab;
-  for (int i = 0; i < t.ndecl; ++i) {
-    auto d = split_decl2(t.decl[i]);
-    if (!e.has(d.first)) e.create(d.first, d.second, sz_);
-  }
+  auto make = [&](const char* decl) {
+    if (!decl[0]) return;
+    auto d = split_decl2(decl);
+    FNO_REQUIRE(!e.has(d.first), kEDEVICE, "EOM tensor already exists: " + d.first);
+    e.create(d.first, d.second, sz_);
+    sp->created.push_back(d.first);
+  };
+  for (int i = 0; i < t.ndecl; ++i) make(t.decl[i]);
+  for (int i = 0; i < t.nprim_decl; ++i) make(t.prim_decl[i]);
   for (int i = 0; i < t.nviews; ++i) {
     std::string s(t.views[i]);
     if (s.empty()) continue;
@@ -73,7 +97,9 @@ void Context::setup_eom(int kind) {
       if (c == 'v') rng.push_back({nocc, nvir});
       if (c == 'n') rng.push_back({0, nocc + nvir});
     }
+    FNO_REQUIRE(!e.has(name), kEDEVICE, "EOM view already exists: " + name);
     e.view(name, e.get(par), rng);
+    sp->created.push_back(name);
   }
   // R-vector layout: packed blocks in rank order
   sp->dim = 0;
@@ -120,8 +146,15 @@ void Context::setup_eom(int kind) {
     launch_denominators(e.tables, md, B.nh, d_e, d_e + nocc, sp->diag + B.offset, e.stream);
     launch_axpby(sp->diag + B.offset, sp->diag + B.offset, -1.0, 0.0, B.size, e.stream);
   }
-  // ground-state intermediates at the current amplitudes
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), d_e), owned_.end());
+  FNO_HIP(hipStreamSynchronize(e.stream));
+  FNO_HIP(hipFree(d_e));
+  // ground-state intermediates at the current amplitudes, then the T-only
+  // intermediates of the quadruples projection (DIP, DEA)
   residual();
+  e.prec = Prec::FP64;
+  for (int i = 0; i < t.nprep; ++i)
+    if (t.prep[i][0]) e.term(t.prep[i]);
   sp->ready = true;
   eom_ = std::move(sp);
 }
@@ -180,7 +213,7 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
   FNO_REQUIRE(len == eom_size(kind), kEINVAL, "R vector length mismatch");
   if (eom_) eom_->ready = eom_->ready && eom_->kind == kind;
   // amplitudes may have been changed through fno_set_amplitudes: rebuild the intermediates
-  eom_.reset();
+  release_eom();
   setup_eom(kind);
   Engine& e = *eng;
   double* dr = alloc((int64_t)len);
@@ -200,7 +233,7 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
 int Context::eom(int kind, const EOMOptions& opt, EOMResult& res) {
   FNO_REQUIRE(cc_done, kESTATE, "fno_eom needs a converged fno_ccsdt first");
   FNO_REQUIRE(opt.nroots >= 1 && opt.max_iter >= 1, kEINVAL, "bad EOM options");
-  eom_.reset();
+  release_eom();
   setup_eom(kind);
   EomSpace& sp = *eom_;
   Engine& e = *eng;

@@ -21,6 +21,10 @@ struct EomTables {
   int nzero;
   const char* const* terms;
   int nterms;
+  const char* const* prim_decl;  // T-only intermediates (DIP, DEA): built once per amplitudes
+  int nprim_decl;
+  const char* const* prep;
+  int nprep;
 };
 
 struct Context::EomSpace {
@@ -29,6 +33,7 @@ struct Context::EomSpace {
   std::vector<Block> blocks;   // (nh, np), packed sizes and offsets in the R vector
   int64_t dim = 0;
   double* diag = nullptr;      // zeroth-order diagonal sum e_particles - sum e_holes
+  std::vector<std::string> created;  // engine tensors owned by this variant
   bool ready = false;
 };
 

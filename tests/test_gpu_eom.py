@@ -2,7 +2,8 @@
 
 Sigma elements: FP64 to 1e-11 relative to the largest element.  Roots: 1e-8
 Eh against the oracle (dense or Davidson), exact FCI where the operator space
-is complete (IP with 3 electrons, EA with 2).  Mixed precision: 1e-5 Eh.
+is complete (IP with 3 electrons, DIP with 4, EA and DEA with 2).  Mixed
+precision: 1e-5 Eh.
 """
 import math
 
@@ -36,7 +37,8 @@ def _set(c, amps):
 
 
 @pytest.mark.parametrize("kind,o,v,seed", [("IP", 3, 5, 1), ("EA", 3, 5, 2), ("IP", 5, 9, 3), ("EA", 4, 10, 4),
-                                           ("IP", 6, 7, 5), ("EA", 2, 12, 6)])
+                                           ("IP", 6, 7, 5), ("EA", 2, 12, 6), ("DIP", 4, 5, 7), ("DIP", 6, 6, 8),
+                                           ("DEA", 2, 6, 9), ("DEA", 4, 7, 10)])
 def test_sigma_matches_oracle(P, kind, o, v, seed):
     print(f"sigma parity {kind} o={o} v={v}", flush=True)
     h = make_hamiltonian(o, v, seed)
@@ -64,6 +66,26 @@ def test_ip_exact_for_three_electrons(P):
     assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
 
 
+def test_dip_exact_for_four_electrons(P):
+    h = make_hamiltonian(4, 4, 23)
+    with _ctx(P, h.fock, h.eri, 4) as c:
+        c.ccsdt(r_tol=1e-11, e_tol=1e-13)
+        r = c.eom("DIP", nroots=4, r_tol=1e-9, e_tol=1e-11)
+    assert r["converged"]
+    fci = det.DetModel(h.fock, h.eri, 4).fci(2)[:4]
+    assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
+
+
+def test_dea_exact_for_two_electrons(P):
+    h = make_hamiltonian(2, 5, 24)
+    with _ctx(P, h.fock, h.eri, 2) as c:
+        c.ccsdt(r_tol=1e-11, e_tol=1e-13)
+        r = c.eom("DEA", nroots=4, r_tol=1e-9, e_tol=1e-11)
+    assert r["converged"]
+    fci = det.DetModel(h.fock, h.eri, 2).fci(4)[:4]
+    assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
+
+
 def test_ea_exact_for_two_electrons(P):
     h = make_hamiltonian(2, 6, 22)
     with _ctx(P, h.fock, h.eri, 2) as c:
@@ -74,14 +96,14 @@ def test_ea_exact_for_two_electrons(P):
     assert np.abs(np.sort(r["e_tot"]) - fci).max() < 1e-8
 
 
-@pytest.mark.parametrize("kind", ["IP", "EA"])
-def test_roots_match_oracle(P, kind):
-    h = make_hamiltonian(4, 8, 31)
-    ref = cc.solve_ccsdt(h.fock, h.eri, 4, r_tol=1e-10, e_tol=1e-12)
-    d = cc.davidson(h.fock, h.eri, 4, ref["amps"], kind, 3, r_tol=1e-8, e_tol=1e-11)
+@pytest.mark.parametrize("kind,o,v", [("IP", 4, 8), ("EA", 4, 8), ("DIP", 5, 4), ("DEA", 3, 5)])
+def test_roots_match_oracle(P, kind, o, v):
+    h = make_hamiltonian(o, v, 31)
+    ref = cc.solve_ccsdt(h.fock, h.eri, o, r_tol=1e-10, e_tol=1e-12)
+    d = cc.davidson(h.fock, h.eri, o, ref["amps"], kind, 3, r_tol=1e-8, e_tol=1e-11)
     assert d["converged"]
     w = np.sort(d["omega"])
-    with _ctx(P, h.fock, h.eri, 4) as c:
+    with _ctx(P, h.fock, h.eri, o) as c:
         g = c.ccsdt(r_tol=1e-10, e_tol=1e-12)
         r = c.eom(kind, nroots=3, r_tol=1e-8, e_tol=1e-10)
     assert r["converged"]
@@ -89,17 +111,18 @@ def test_roots_match_oracle(P, kind):
     assert np.abs(np.sort(r["omega"]) - w).max() < 1e-8
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_precision_roots(P, prec):
+@pytest.mark.parametrize("kind,prec", [("EA", "fp32"), ("EA", "bf16x3"), ("DIP", "fp32"), ("DEA", "fp32"),
+                                       ("DEA", "bf16x3")])
+def test_mixed_precision_roots(P, kind, prec):
     h = make_hamiltonian(4, 10, 33)
     with _ctx(P, h.fock, h.eri, 4) as c:
         c.ccsdt(r_tol=1e-10, e_tol=1e-12)
-        r64 = c.eom("EA", nroots=3, r_tol=1e-7, e_tol=1e-10)
-        r = c.eom("EA", nroots=3, r_tol=1e-5, e_tol=1e-8, prec=prec, allow_noconv=True)
+        r64 = c.eom(kind, nroots=3, r_tol=1e-7, e_tol=1e-10)
+        r = c.eom(kind, nroots=3, r_tol=1e-5, e_tol=1e-8, prec=prec, allow_noconv=True)
     assert np.abs(np.sort(r["omega"]) - np.sort(r64["omega"])).max() < 1e-5
 
 
-@pytest.mark.parametrize("kind", ["IP", "EA"])
+@pytest.mark.parametrize("kind", ["IP", "EA", "DIP", "DEA"])
 def test_full_size_sampled_sigma(P, kind):
     """o=12, v=48 after FNO (80 virtuals kept to 48): sampled sigma elements vs the oracle."""
     h = config_hamiltonian("C3")
@@ -119,7 +142,9 @@ def test_full_size_sampled_sigma(P, kind):
         c.set_amplitudes(3, t3p)
         sig = c.eom_sigma(kind, np.concatenate(rvec))
     amps = {1: t1, 2: LazyAntisym(t2p, o, v, 2, 2)[:, :, :, :], 3: LazyAntisym(t3p, o, v, 3, 3)}
-    rb = {b: LazyAntisym(x, o, v, *b)[(slice(None),) * (b[0] + b[1])] for b, x in zip(blocks, rvec)}
+    # blocks of rank 6 (4h2p, 4p2h) stay lazy: dense they would take gigabytes
+    rb = {b: (LazyAntisym(x, o, v, *b) if b[0] + b[1] == 6 else LazyAntisym(x, o, v, *b)[(slice(None),) * (b[0] + b[1])])
+          for b, x in zip(blocks, rvec)}
     offs = np.cumsum([0] + [x.size for x in rvec])
     big = blocks[2]
     S3 = LazyAntisym(sig[offs[2]:offs[3]], o, v, *big)
@@ -129,7 +154,8 @@ def test_full_size_sampled_sigma(P, kind):
     for idx in picks:
         ref = cc.eom_sigma_element(tr["fock"], tr["eri"], o, amps, kind, rb, big, idx)
         assert abs(S3[idx] - ref) < 1e-10 * max(1.0, abs(ref)), idx
-    S1 = LazyAntisym(sig[offs[0]:offs[1]], o, v, *blocks[0])
-    idx1 = tuple([1] * 0 + list(range(blocks[0][0]))) + tuple(range(blocks[0][1]))
-    ref1 = cc.eom_sigma_element(tr["fock"], tr["eri"], o, amps, kind, rb, blocks[0], idx1)
-    assert abs(S1[idx1] - ref1) < 1e-10 * max(1.0, abs(ref1))
+    for b in (0, 1):
+        Sb = LazyAntisym(sig[offs[b]:offs[b + 1]], o, v, *blocks[b])
+        idxb = tuple(range(1, 1 + blocks[b][0])) + tuple(range(3, 3 + 2 * blocks[b][1], 2))
+        refb = cc.eom_sigma_element(tr["fock"], tr["eri"], o, amps, kind, rb, blocks[b], idxb)
+        assert abs(Sb[idxb] - refb) < 1e-10 * max(1.0, abs(refb)), (blocks[b], idxb)
