@@ -181,6 +181,24 @@ int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops)
  */
 int fno_profile(fno_ctx *ctx, int on);
 int fno_profile_report(fno_ctx *ctx, char *buf, size_t len);
+/*
+ * Restrict timing to the kernels whose name contains `substr` (NULL or "" =
+ * all kernels).  With a filter set, the residual sweep can still be replayed
+ * from hipGraphs: the selected kernels run between graph segments, each
+ * bracketed by its own events.  FNO_EINVAL on a null context.
+ */
+int fno_profile_filter(fno_ctx *ctx, const char *substr);
+
+/*
+ * Launch mode of the CCSDT residual sweep (the loop of fno_ccsdt, and the
+ * ground-state intermediates of fno_eom / fno_eom_sigma / fno_cc_residual).
+ * on = 1 (default): once a sweep has run without allocating device memory, the
+ * next one is recorded into hipGraphs on the context's stream and later sweeps
+ * replay it; any new allocation in the context discards the recording.
+ * on = 0: every launch is issued from the host.  Results are identical in both
+ * modes (same kernels, same order).
+ */
+int fno_set_graphs(fno_ctx *ctx, int on);
 
 size_t fno_debug_tensor_size(fno_ctx *ctx, const char *name);
 int fno_debug_tensor(fno_ctx *ctx, const char *name, double *buf, size_t len);

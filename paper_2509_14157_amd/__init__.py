@@ -22,7 +22,8 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
+           "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_profile_filter",
+           "fno_set_graphs", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
 
 
 class FnoError(RuntimeError):
@@ -78,6 +79,8 @@ def library() -> C.CDLL:
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
         lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
+        lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
+        lib.fno_set_graphs.argtypes = [C.c_void_p, C.c_int]
         lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_debug_tensor_size.restype = C.c_size_t
         lib.fno_debug_tensor.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_size_t]
@@ -191,8 +194,14 @@ class Context:
         return t.value, a.value
 
     # ---- profiling
-    def profile(self, on: bool = True) -> None:
+    def profile(self, on: bool = True, only: str | None = None) -> None:
+        """Time kernels with HIP events; `only` restricts it to names containing that text."""
+        self._check(self._lib.fno_profile_filter(self._h, (only or "").encode()))
         self._check(self._lib.fno_profile(self._h, int(bool(on))))
+
+    def set_graphs(self, on: bool = True) -> None:
+        """Replay the residual sweep from recorded hipGraphs (default) or launch eagerly."""
+        self._check(self._lib.fno_set_graphs(self._h, int(bool(on))))
 
     def profile_report(self) -> dict:
         import json

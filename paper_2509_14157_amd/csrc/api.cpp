@@ -70,7 +70,7 @@ const char* fno_last_error(const fno_ctx* ctx) { return ctx ? ctx->err.c_str() :
 
 int fno_set_stream(fno_ctx* ctx, void* s) {
   return guard(ctx, [&](fno::Context& c) {
-    c.eng->stream = (hipStream_t)s;
+    c.set_stream((hipStream_t)s);
     return FNO_OK;
   });
 }
@@ -229,6 +229,20 @@ int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops)
 int fno_profile(fno_ctx* ctx, int on) {
   return guard(ctx, [&](fno::Context& c) {
     c.eng->profile = on != 0;
+    return FNO_OK;
+  });
+}
+
+int fno_profile_filter(fno_ctx* ctx, const char* substr) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.eng->profile_filter = substr ? std::string(substr) : std::string();
+    return FNO_OK;
+  });
+}
+
+int fno_set_graphs(fno_ctx* ctx, int on) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.use_graphs = on != 0;
     return FNO_OK;
   });
 }

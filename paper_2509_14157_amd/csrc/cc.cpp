@@ -96,7 +96,6 @@ void Context::setup_cc() {
   e.set_sym(G, {{0, 1}, {2, 3}});
   Tensor* Gd = e.create("Gd", "n,n,n,n", sz_);
   e.set_sym(Gd, {{0, 1}, {2, 3}});
-  e.create("Gtmp", "n,n,n,n", sz_);
   for (const char* nm : {"Fd", "Xt", "Yt", "Ftmp", "Ident"}) e.create(nm, "n,n", sz_);
   e.create("Iocc", "o,o", sz_);
   {
@@ -149,14 +148,17 @@ void Context::dress() {
   launch_axpby(e.get("Yt")->d, e.get("Ident")->d, 1.0, 0.0, nn, e.stream);
   e.term("Xt_vo[am] -= 1 * T1[ma]");
   e.term("Yt_vo[am] += 1 * T1[ma]");
-  e.zero(e.get("Gtmp"));
-  e.term("Gtmp[qrsP] += 1 * G[pqrs] * Xt[Pp]");
-  e.zero(e.get("Gd"));
-  e.term("Gd[rsPQ] += 1 * Gtmp[qrsP] * Xt[Qq]");
-  e.zero(e.get("Gtmp"));
-  e.term("Gtmp[sPQR] += 1 * Gd[rsPQ] * Yt[rR]");
-  e.zero(e.get("Gd"));
-  e.term("Gd[PQRS] += 1 * Gtmp[sPQR] * Yt[sS]");
+  // g^[PQRS] = sum X[P,p] X[Q,q] g[pqrs] Y[r,R] Y[s,S]: X and Y differ from
+  // the identity only in their virtual-occupied block, so each slot is an
+  // in-place update of one slice (K = o for X, K = v for Y)
+  Tensor* gd = e.get("Gd");
+  Tensor* g0 = e.get("G");
+  FNO_HIP(hipMemcpyAsync(gd->d, g0->d, (size_t)g0->elems * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+  const double* t1 = e.get("T1")->d;
+  launch_dress_pass(gd->d, t1, nocc, nvir, 0, true, e.stream);
+  launch_dress_pass(gd->d, t1, nocc, nvir, 1, true, e.stream);
+  launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
+  launch_dress_pass(gd->d, t1, nocc, nvir, 3, false, e.stream);
   // f^ = X h Y + sum_i g^[p i q i]
   e.zero(e.get("Ftmp"));
   e.zero(e.get("Fd"));
@@ -179,9 +181,54 @@ double Context::energy() {
   return r;
 }
 
+// The residual sweep is the same sequence of launches every iteration: once
+// an eager sweep has run without allocating anything, the next one is
+// recorded into hipGraph segments and later sweeps replay them (host launch
+// overhead removed).  Any allocation in the engine invalidates the recording.
 void Context::residual() {
   Engine& e = *eng;
   const Prec tri = e.prec;  // precision of the triples-residual contractions
+  auto matches = [&]() {
+    return cc_prog_.valid() && cc_prog_.epoch == e.epoch && cc_prog_.prec == (int)tri &&
+           cc_prog_.profiled == e.profile && cc_prog_.filter == e.profile_filter;
+  };
+  if (use_graphs && matches()) {
+    e.replay(cc_prog_);
+    e.prec = tri;
+    return;
+  }
+  cc_prog_.clear();
+  if (use_graphs && cc_stable_ && cc_stable_epoch_ == e.epoch && cc_stable_prec_ == (int)tri &&
+      cc_stable_profiled_ == e.profile && cc_stable_filter_ == e.profile_filter) {
+    bool recorded = false;
+    e.begin_record(cc_prog_);
+    try {
+      residual_body(tri);
+      e.end_record(cc_prog_);
+      recorded = true;
+    } catch (const Error&) {
+      // something in the sweep cannot be recorded (it needed memory or a
+      // host synchronization): discard the capture and launch from the host
+      e.abort_record();
+      e.prec = tri;
+      cc_stable_ = false;
+    }
+    if (recorded && cc_prog_.valid()) {
+      e.replay(cc_prog_);
+      return;
+    }
+  }
+  const uint64_t before = e.epoch;
+  residual_body(tri);
+  cc_stable_ = e.epoch == before;
+  cc_stable_epoch_ = e.epoch;
+  cc_stable_prec_ = (int)tri;
+  cc_stable_profiled_ = e.profile;
+  cc_stable_filter_ = e.profile_filter;
+}
+
+void Context::residual_body(Prec tri) {
+  Engine& e = *eng;
   e.prec = Prec::FP64;
   launch_fill(res_, 0.0, nt_, e.stream);
   for (const char* nm : {"F2_vv", "F2_oo", "W2_oooo", "W2_vvvv", "W2_ovvo", "F3_vv", "F3_oo", "W3_oooo", "W3_vvvv",
@@ -190,15 +237,24 @@ void Context::residual() {
   dress();
   e.stats.clear();
   e.record = true;
-  // dressing, intermediates and the singles/doubles residual are FP64; the
-  // triples residual contractions (ladders, ring, one-body, drivers) run in
-  // the requested precision and accumulate into the FP64 residual
-  e.terms(kCCInter2, count(kCCInter2));
-  e.terms(kCCR1, count(kCCR1));
-  e.terms(kCCR2, count(kCCR2));
-  e.terms(kCCInter3, count(kCCInter3));
-  e.prec = tri;
-  e.terms(kCCR3, count(kCCR3));
+  {
+    // the amplitudes are fixed during the sweep: their expanded operand
+    // matrices are shared between terms (the ring, R1 and the F_ov term of R2
+    // use one layout of T3; the T3 pieces of W3_vvvo/W3_ovoo and the G terms
+    // of R2 another).  The triples terms run first so that the largest GEMM
+    // (the ring) fixes the stored orientation.
+    CacheScope cache(e, {"T1", "T2", "T3"});
+    // dressing, intermediates and the singles/doubles residual are FP64; the
+    // triples residual contractions (ladders, ring, one-body, drivers) run in
+    // the requested precision and accumulate into the FP64 residual
+    e.terms(kCCInter2, count(kCCInter2));
+    e.terms(kCCInter3, count(kCCInter3));
+    e.prec = tri;
+    e.terms(kCCR3, count(kCCR3));
+    e.prec = Prec::FP64;
+    e.terms(kCCR1, count(kCCR1));
+    e.terms(kCCR2, count(kCCR2));
+  }
   e.prec = tri;
   e.record = false;
   tally_flops();
@@ -269,15 +325,12 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   double rnorm = INFINITY, de = 0;
   int it = 0, status = kENOCONV;
   e.prec = opt.prec;
+  double* dres = alloc(2 + 16);  // |r|^2, then the overlaps of the new error vector
+  const int mm = std::max(m, 1);
   for (it = 1; it <= opt.max_iter; ++it) {
     residual();
-    rnorm = std::sqrt(dot(res_, res_, nt_));
-    if (!std::isfinite(rnorm)) {
-      e.prec = Prec::FP64;
-      throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
-    }
     int slot;
-    if ((int)order.size() < std::max(m, 1)) {
+    if ((int)order.size() < mm) {
       slot = (int)order.size();
     } else {
       slot = order.front();
@@ -286,9 +339,20 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     order.push_back(slot);
     launch_axpby(ht[slot], amp_, 1.0, 0.0, nt_, e.stream);
     launch_jacobi(ht[slot], res_, den_, he[slot], nt_, e.stream);
+    // |r|^2 and every overlap <e_slot|e_s> in two launches and one transfer
+    launch_dots(res_, nt_, 1, res_, nt_, scratch_, dres, e.stream);
+    if (m > 0) launch_dots(he[0], nt_, (int)order.size() > 0 ? mm : 0, he[slot], nt_, scratch_, dres + 2, e.stream);
+    double hv[2 + 16];
+    FNO_HIP(hipMemcpyAsync(hv, dres, (2 + (m > 0 ? mm : 0)) * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    rnorm = std::sqrt(hv[0]);
+    if (!std::isfinite(rnorm)) {
+      e.prec = Prec::FP64;
+      throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
+    }
     bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
     if (m > 0) {
-      for (int s : order) B[slot * 16 + s] = B[s * 16 + slot] = dot(he[slot], he[s], nt_);
+      for (int s : order) B[slot * 16 + s] = B[s * 16 + slot] = hv[2 + s];
     }
     if (extrap) {
       const int k = (int)order.size();
@@ -306,7 +370,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
         for (int a = 0; a < k; ++a) c[order[a]] = rhs[a];
         FNO_HIP(hipMemcpyAsync(dcoef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
         launch_combine(amp_, ht[0], nt_, dcoef, (int)c.size(), 1.0, 0.0, nt_, e.stream);
-        FNO_HIP(hipStreamSynchronize(e.stream));
+        FNO_HIP(hipStreamSynchronize(e.stream));  // c is a host temporary
       } else {
         launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
       }
@@ -326,8 +390,10 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   FNO_HIP(hipStreamSynchronize(e.stream));
   owned_.erase(std::remove(owned_.begin(), owned_.end(), hist), owned_.end());
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dcoef), owned_.end());
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), dres), owned_.end());
   FNO_HIP(hipFree(hist));
   FNO_HIP(hipFree(dcoef));
+  FNO_HIP(hipFree(dres));
   e_corr = e_old;
   cc_done = true;
   if (ec) *ec = e_old;

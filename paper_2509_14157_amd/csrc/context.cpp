@@ -22,6 +22,22 @@ Context::Context(int dev) : device(dev) {
   eng = std::make_unique<Engine>(dev);
 }
 
+void Context::set_stream(hipStream_t s) {
+  FNO_HIP(hipDeviceSynchronize());
+  user_stream = s;
+  eng->stream = s ? s : eng->own_stream();
+  cc_prog_.clear();
+}
+
+void Context::reset_engine(std::unique_ptr<Engine> e) {
+  FNO_HIP(hipDeviceSynchronize());
+  cc_prog_.clear();  // recorded launches point into the old engine
+  cc_stable_ = false;
+  eom_.reset();
+  eng = std::move(e);
+  if (user_stream) eng->stream = user_stream;
+}
+
 Context::~Context() {
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
@@ -63,7 +79,7 @@ void Context::load(int o, int v, const double* f, const double* g, double en) {
         }
   // reset any previous problem
   if (loaded) {
-    eng = std::make_unique<Engine>(device);
+    reset_engine(std::make_unique<Engine>(device));
     for (double* p : owned_) (void)hipFree(p);
     owned_.clear();
     eom_.reset();
@@ -230,7 +246,7 @@ void Context::truncate(double occt, int keep, int* kept, double* emp2, double* o
     for (double* p : owned_) (void)hipFree(p);
     owned_.clear();
     eom_.reset();
-    eng = std::move(ge);
+    reset_engine(std::move(ge));
     cc_ready = cc_done = false;
   }
   Engine& E = *eng;

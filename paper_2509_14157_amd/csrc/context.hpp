@@ -66,6 +66,12 @@ class Context {
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
 
   double last_triples_flops = 0, last_all_flops = 0;
+
+  // launch mode: replay the residual sweep from a recorded hipGraph program
+  bool use_graphs = true;
+  hipStream_t user_stream = nullptr;  // caller's stream (fno_set_stream), kept across engine rebuilds
+  void set_stream(hipStream_t s);
+  void reset_engine(std::unique_ptr<Engine> e);
   struct EomSpace;  // per-variant layout and tensors (eom_space.hpp)
   int debug_gemm(Prec p, int tile, int64_t M, int64_t N, int64_t K, bool a_kfast, bool b_nfast, double alpha,
                  double beta, const double* A, const double* B, double* Cm);
@@ -76,6 +82,14 @@ class Context {
   void dress();
   double energy();
   void residual();
+  void residual_body(Prec tri);
+  Program cc_prog_;              // recorded residual sweep
+  // the last host-launched sweep allocated nothing; the settings it ran with
+  bool cc_stable_ = false;
+  uint64_t cc_stable_epoch_ = 0;
+  int cc_stable_prec_ = -1;
+  bool cc_stable_profiled_ = false;
+  std::string cc_stable_filter_;
   void tally_flops();
   double dot(const double* x, const double* y, int64_t n);
 

@@ -1,6 +1,9 @@
 // Contraction planner and executor (host side).
 #include "engine.hpp"
 
+#include <array>
+#include <cstdio>
+
 #include <algorithm>
 #include <cctype>
 #include <cstring>
@@ -29,6 +32,8 @@ static void colex_tuples(int n, int g, std::vector<uint8_t>& out) {
 
 Engine::Engine(int dev) : device(dev) {
   FNO_HIP(hipSetDevice(device));
+  FNO_HIP(hipStreamCreate(&own_stream_));
+  stream = own_stream_;
   std::vector<uint32_t> b(kBinomN * (kMaxGroup + 1));
   for (int n = 0; n < kBinomN; ++n)
     for (int k = 0; k <= kMaxGroup; ++k) b[n * (kMaxGroup + 1) + k] = (uint32_t)binom_host(n, k);
@@ -61,13 +66,91 @@ Engine::~Engine() {
   for (int i = 0; i < 6; ++i)
     if (ws_[i]) (void)hipFree(ws_[i]);
   for (auto ev : evpool_) (void)hipEventDestroy(ev);
+  for (auto& kv : ecache_) {
+    if (kv.second.hi) (void)hipFree(kv.second.hi);
+    if (kv.second.lo) (void)hipFree(kv.second.lo);
+  }
   if (d_binom_) (void)hipFree(d_binom_);
   for (int g = 0; g <= kMaxGroup; ++g)
     if (d_dec_[g]) (void)hipFree(d_dec_[g]);
+  if (own_stream_) (void)hipStreamDestroy(own_stream_);
+}
+
+// ------------------------------------------------------------------ recording
+void Engine::begin_record(Program& prog) {
+  FNO_REQUIRE(rec_ == nullptr, kEINVAL, "nested recording");
+  FNO_REQUIRE(stream != nullptr, kEINVAL, "recording needs a non-null stream");
+  prog.clear();
+  prog.epoch = epoch;
+  prog.prec = (int)prec;
+  prog.profiled = profile;
+  prog.filter = profile_filter;
+  rec_ = &prog;
+  FNO_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+}
+
+// close the current graph segment, insert `run`, open the next segment
+void Engine::split_record(std::function<void()> run) {
+  hipGraph_t g = nullptr;
+  FNO_HIP(hipStreamEndCapture(stream, &g));
+  size_t nodes = 0;
+  FNO_HIP(hipGraphGetNodes(g, nullptr, &nodes));
+  if (nodes > 0) {
+    Program::Item it;
+    FNO_HIP(hipGraphInstantiate(&it.exec, g, nullptr, nullptr, 0));
+    rec_->items.push_back(std::move(it));
+  }
+  FNO_HIP(hipGraphDestroy(g));
+  if (run) {
+    Program::Item it;
+    it.run = std::move(run);
+    rec_->items.push_back(std::move(it));
+  }
+  FNO_HIP(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+}
+
+void Engine::end_record(Program& prog) {
+  FNO_REQUIRE(rec_ == &prog, kEINVAL, "not recording this program");
+  hipGraph_t g = nullptr;
+  hipError_t err = hipStreamEndCapture(stream, &g);
+  rec_ = nullptr;
+  FNO_HIP(err);
+  size_t nodes = 0;
+  FNO_HIP(hipGraphGetNodes(g, nullptr, &nodes));
+  if (nodes > 0) {
+    Program::Item it;
+    FNO_HIP(hipGraphInstantiate(&it.exec, g, nullptr, nullptr, 0));
+    prog.items.push_back(std::move(it));
+  }
+  FNO_HIP(hipGraphDestroy(g));
+  // a recording is only valid if nothing was (re)allocated while it ran
+  if (prog.epoch != epoch) prog.clear();
+}
+
+void Engine::abort_record() {
+  if (!rec_) return;
+  Program* prog = rec_;
+  rec_ = nullptr;
+  hipGraph_t g = nullptr;
+  (void)hipStreamEndCapture(stream, &g);
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  prog->clear();
+}
+
+void Engine::replay(const Program& prog) {
+  for (auto& it : prog.items) {
+    if (it.exec)
+      FNO_HIP(hipGraphLaunch(it.exec, stream));
+    else
+      it.run();
+  }
 }
 
 void* Engine::workspace(int slot, size_t bytes) {
   if (bytes > ws_bytes_[slot]) {
+    FNO_REQUIRE(!rec_, kEINVAL, "workspace growth while recording");
+    ++epoch;
     if (ws_[slot]) {
       FNO_HIP(hipStreamSynchronize(stream));
       FNO_HIP(hipFree(ws_[slot]));
@@ -165,6 +248,8 @@ int64_t Engine::spec_size(const std::string& spec, const SpaceSizes& sz) {
 }
 
 Tensor* Engine::create(const std::string& name, const std::string& spec, const SpaceSizes& sz, double* external) {
+  FNO_REQUIRE(!rec_, kEINVAL, "tensor creation while recording");
+  ++epoch;
   FNO_REQUIRE(!reg_.count(name), kEINVAL, "tensor exists: " + name);
   auto t = std::make_unique<Tensor>();
   t->name = name;
@@ -277,6 +362,8 @@ void Engine::set_sym(Tensor* t, const std::vector<std::vector<int>>& sym) {
 }
 
 void Engine::drop(const std::string& name) {
+  FNO_REQUIRE(!rec_, kEINVAL, "tensor release while recording");
+  ++epoch;
   auto it = reg_.find(name);
   if (it == reg_.end()) return;
   if (it->second->owner && it->second->d) {
@@ -284,6 +371,15 @@ void Engine::drop(const std::string& name) {
     FNO_HIP(hipFree(it->second->d));
   }
   reg_.erase(it);
+  for (auto cit = ecache_.begin(); cit != ecache_.end();)
+    if (cit->second.tensor == name) {
+      FNO_HIP(hipStreamSynchronize(stream));
+      if (cit->second.hi) FNO_HIP(hipFree(cit->second.hi));
+      if (cit->second.lo) FNO_HIP(hipFree(cit->second.lo));
+      cit = ecache_.erase(cit);
+    } else {
+      ++cit;
+    }
   for (auto pit = plans_.begin(); pit != plans_.end();)
     if (pit->first.find(name) != std::string::npos)
       pit = plans_.erase(pit);
@@ -314,6 +410,12 @@ struct Engine::Plan {
   FoldCombos fc{};
   double flops = 0;
   Prec prec = Prec::FP64;
+  // expansion-cache keys of A (M x K) and B (K x N), and the parity of this
+  // term's slot arrangement relative to the key's canonical one (direct and
+  // transposed use)
+  bool a_cache = false, b_cache = false;
+  std::string a_key, a_keyT, b_key, b_keyT;
+  int a_sign = 1, a_signT = 1, b_sign = 1, b_signT = 1;
   // table-driven expansion / fold (device tables owned by the plan)
   bool a_tab_ok = false, b_tab_ok = false, f_tab_ok = false;
   ExpandTab a_tab{}, b_tab{};
@@ -534,6 +636,81 @@ int perm_sign(const std::vector<int>& p) {
   return s;
 }
 
+// Canonical description of the matrix a packed operand expands into: for each
+// row group and each column group, the storage group it is cut from and its
+// size.  Two expansions with the same description hold the same values up to
+// the parity of where their letters sit inside the antisymmetric storage
+// groups; `sign` is that parity relative to the order (rows first, then
+// columns, each by group and position), `signT` relative to (columns first).
+struct CanonKey {
+  bool ok = false;
+  std::string key, keyT;
+  int sign = 1, signT = 1;
+};
+
+CanonKey canon_key(const Tensor* t, const std::vector<int>& ids, const MatDim& rows, const MatDim& cols, Prec prec) {
+  CanonKey ck;
+  std::vector<std::vector<int>> st;
+  int s = 0;
+  for (auto& g : t->groups) {
+    std::vector<int> v;
+    for (int k = 0; k < g.g; ++k) v.push_back(s++);
+    st.push_back(v);
+  }
+  if (t->sym != st) return ck;  // only packed antisymmetric tensors
+  const int ns = s;
+  std::vector<int> grp_of(ns);
+  for (size_t q = 0; q < st.size(); ++q)
+    for (int x : st[q]) grp_of[x] = (int)q;
+  std::vector<std::array<int, 3>> where(ns, {-1, -1, -1});
+  const MatDim* side[2] = {&rows, &cols};
+  std::string desc[2];
+  for (int sd = 0; sd < 2; ++sd)
+    for (int q = 0; q < side[sd]->ngroups; ++q) {
+      const DimGroup& G = side[sd]->grp[q];
+      int src = -1;
+      for (int k = 0; k < G.g; ++k) {
+        int slot = -1;
+        for (int x = 0; x < ns; ++x)
+          if (ids[x] == G.letter[k]) slot = x;
+        if (slot < 0) return ck;
+        if (src < 0) src = grp_of[slot];
+        if (grp_of[slot] != src) return ck;
+        where[slot] = {sd, q, k};
+      }
+      desc[sd] += "(" + std::to_string(src) + "," + std::to_string(G.g) + ")";
+    }
+  for (auto& w : where)
+    if (w[0] < 0) return ck;
+  auto parity = [&](bool trans) {
+    int sg = 1;
+    for (auto& gslots : st) {
+      std::vector<int> ord = gslots;
+      std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+        std::array<int, 3> wa = where[a], wb = where[b];
+        if (trans) {
+          wa[0] = 1 - wa[0];
+          wb[0] = 1 - wb[0];
+        }
+        return wa < wb;
+      });
+      std::vector<int> pos(ord.size());
+      for (size_t i = 0; i < ord.size(); ++i) pos[i] = ord[i] - gslots[0];
+      sg *= perm_sign(pos);
+    }
+    return sg;
+  };
+  char ptr[32];
+  std::snprintf(ptr, sizeof(ptr), "%p", (const void*)t->d);
+  const std::string head = t->name + "@" + ptr + "#" + std::to_string((int)prec) + "|";
+  ck.key = head + desc[0] + "|" + desc[1];
+  ck.keyT = head + desc[1] + "|" + desc[0];
+  ck.sign = parity(false);
+  ck.signT = parity(true);
+  ck.ok = true;
+  return ck;
+}
+
 }  // namespace
 
 std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
@@ -542,6 +719,8 @@ std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
   auto it = plans_.find(key);
   if (it != plans_.end()) return it->second;
   Parsed ps = parse(spec);
+  FNO_REQUIRE(!rec_, kEINVAL, "new contraction plan while recording");
+  ++epoch;
   auto P = std::make_shared<Plan>();
   P->spec = spec;
   P->out = get(ps.out);
@@ -778,6 +957,22 @@ std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
     P->b_nfast = true;
     P->ldb = P->N.size;
   }
+  if (P->B && !P->a_direct) {
+    CanonKey k = canon_key(P->A, ia, P->M, P->K, prec);
+    P->a_cache = k.ok;
+    P->a_key = k.key;
+    P->a_keyT = k.keyT;
+    P->a_sign = k.sign;
+    P->a_signT = k.signT;
+  }
+  if (P->B && !P->b_direct) {
+    CanonKey k = canon_key(P->B, ib, P->K, P->N, prec);
+    P->b_cache = k.ok;
+    P->b_key = k.key;
+    P->b_keyT = k.keyT;
+    P->b_sign = k.sign;
+    P->b_signT = k.signT;
+  }
   // table-driven expansion and fold
   if (!P->a_direct) P->a_tab_ok = build_expand_tab(tables, P->ad, ga_st, P->M, P->K, P->a_tab, P->bufs, stream);
   if (P->B && !P->b_direct)
@@ -849,7 +1044,8 @@ void Engine::execute(const Plan& p, double scale) {
     // single operand: fold A (gathered as an M x 1 FP64 matrix) into the output
     FNO_REQUIRE(Ksz == 1, kEINVAL, "single-operand term with summation: " + p.spec);
     const void* X = p.A->d + p.A->base;
-    hipEvent_t e0 = profile ? event() : nullptr;
+    const bool tm = timed(p.f_tab_ok ? "fno::copy (expand_tab + fold_tab)" : "fno::copy (expand + fold)") && !rec_;
+    hipEvent_t e0 = tm ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
     if (!p.a_direct) {
       void* a = workspace(0, (size_t)Msz * 8);
@@ -871,47 +1067,93 @@ void Engine::execute(const Plan& p, double scale) {
     }
     return;
   }
-  if (p.a_direct) {
-    A = p.A->d + p.A->base;
-  } else {
-    void* a = workspace(0, (size_t)(Msz * Ksz) * esz);
-    void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
-    hipEvent_t e0 = profile ? event() : nullptr;
+  // operand matrices: the tensor itself, a cached expansion (direct or
+  // transposed), or a fresh expansion into the cache or a workspace
+  double factor = 1.0;
+  bool a_kfast = p.a_kfast, b_nfast = p.b_nfast;
+  int64_t lda = p.lda, ldb = p.ldb;
+  auto expand_into = [&](const Tensor* t, bool tab_ok, const ExpandTab& tab, const OperandDesc& od, const MatDim& r,
+                         const MatDim& c, void* hi, void* lo) {
+    const bool tm = timed(tab_ok ? "fno::expand_tab" : "fno::expand_kernel") && !rec_;
+    hipEvent_t e0 = tm ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    if (p.a_tab_ok)
-      launch_expand_tab(p.a_tab, p.A->d, a, alo, prec, stream);
+    if (tab_ok)
+      launch_expand_tab(tab, t->d, hi, lo, prec, stream);
     else
-      launch_expand(tables, p.ad, p.M, p.K, p.A->d, a, alo, prec, true, stream);
+      launch_expand(tables, od, r, c, t->d, hi, lo, prec, true, stream);
     if (e0) {
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
-      prof_mark(p.a_tab_ok ? "fno::expand_tab" : "fno::expand_kernel", p.spec, 0,
-                (double)(Msz * Ksz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
+      prof_mark(tab_ok ? "fno::expand_tab" : "fno::expand_kernel", p.spec, 0,
+                (double)(r.size * c.size) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
     }
+  };
+  // returns true when the operand was served from (or expanded into) the cache
+  auto cached = [&](const Tensor* t, bool ok, const std::string& key, const std::string& keyT, int sgn, int sgnT,
+                    int64_t rows, int64_t cols, bool tab_ok, const ExpandTab& tab, const OperandDesc& od,
+                    const MatDim& r, const MatDim& c, const void*& hi, const void*& lo, bool& fast, int64_t& ld) {
+    if (!ok || !is_cacheable(t->name)) return false;
+    auto it = ecache_.find(key);
+    if (it != ecache_.end() && it->second.valid) {
+      hi = it->second.hi;
+      lo = it->second.lo;
+      fast = true;
+      ld = cols;
+      factor *= sgn * it->second.sign;
+      return true;
+    }
+    it = ecache_.find(keyT);
+    if (it != ecache_.end() && it->second.valid) {
+      hi = it->second.hi;
+      lo = it->second.lo;
+      fast = false;
+      ld = rows;
+      factor *= sgnT * it->second.sign;
+      return true;
+    }
+    CacheEntry& ce = ecache_[key];
+    const size_t need = (size_t)(rows * cols) * esz;
+    if (ce.bytes < need) {
+      FNO_REQUIRE(!rec_, kEINVAL, "expansion cache growth while recording");
+      ++epoch;
+      FNO_HIP(hipStreamSynchronize(stream));
+      if (ce.hi) FNO_HIP(hipFree(ce.hi));
+      if (ce.lo) FNO_HIP(hipFree(ce.lo));
+      ce.hi = ce.lo = nullptr;
+      ce.bytes = 0;
+      FNO_HIP(hipMalloc(&ce.hi, std::max<size_t>(need, 256)));
+      if (prec == Prec::BF16X3) FNO_HIP(hipMalloc(&ce.lo, std::max<size_t>(need, 256)));
+      ce.bytes = need;
+    }
+    ce.tensor = t->name;
+    expand_into(t, tab_ok, tab, od, r, c, ce.hi, ce.lo);
+    ce.sign = sgn;
+    ce.valid = true;
+    hi = ce.hi;
+    lo = ce.lo;
+    fast = true;
+    ld = cols;
+    return true;
+  };
+  if (p.a_direct) {
+    A = p.A->d + p.A->base;
+  } else if (!cached(p.A, p.a_cache, p.a_key, p.a_keyT, p.a_sign, p.a_signT, Msz, Ksz, p.a_tab_ok, p.a_tab, p.ad,
+                     p.M, p.K, A, Alo, a_kfast, lda)) {
+    void* a = workspace(0, (size_t)(Msz * Ksz) * esz);
+    void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
+    expand_into(p.A, p.a_tab_ok, p.a_tab, p.ad, p.M, p.K, a, alo);
     A = a;
     Alo = alo;
   }
-  if (p.B) {
-    if (p.b_direct) {
-      B = p.B->d + p.B->base;
-    } else {
-      void* b = workspace(1, (size_t)(Ksz * Nsz) * esz);
-      void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
-      hipEvent_t e0 = profile ? event() : nullptr;
-      if (e0) FNO_HIP(hipEventRecord(e0, stream));
-      if (p.b_tab_ok)
-        launch_expand_tab(p.b_tab, p.B->d, b, blo, prec, stream);
-      else
-        launch_expand(tables, p.bd, p.K, p.N, p.B->d, b, blo, prec, true, stream);
-      if (e0) {
-        hipEvent_t e1 = event();
-        FNO_HIP(hipEventRecord(e1, stream));
-        prof_mark(p.b_tab_ok ? "fno::expand_tab" : "fno::expand_kernel", p.spec, 0,
-                  (double)(Ksz * Nsz) * (double)(esz * (prec == Prec::BF16X3 ? 2 : 1)), e0, e1);
-      }
-      B = b;
-      Blo = blo;
-    }
+  if (p.b_direct) {
+    B = p.B->d + p.B->base;
+  } else if (!cached(p.B, p.b_cache, p.b_key, p.b_keyT, p.b_sign, p.b_signT, Ksz, Nsz, p.b_tab_ok, p.b_tab, p.bd,
+                     p.K, p.N, B, Blo, b_nfast, ldb)) {
+    void* b = workspace(1, (size_t)(Ksz * Nsz) * esz);
+    void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
+    expand_into(p.B, p.b_tab_ok, p.b_tab, p.bd, p.K, p.N, b, blo);
+    B = b;
+    Blo = blo;
   }
   if (prec == Prec::BF16X3)
     FNO_REQUIRE(Alo != nullptr && Blo != nullptr, kEINVAL, "split-BF16 GEMM needs expanded operands: " + p.spec);
@@ -922,31 +1164,40 @@ void Engine::execute(const Plan& p, double scale) {
   g.K = Ksz;
   g.A = A;
   g.A_lo = Alo;
-  g.lda = p.lda;
-  g.a_kfast = p.a_kfast;
+  g.lda = lda;
+  g.a_kfast = a_kfast;
   g.B = B;
   g.B_lo = Blo;
-  g.ldb = p.ldb;
-  g.b_nfast = p.b_nfast;
+  g.ldb = ldb;
+  g.b_nfast = b_nfast;
   g.tile = -1;
   auto timed_gemm = [&]() {
     g.split = gemm_split_factor(g);
     if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
-    hipEvent_t e0 = profile ? event() : nullptr;
-    if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    launch_gemm(g, stream);
-    if (e0) {
+    const std::string label = gemm_label(g);
+    const double b = (double)esz * (double)(Msz * Ksz + Ksz * Nsz) * (prec == Prec::BF16X3 ? 2 : 1) +
+                     (prec == Prec::FP64 ? 8.0 : 4.0) * (double)(Msz * Nsz);
+    if (!timed(label)) {
+      launch_gemm(g, stream);
+      return;
+    }
+    auto run = [this, g, label, spec = p.spec, flops = p.flops, b]() {
+      hipEvent_t e0 = event();
+      FNO_HIP(hipEventRecord(e0, stream));
+      launch_gemm(g, stream);
       hipEvent_t e1 = event();
       FNO_HIP(hipEventRecord(e1, stream));
-      const double b = (double)esz * (double)(Msz * Ksz + Ksz * Nsz) * (prec == Prec::BF16X3 ? 2 : 1) +
-                       (prec == Prec::FP64 ? 8.0 : 4.0) * (double)(Msz * Nsz);
-      prof_mark(gemm_label(g), p.spec, p.flops, b, e0, e1);
-    }
+      prof_mark(label, spec, flops, b, e0, e1);
+    };
+    if (rec_)
+      split_record(run);  // kept out of the graph segments, timed on every replay
+    else
+      run();
   };
   if (p.x_direct) {
     g.C = p.out->d;
     g.ldc = Nsz;
-    g.alpha = p.alpha * scale;
+    g.alpha = p.alpha * scale * factor;
     g.beta = 1.0;
     timed_gemm();
   } else {
@@ -954,10 +1205,11 @@ void Engine::execute(const Plan& p, double scale) {
     void* X = workspace(2, (size_t)(Msz * Nsz) * xsz);
     g.C = X;
     g.ldc = Nsz;
-    g.alpha = 1.0;
+    g.alpha = factor;
     g.beta = 0.0;
     timed_gemm();
-    hipEvent_t e0 = profile ? event() : nullptr;
+    const bool tm = timed(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel") && !rec_;
+    hipEvent_t e0 = tm ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
     if (p.f_tab_ok)
       launch_fold_tab(p.f_tab, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d, p.alpha * scale,
@@ -973,6 +1225,17 @@ void Engine::execute(const Plan& p, double scale) {
     }
   }
   if (record) stats.push_back({p.spec, Msz, Nsz, Ksz, p.flops});
+}
+
+void Engine::cache_operands(const std::vector<std::string>& names) {
+  for (auto& kv : ecache_) kv.second.valid = false;
+  cacheable_ = names;
+}
+
+size_t Engine::cache_bytes() const {
+  size_t b = 0;
+  for (auto& kv : ecache_) b += kv.second.bytes * (kv.second.lo ? 2 : 1);
+  return b;
 }
 
 void Engine::term(const std::string& spec, double scale) {

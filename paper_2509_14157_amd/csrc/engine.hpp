@@ -13,6 +13,8 @@
 // operand are produced as ordered tuples only.
 #pragma once
 
+#include <algorithm>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -80,6 +82,27 @@ struct GemmStats {
   double flops = 0;
 };
 
+// A recorded sequence of launches: graph segments, and between them the
+// kernels kept out of the graphs so that they can be timed with events.
+struct Program {
+  struct Item {
+    hipGraphExec_t exec = nullptr;
+    std::function<void()> run;
+  };
+  std::vector<Item> items;
+  uint64_t epoch = 0;  // engine epoch the recording is valid for
+  int prec = -1;
+  bool profiled = false;
+  std::string filter;
+  bool valid() const { return !items.empty(); }
+  void clear() {
+    for (auto& it : items)
+      if (it.exec) (void)hipGraphExecDestroy(it.exec);
+    items.clear();
+  }
+  ~Program() { clear(); }
+};
+
 class Engine {
  public:
   explicit Engine(int device);
@@ -87,8 +110,11 @@ class Engine {
   Engine(const Engine&) = delete;
   Engine& operator=(const Engine&) = delete;
 
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;  // the engine's own stream unless the caller sets one
   Prec prec = Prec::FP64;
+  // Incremented whenever a device buffer that recorded launches may point to
+  // is allocated, moved or freed (tensors, plans, workspaces, cache entries).
+  uint64_t epoch = 1;
   IndexTables tables{};
   int device = 0;
 
@@ -108,12 +134,34 @@ class Engine {
   void term(const std::string& spec, double scale = 1.0);
   void terms(const char* const* specs, int n, double scale = 1.0);
 
+  // --- expansion cache
+  // Operand matrices expanded from the named tensors are kept and reused by
+  // later terms (directly or transposed, with the sign of the slot
+  // arrangement) until the next call, which invalidates every entry.  The
+  // caller guarantees that the named tensors do not change in between.
+  void cache_operands(const std::vector<std::string>& names);
+  size_t cache_bytes() const;
+
   // --- statistics (per-term algorithmic flops of the GEMMs issued)
   bool record = false;
   std::vector<GemmStats> stats;
 
-  // --- per-kernel profiling with HIP events on `stream`
+  // --- recording into a Program (hipGraph segments); nothing executes while
+  // recording: replay the program to run it
+  void begin_record(Program& prog);
+  void end_record(Program& prog);
+  void abort_record();  // after an error while recording: discard the capture
+  void replay(const Program& prog);
+  bool recording() const { return rec_ != nullptr; }
+  hipStream_t own_stream() const { return own_stream_; }
+
+  // --- per-kernel profiling with HIP events on `stream`; with a non-empty
+  // filter only kernels whose label contains it are timed
   bool profile = false;
+  std::string profile_filter;
+  bool timed(const std::string& label) const {
+    return profile && (profile_filter.empty() || label.find(profile_filter) != std::string::npos);
+  }
   void prof_mark(const std::string& label, const std::string& spec, double flops, double bytes, hipEvent_t a,
                  hipEvent_t b);
   hipEvent_t event();
@@ -128,6 +176,22 @@ class Engine {
   struct Plan;
   std::map<std::string, std::unique_ptr<Tensor>> reg_;
   std::map<std::string, std::shared_ptr<Plan>> plans_;
+  hipStream_t own_stream_ = nullptr;
+  Program* rec_ = nullptr;
+  void split_record(std::function<void()> run);
+  struct CacheEntry {
+    std::string tensor;
+    void* hi = nullptr;
+    void* lo = nullptr;
+    size_t bytes = 0;  // per buffer
+    int sign = 1;      // stored matrix = sign * canonical matrix
+    bool valid = false;
+  };
+  std::map<std::string, CacheEntry> ecache_;
+  std::vector<std::string> cacheable_;
+  bool is_cacheable(const std::string& name) const {
+    return std::find(cacheable_.begin(), cacheable_.end(), name) != cacheable_.end();
+  }
   void* ws_[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   size_t ws_bytes_[6] = {0, 0, 0, 0, 0, 0};
   uint32_t* d_binom_ = nullptr;
@@ -142,6 +206,15 @@ class Engine {
   size_t evnext_ = 0;
   std::shared_ptr<Plan> plan(const std::string& spec);
   void execute(const Plan& p, double scale);
+};
+
+// Expansion cache enabled for the named tensors for the lifetime of the scope.
+struct CacheScope {
+  Engine& e;
+  CacheScope(Engine& en, const std::vector<std::string>& names) : e(en) { e.cache_operands(names); }
+  ~CacheScope() { e.cache_operands({}); }
+  CacheScope(const CacheScope&) = delete;
+  CacheScope& operator=(const CacheScope&) = delete;
 };
 
 }  // namespace fno

@@ -153,8 +153,11 @@ void Context::setup_eom(int kind) {
   // intermediates of the quadruples projection (DIP, DEA)
   residual();
   e.prec = Prec::FP64;
-  for (int i = 0; i < t.nprep; ++i)
-    if (t.prep[i][0]) e.term(t.prep[i]);
+  {
+    CacheScope cache(e, {"T2", "T3"});
+    for (int i = 0; i < t.nprep; ++i)
+      if (t.prep[i][0]) e.term(t.prep[i]);
+  }
   sp->ready = true;
   eom_ = std::move(sp);
 }
@@ -176,6 +179,10 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
   for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
   e.stats.clear();
   e.record = true;
+  // the R blocks are fixed during one sigma: share their expansions
+  std::vector<std::string> inputs;
+  for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
+  CacheScope cache(e, inputs);
   for (int i = 0; i < t.nterms; ++i) {
     std::string s(t.terms[i]);
     // contractions that read or write the R3 block run in the requested precision

@@ -644,4 +644,47 @@ void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, d
   FNO_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- T1 dressing
+// One index of the dressed integrals g^ = (X x X) g (Y x Y), X = 1 - t1 on the
+// creation indices, Y = 1 + t1 on the annihilation indices (t1[i][a] couples
+// occupied i with virtual a only).  In place on g (n^4, row-major), slot
+// `pos` (stride n^(3-pos)):
+//   creation:     g[.., a, ..] -= sum_i t1[i][a] g[.., i, ..]   (virtual slice from the occupied one)
+//   annihilation: g[.., i, ..] += sum_a t1[i][a] g[.., a, ..]   (occupied slice from the virtual one)
+// Each pass reads only the slice it does not write.
+__global__ void __launch_bounds__(256) dress_pass_kernel(double* __restrict__ g, const double* __restrict__ t1,
+                                                         int nocc, int nvir, int64_t inner, int creation,
+                                                         int64_t total) {
+  const int n = nocc + nvir;
+  const int ntarget = creation ? nvir : nocc;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t in = e % inner;
+    const int64_t rest = e / inner;
+    const int tp = (int)(rest % ntarget);
+    const int64_t outer = rest / ntarget;
+    const int64_t base = outer * n * inner + in;
+    double acc = 0.0;
+    if (creation) {
+      for (int i = 0; i < nocc; ++i) acc -= t1[(int64_t)i * nvir + tp] * g[base + (int64_t)i * inner];
+      g[base + (int64_t)(nocc + tp) * inner] += acc;
+    } else {
+      for (int a = 0; a < nvir; ++a) acc += t1[(int64_t)tp * nvir + a] * g[base + (int64_t)(nocc + a) * inner];
+      g[base + (int64_t)tp * inner] += acc;
+    }
+  }
+}
+
+void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos, bool creation, hipStream_t s) {
+  const int64_t n = nocc + nvir;
+  int64_t inner = 1;
+  for (int q = pos + 1; q < 4; ++q) inner *= n;
+  int64_t outer = 1;
+  for (int q = 0; q < pos; ++q) outer *= n;
+  const int64_t total = outer * (creation ? nvir : nocc) * inner;
+  if (total == 0) return;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  dress_pass_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, creation ? 1 : 0, total);
+  FNO_HIP(hipGetLastError());
+}
+
 }  // namespace fno

@@ -33,6 +33,8 @@ void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, con
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s);
 void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, double alpha, int64_t total,
                      hipStream_t s);
+// One slot of the T1 similarity transform of the integrals, in place (see kernels.hip).
+void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos, bool creation, hipStream_t s);
 void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hipStream_t s);
 void launch_denominators(const IndexTables& tb, const MatDim& dims, int nh, const double* eo, const double* ev,
                          double* out, hipStream_t s);
