@@ -2,6 +2,9 @@
 //
 // One workgroup (4 wavefronts, 2 x 2) owns a BM x BN tile of C; each
 // wavefront owns a (BM/2) x (BN/2) sub-tile made of 16 x 16 MFMA blocks.
+// The FP64/FP32 kernels are bounded to two resident waves per SIMD: with one
+// wave (the 128 x 128 FP64 tile otherwise needs 384 registers per lane) the
+// LDS and barrier latencies are exposed, with two the other wave fills them.
 // Operand tiles are staged through LDS in k-major order, so that the lanes of
 // one MFMA (row = lane % 16, k = lane / 16) read contiguous LDS words.  The
 // next k-tile is fetched into registers while the current one is consumed.
@@ -42,7 +45,7 @@ __device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
 // ---------------------------------------------------------------------------
 // 16x16x4 path (FP64 / FP32).  BK = 16 (4 MFMA k-steps per staged tile).
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
-__global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+__global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                       int64_t kchunk, int64_t cz) {
@@ -164,6 +167,126 @@ __global__ void __launch_bounds__(256) gemm_k4_kernel(int64_t M, int64_t N, int6
   // C/D layout of the 16x16 MFMA block: lane l holds column l % 16; the
   // FP32 instruction gives it rows 4 * (l / 16) + r, the FP64 instruction
   // rows l / 16 + 4 * r (r = 0..3).
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int64_t col = n0 + wn * WN + j * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = (sizeof(T) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+        const int64_t row = m0 + wm * WM + i * 16 + rr;
+        if (row < M && col < N) {
+          T v = alpha * acc[i][j][r];
+          if (beta != (T)0) v += beta * C[row * ldc + col];
+          C[row * ldc + col] = v;
+        }
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Double-buffered 16x16x4 path (FP64 / FP32): two LDS stages, one barrier per
+// k-tile.  While the MFMAs of stage s run, the next k-tile is already in
+// flight from global memory into registers; it is written into the other LDS
+// stage afterwards.  Same wave layout and C/D mapping as gemm_k4_kernel.
+template <typename T, int BM, int BN, int BK, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256, 2) gemm_db_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                      int64_t kchunk, int64_t cz) {
+  static_assert(BK % 4 == 0 && (BM * BK) % 256 == 0 && (BN * BK) % 256 == 0, "tile shape");
+  {
+    const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+    A += AK ? k0 : k0 * lda;
+    B += BN_FAST ? k0 * ldb : k0;
+    C += (int64_t)blockIdx.z * cz;
+    K = (K - k0 < kchunk) ? K - k0 : kchunk;
+  }
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int A_PER = BM * BK / 256;
+  constexpr int B_PER = BN * BK / 256;
+  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * BM;
+  const int64_t n0 = (int64_t)blockIdx.x * BN;
+
+  typename Acc<T>::type acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = (typename Acc<T>::type){0, 0, 0, 0};
+
+  T ra[A_PER], rb[B_PER];
+  auto load_tiles = [&](int64_t k0) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      const int e = tid + p * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      const int64_t gm = m0 + mm, gk = k0 + kk;
+      ra[p] = (gm < M && gk < K) ? (AK ? A[gm * lda + gk] : A[gk * lda + gm]) : (T)0;
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      const int e = tid + p * 256;
+      const int nn = BN_FAST ? e % BN : e / BK;
+      const int kk = BN_FAST ? e / BN : e % BK;
+      const int64_t gn = n0 + nn, gk = k0 + kk;
+      rb[p] = (gn < N && gk < K) ? (BN_FAST ? B[gk * ldb + gn] : B[gn * ldb + gk]) : (T)0;
+    }
+  };
+  auto store_tiles = [&](int s) {
+#pragma unroll
+    for (int p = 0; p < A_PER; ++p) {
+      const int e = tid + p * 256;
+      const int mm = AK ? e / BK : e % BM;
+      const int kk = AK ? e % BK : e / BM;
+      As[s][kk][mm] = ra[p];
+    }
+#pragma unroll
+    for (int p = 0; p < B_PER; ++p) {
+      const int e = tid + p * 256;
+      const int nn = BN_FAST ? e % BN : e / BK;
+      const int kk = BN_FAST ? e / BN : e % BK;
+      Bs[s][kk][nn] = rb[p];
+    }
+  };
+
+  const int64_t nk = (K + BK - 1) / BK;
+  if (nk > 0) {
+    load_tiles(0);
+    store_tiles(0);
+  }
+  __syncthreads();
+  for (int64_t kt = 0; kt < nk; ++kt) {
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) load_tiles((kt + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int kr = ks + (lane >> 4);
+      T af[TM], bfr[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) af[i] = As[cur][kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) bfr[j] = Bs[cur][kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(af[i], bfr[j], acc[i][j]);
+    }
+    if (more) store_tiles(cur ^ 1);
+    __syncthreads();
+  }
+
 #pragma unroll
   for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -353,8 +476,11 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
 // Tile table used by the planner and the autotuner.
 struct TileCfg {
   int bm, bn;
+  int bk;  // double-buffered k-tile depth (FP64 / FP32); 0 = single-buffered BK = 16
 };
-static const TileCfg kTiles[] = {{64, 64}, {128, 64}, {64, 128}, {128, 128}, {32, 64}, {64, 32}};
+static const TileCfg kTiles[] = {{64, 64, 0},    {128, 64, 0},  {64, 128, 0},  {128, 128, 0}, {32, 64, 0},
+                                 {64, 32, 0},    {128, 128, 16}, {128, 128, 32}, {128, 64, 32}, {64, 128, 32},
+                                 {64, 64, 32}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(Prec) { return kNumTiles; }
@@ -462,6 +588,49 @@ static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
     launch_b3<BM, BN>(g, s);
 }
 
+template <typename T, int BM, int BN, int BK>
+static void launch_db(const GemmArgs& g, hipStream_t s) {
+  const int split = g.split > 1 ? g.split : 1;
+  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + BK - 1) / BK) * BK : (g.K > 0 ? g.K : 1);
+  const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
+  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
+  const T* A = (const T*)g.A;
+  const T* B = (const T*)g.B;
+  T* C = split > 1 ? (T*)g.ws : (T*)g.C;
+  const int64_t ldc = split > 1 ? g.N : g.ldc;
+  const int64_t cz = split > 1 ? g.M * g.N : 0;
+  T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
+  if (g.a_kfast && g.b_nfast)
+    gemm_db_kernel<T, BM, BN, BK, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
+                                                                   be, kchunk, cz);
+  else if (g.a_kfast)
+    gemm_db_kernel<T, BM, BN, BK, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
+                                                                    be, kchunk, cz);
+  else if (g.b_nfast)
+    gemm_db_kernel<T, BM, BN, BK, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
+                                                                    be, kchunk, cz);
+  else
+    gemm_db_kernel<T, BM, BN, BK, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc,
+                                                                     al, be, kchunk, cz);
+  if (split > 1) {
+    const int64_t total = g.M * g.N;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    splitk_reduce_kernel<T><<<dim3((unsigned)blocks), 256, 0, s>>>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc,
+                                                                   (T)g.alpha, (T)g.beta);
+  }
+}
+
+// double-buffered configurations: FP64/FP32 kernels; split-BF16 keeps its own kernel
+template <int BM, int BN, int BK>
+static void dispatch_db(const GemmArgs& g, hipStream_t s) {
+  if (g.prec == Prec::FP64)
+    launch_db<double, BM, BN, BK>(g, s);
+  else if (g.prec == Prec::FP32)
+    launch_db<float, BM, BN, BK>(g, s);
+  else
+    launch_b3<BM, BN>(g, s);
+}
+
 int gemm_split_factor(const GemmArgs& g) {
   // enough workgroups to fill 256 CUs a few times over; chunks of >= 128 k
   const int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
@@ -482,6 +651,9 @@ std::string gemm_label(const GemmArgs& g) {
   std::string bm = std::to_string(kTiles[t].bm), bn = std::to_string(kTiles[t].bn);
   std::string lay = std::string(g.a_kfast ? "true" : "false") + ", " + (g.b_nfast ? "true" : "false");
   if (g.prec == Prec::BF16X3) return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ">";
+  if (kTiles[t].bk > 0)
+    return std::string("fno::gemm_db_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " +
+           bn + ", " + std::to_string(kTiles[t].bk) + ", " + lay + ">";
   return std::string("fno::gemm_k4_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " + bn +
          ", " + lay + ">";
 }
@@ -495,7 +667,12 @@ void launch_gemm(const GemmArgs& g, hipStream_t s) {
     case 2: dispatch_tile<64, 128>(g, s); break;
     case 3: dispatch_tile<128, 128>(g, s); break;
     case 4: dispatch_tile<32, 64>(g, s); break;
-    default: dispatch_tile<64, 32>(g, s); break;
+    case 5: dispatch_tile<64, 32>(g, s); break;
+    case 6: dispatch_db<128, 128, 16>(g, s); break;
+    case 7: dispatch_db<128, 128, 32>(g, s); break;
+    case 8: dispatch_db<128, 64, 32>(g, s); break;
+    case 9: dispatch_db<64, 128, 32>(g, s); break;
+    default: dispatch_db<64, 64, 32>(g, s); break;
   }
   FNO_HIP(hipGetLastError());
 }
