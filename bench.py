@@ -88,6 +88,19 @@ def cpu_baseline(ham, occt, triples_flops):
     }
 
 
+def copy_calibration(nbytes=512 << 20, reps=5):
+    """A plain copy kernel of known size: under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its
+    per-dispatch reading against nbytes gives the scale factor of those counters."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "reads_bytes": nbytes, "writes_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -97,7 +110,12 @@ def main():
     ap.add_argument("--occt", type=float, default=0.99)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this library runs the hot path on one GPU; --gpus must be 1 "

@@ -42,13 +42,31 @@ __device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Tile of a workgroup.  The grid is one-dimensional over the MT x NT tiles
+// (split-K slices in z).  Consecutive workgroup ids are spread round-robin
+// over the 8 XCDs, each with its own L2: id L goes to XCD L % 8, so XCD x is
+// given the contiguous tile range [x*q + min(x, r), ...) of its share, walked
+// with M fastest (m_fast: consecutive tiles share a B column strip) or N
+// fastest (consecutive tiles share an A row strip).  The operand whose strips
+// are shared is then read from HBM about once instead of once per tile row.
+__device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, int m_fast, int64_t& m0, int64_t& n0) {
+  const int64_t MT = (M + BM - 1) / BM, NT = (N + BN - 1) / BN, T = MT * NT;
+  const int64_t L = blockIdx.x;
+  const int64_t q = T / 8, r = T % 8, x = L % 8, k = L / 8;
+  const int64_t t = x * q + (x < r ? x : r) + k;
+  const int64_t mt = m_fast ? t % MT : t / NT;
+  const int64_t nt = m_fast ? t / MT : t % NT;
+  m0 = mt * BM;
+  n0 = nt * BN;
+}
+
 // ---------------------------------------------------------------------------
 // 16x16x4 path (FP64 / FP32).  BK = 16 (4 MFMA k-steps per staged tile).
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
 __global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
-                                                      int64_t kchunk, int64_t cz) {
+                                                      int64_t kchunk, int64_t cz, int m_fast) {
   constexpr int BK = 16;
   {  // split-K: this z-slice owns K range [z*kchunk, z*kchunk + kchunk)
     const int64_t k0 = (int64_t)blockIdx.z * kchunk;
@@ -69,8 +87,8 @@ __global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  int64_t m0, n0;
+  tile_of(M, N, BM, BN, m_fast, m0, n0);
 
   typename Acc<T>::type acc[TM][TN];
 #pragma unroll
@@ -194,7 +212,7 @@ template <typename T, int BM, int BN, int BK, bool AK, bool BN_FAST>
 __global__ void __launch_bounds__(256, 2) gemm_db_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
-                                                      int64_t kchunk, int64_t cz) {
+                                                      int64_t kchunk, int64_t cz, int m_fast) {
   static_assert(BK % 4 == 0 && (BM * BK) % 256 == 0 && (BN * BK) % 256 == 0, "tile shape");
   {
     const int64_t k0 = (int64_t)blockIdx.z * kchunk;
@@ -215,8 +233,8 @@ __global__ void __launch_bounds__(256, 2) gemm_db_kernel(int64_t M, int64_t N, i
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  int64_t m0, n0;
+  tile_of(M, N, BM, BN, m_fast, m0, n0);
 
   typename Acc<T>::type acc[TM][TN];
 #pragma unroll
@@ -314,7 +332,7 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
                                                           const __bf16* __restrict__ Bh,
                                                           const __bf16* __restrict__ Bl, int64_t ldb,
                                                           float* __restrict__ C, int64_t ldc, float alpha,
-                                                          float beta, int64_t kchunk, int64_t cz) {
+                                                          float beta, int64_t kchunk, int64_t cz, int m_fast) {
   constexpr int BK = 32;
   {
     const int64_t k0 = (int64_t)blockIdx.z * kchunk;
@@ -339,8 +357,8 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t m0 = (int64_t)blockIdx.y * BM;
-  const int64_t n0 = (int64_t)blockIdx.x * BN;
+  int64_t m0, n0;
+  tile_of(M, N, BM, BN, m_fast, m0, n0);
 
   f4_t acc[TM][TN];
 #pragma unroll
@@ -496,6 +514,11 @@ static int default_tile(const GemmArgs& g) {
   return 0;
 }
 
+// Tile walk order: M fastest when B (K x N) is the larger operand, so that the
+// workgroups of one XCD sharing a B column strip run back to back; N fastest
+// otherwise.
+static int m_fast_order(const GemmArgs& g) { return g.N > g.M ? 1 : 0; }
+
 // reduction of split-K partials: C = alpha * sum_z P[z] + beta * C
 template <typename T>
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(const T* __restrict__ P, int split, int64_t M, int64_t N,
@@ -516,7 +539,8 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
   const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 15) / 16) * 16 : (g.K > 0 ? g.K : 1);
   const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
+  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), 1u, (unsigned)nz);
+  const int mf = m_fast_order(g);
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
   T* C = split > 1 ? (T*)g.ws : (T*)g.C;
@@ -525,16 +549,16 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
   T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
   if (g.a_kfast && g.b_nfast)
     gemm_k4_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                               kchunk, cz);
+                                                               kchunk, cz, mf);
   else if (g.a_kfast)
     gemm_k4_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                                kchunk, cz);
+                                                                kchunk, cz, mf);
   else if (g.b_nfast)
     gemm_k4_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                                kchunk, cz);
+                                                                kchunk, cz, mf);
   else
     gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
-                                                                 be, kchunk, cz);
+                                                                 be, kchunk, cz, mf);
   if (split > 1) {
     int64_t total = g.M * g.N;
     int64_t blocks = (total + 255) / 256;
@@ -549,7 +573,8 @@ static void launch_b3(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
   const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 31) / 32) * 32 : (g.K > 0 ? g.K : 1);
   const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
+  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), 1u, (unsigned)nz);
+  const int mf = m_fast_order(g);
   const __bf16 *Ah = (const __bf16*)g.A, *Al = (const __bf16*)g.A_lo;
   const __bf16 *Bh = (const __bf16*)g.B, *Bl = (const __bf16*)g.B_lo;
   float* C = split > 1 ? (float*)g.ws : (float*)g.C;
@@ -558,16 +583,16 @@ static void launch_b3(const GemmArgs& g, hipStream_t s) {
   float al = split > 1 ? 1.0f : (float)g.alpha, be = split > 1 ? 0.0f : (float)g.beta;
   if (g.a_kfast && g.b_nfast)
     gemm_bf16x3_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                               ldc, al, be, kchunk, cz);
+                                                               ldc, al, be, kchunk, cz, mf);
   else if (g.a_kfast)
     gemm_bf16x3_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                ldc, al, be, kchunk, cz);
+                                                                ldc, al, be, kchunk, cz, mf);
   else if (g.b_nfast)
     gemm_bf16x3_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                ldc, al, be, kchunk, cz);
+                                                                ldc, al, be, kchunk, cz, mf);
   else
     gemm_bf16x3_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                 ldc, al, be, kchunk, cz);
+                                                                 ldc, al, be, kchunk, cz, mf);
   if (split > 1) {
     int64_t total = g.M * g.N;
     int64_t blocks = (total + 255) / 256;
@@ -593,7 +618,8 @@ static void launch_db(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
   const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + BK - 1) / BK) * BK : (g.K > 0 ? g.K : 1);
   const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
-  dim3 grid((unsigned)((g.N + BN - 1) / BN), (unsigned)((g.M + BM - 1) / BM), (unsigned)nz);
+  dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), 1u, (unsigned)nz);
+  const int mf = m_fast_order(g);
   const T* A = (const T*)g.A;
   const T* B = (const T*)g.B;
   T* C = split > 1 ? (T*)g.ws : (T*)g.C;
@@ -602,16 +628,16 @@ static void launch_db(const GemmArgs& g, hipStream_t s) {
   T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
   if (g.a_kfast && g.b_nfast)
     gemm_db_kernel<T, BM, BN, BK, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
-                                                                   be, kchunk, cz);
+                                                                   be, kchunk, cz, mf);
   else if (g.a_kfast)
     gemm_db_kernel<T, BM, BN, BK, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
-                                                                    be, kchunk, cz);
+                                                                    be, kchunk, cz, mf);
   else if (g.b_nfast)
     gemm_db_kernel<T, BM, BN, BK, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
-                                                                    be, kchunk, cz);
+                                                                    be, kchunk, cz, mf);
   else
     gemm_db_kernel<T, BM, BN, BK, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc,
-                                                                     al, be, kchunk, cz);
+                                                                     al, be, kchunk, cz, mf);
   if (split > 1) {
     const int64_t total = g.M * g.N;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);

@@ -674,7 +674,60 @@ __global__ void __launch_bounds__(256) dress_pass_kernel(double* __restrict__ g,
   }
 }
 
+// Same update, one thread per position of the other three slots: the thread
+// reads its source slice once and produces every target of the slot (the
+// occupied side, at most kDressMaxOcc values, lives in registers).
+constexpr int kDressMaxOcc = 32;
+__global__ void __launch_bounds__(256) dress_slice_kernel(double* __restrict__ g, const double* __restrict__ t1,
+                                                          int nocc, int nvir, int64_t inner, int creation,
+                                                          int64_t total) {
+  const int n = nocc + nvir;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t in = e % inner;
+    const int64_t outer = e / inner;
+    double* base = g + outer * n * inner + in;
+    double occ[kDressMaxOcc];
+    if (creation) {
+      // g[a] -= sum_i t1[i][a] g[i]
+#pragma unroll
+      for (int i = 0; i < kDressMaxOcc; ++i) occ[i] = i < nocc ? base[(int64_t)i * inner] : 0.0;
+      for (int a = 0; a < nvir; ++a) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < kDressMaxOcc; ++i)
+          if (i < nocc) acc += t1[(int64_t)i * nvir + a] * occ[i];
+        base[(int64_t)(nocc + a) * inner] -= acc;
+      }
+    } else {
+      // g[i] += sum_a t1[i][a] g[a]
+#pragma unroll
+      for (int i = 0; i < kDressMaxOcc; ++i) occ[i] = 0.0;
+      for (int a = 0; a < nvir; ++a) {
+        const double v = base[(int64_t)(nocc + a) * inner];
+#pragma unroll
+        for (int i = 0; i < kDressMaxOcc; ++i)
+          if (i < nocc) occ[i] += t1[(int64_t)i * nvir + a] * v;
+      }
+#pragma unroll
+      for (int i = 0; i < kDressMaxOcc; ++i)
+        if (i < nocc) base[(int64_t)i * inner] += occ[i];
+    }
+  }
+}
+
 void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos, bool creation, hipStream_t s) {
+  if (nocc <= kDressMaxOcc) {
+    const int64_t n = nocc + nvir;
+    int64_t inner = 1, outer = 1;
+    for (int q = pos + 1; q < 4; ++q) inner *= n;
+    for (int q = 0; q < pos; ++q) outer *= n;
+    const int64_t total = outer * inner;
+    if (total == 0 || nvir == 0 || nocc == 0) return;
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    dress_slice_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, creation ? 1 : 0, total);
+    FNO_HIP(hipGetLastError());
+    return;
+  }
   const int64_t n = nocc + nvir;
   int64_t inner = 1;
   for (int q = pos + 1; q < 4; ++q) inner *= n;
