@@ -113,6 +113,9 @@ typedef struct {
   fno_prec prec;    /* precision of the R3 sigma contractions */
   int guess;        /* 0 = unit vectors on the lowest principal-block diagonal */
   int precond;      /* 0 = (omega - D)^-1 with the zeroth-order diagonal D */
+  int block;        /* sigma vectors evaluated together (the R-derived tensors hold a
+                       block of vectors; every contraction covers the block in one
+                       GEMM); 0 = nroots, at most 16 */
 } fno_eom_opts;
 void fno_eom_opts_default(fno_eom_opts *o);
 
@@ -125,6 +128,24 @@ void fno_eom_opts_default(fno_eom_opts *o);
  */
 int fno_eom(fno_ctx *ctx, fno_eom_kind kind, const fno_eom_opts *opts, double *omega, double *e_tot,
             double *res_norm, int *iters);
+
+/*
+ * EOM roots of `kind` for n independent problems (batching of uneven-size
+ * instances).  Every context must hold a converged fno_ccsdt; they may differ
+ * in size; none may appear twice.  The Davidson solvers advance in lockstep:
+ * each iteration issues the sigma work of every instance on its own context
+ * stream (replayed from hipGraphs once recorded) before any instance waits
+ * for its results, so the instances' kernels overlap on the device.  Each
+ * instance computes exactly what fno_eom would on that context.
+ *   omega    : n * nroots excitation energies, instance-major.
+ *   res_norm : n * nroots residual norms (may be NULL).
+ *   iters    : n iteration counts (may be NULL).
+ * Returns FNO_OK if every instance converged, FNO_ENOCONV if some did not
+ * (results still written), another status on error (fno_last_error of the
+ * first context names the failing instance).
+ */
+int fno_batch_eom(int n, fno_ctx *const *ctxs, fno_eom_kind kind, const fno_eom_opts *opts, double *omega,
+                  double *res_norm, int *iters);
 
 /* Orbital-space sizes of the current problem (after truncation). */
 int fno_sizes(const fno_ctx *ctx, int *nocc, int *nvir, int *nvir_full);
@@ -199,6 +220,16 @@ int fno_profile_filter(fno_ctx *ctx, const char *substr);
  * modes (same kernels, same order).
  */
 int fno_set_graphs(fno_ctx *ctx, int on);
+
+/*
+ * GEMM tile autotuner (off by default).  With on = 1, the first host-launched
+ * contraction GEMM of every (precision, M, N, K, operand layout) times each
+ * MFMA tile configuration on a scratch output and keeps the fastest for that
+ * shape in this context; fno_profile_report lists the choices under "tuned".
+ * Tiles change the tiling and split-K slicing, not the k order within a
+ * slice, so results agree with the untuned run to rounding.
+ */
+int fno_set_autotune(fno_ctx *ctx, int on);
 
 size_t fno_debug_tensor_size(fno_ctx *ctx, const char *name);
 int fno_debug_tensor(fno_ctx *ctx, const char *name, double *buf, size_t len);

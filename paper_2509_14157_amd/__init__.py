@@ -23,7 +23,7 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_profile_filter",
-           "fno_set_graphs", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
+           "fno_set_graphs", "fno_set_autotune", "fno_batch_eom", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
 
 
 class FnoError(RuntimeError):
@@ -39,7 +39,8 @@ class CCOpts(C.Structure):
 
 class EOMOpts(C.Structure):
     _fields_ = [("nroots", C.c_int), ("max_iter", C.c_int), ("max_sub", C.c_int), ("e_tol", C.c_double),
-                ("r_tol", C.c_double), ("prec", C.c_int), ("guess", C.c_int), ("precond", C.c_int)]
+                ("r_tol", C.c_double), ("prec", C.c_int), ("guess", C.c_int), ("precond", C.c_int),
+                ("block", C.c_int)]
 
 
 _lib = None
@@ -81,6 +82,9 @@ def library() -> C.CDLL:
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_set_graphs.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_set_autotune.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_batch_eom.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(EOMOpts), dp, dp,
+                                      C.POINTER(C.c_int)]
         lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_debug_tensor_size.restype = C.c_size_t
         lib.fno_debug_tensor.argtypes = [C.c_void_p, C.c_char_p, dp, C.c_size_t]
@@ -199,6 +203,10 @@ class Context:
         self._check(self._lib.fno_profile_filter(self._h, (only or "").encode()))
         self._check(self._lib.fno_profile(self._h, int(bool(on))))
 
+    def set_autotune(self, on: bool = True) -> None:
+        """Pick GEMM tiles per shape by timing every configuration on first use."""
+        self._check(self._lib.fno_set_autotune(self._h, int(bool(on))))
+
     def set_graphs(self, on: bool = True) -> None:
         """Replay the residual sweep from recorded hipGraphs (default) or launch eagerly."""
         self._check(self._lib.fno_set_graphs(self._h, int(bool(on))))
@@ -248,13 +256,34 @@ class Context:
         return out
 
     def eom(self, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",
-            allow_noconv=False):
+            allow_noconv=False, block=0):
         o = EOMOpts()
         self._lib.fno_eom_opts_default(C.byref(o))
         o.nroots, o.max_iter, o.max_sub, o.e_tol, o.r_tol = nroots, max_iter, max_sub, e_tol, r_tol
         o.prec = PREC[prec]
+        o.block = block
         om, et, rn = np.zeros(nroots), np.zeros(nroots), np.zeros(nroots)
         it = C.c_int()
         st = self._check(self._lib.fno_eom(self._h, KIND[kind], C.byref(o), _dp(om), _dp(et), _dp(rn), C.byref(it)),
                          allow=(FNO_ENOCONV,) if allow_noconv else ())
         return dict(omega=om, e_tot=et, res_norm=rn, iters=it.value, converged=(st == FNO_OK))
+
+
+def batch_eom(contexts, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",
+              allow_noconv=False, block=0):
+    """EOM roots for several contexts at once (fno_batch_eom); returns a list of result dicts."""
+    lib = library()
+    n = len(contexts)
+    o = EOMOpts()
+    lib.fno_eom_opts_default(C.byref(o))
+    o.nroots, o.max_iter, o.max_sub, o.e_tol, o.r_tol = nroots, max_iter, max_sub, e_tol, r_tol
+    o.prec = PREC[prec]
+    o.block = block
+    handles = (C.c_void_p * n)(*[c._h.value if isinstance(c._h, C.c_void_p) else c._h for c in contexts])
+    om, rn = np.zeros(n * nroots), np.zeros(n * nroots)
+    its = (C.c_int * n)()
+    st = lib.fno_batch_eom(n, handles, KIND[kind], C.byref(o), _dp(om), _dp(rn), its)
+    if st != FNO_OK and not (allow_noconv and st == FNO_ENOCONV):
+        raise FnoError(st, lib.fno_last_error(contexts[0]._h).decode())
+    return [dict(omega=om[i * nroots:(i + 1) * nroots].copy(), res_norm=rn[i * nroots:(i + 1) * nroots].copy(),
+                 iters=its[i], converged=(st == FNO_OK)) for i in range(n)]

@@ -32,6 +32,11 @@ The DIP and DEA R operators reach rank four (4h2p, 4p2h); their quadruples
 projection comes from the linearized table in csrc/eom_quad_terms.inc, whose
 direction blocks receive the continuum labels the same way.
 
+Root blocks.  Every block tensor has a leading batch slot (space b, letter
+Z) over the vectors of one Davidson block: each sigma term then processes the
+whole block in one GEMM (the batch letter is an output letter of the
+R-carrying factor), instead of one launch per vector.
+
 Usage: python -m paper_2509_14157_amd.codegen.eom_jvp  (writes csrc/eom_*_terms.inc)
 """
 from __future__ import annotations
@@ -54,6 +59,10 @@ VARIANTS = {
     "DIP": (("x", "y"), "v", (("T2", (2, 0)), ("T3", (3, 1)), ("T4", (4, 2)))),
     "DEA": (("x", "y"), "o", (("T2", (0, 2)), ("T3", (1, 3)), ("T4", (2, 4)))),
 }
+
+# Every R-derived tensor carries a leading batch slot (index space b) over the
+# vectors of a Davidson block; its letter never occurs in the ground-state tables.
+BATCH = "Z"
 
 # The quadruples projection enters only through its linearization (a
 # hand-written table): direction and image names map onto the amplitude and
@@ -200,8 +209,9 @@ class Generator:
             s += keep
         name = self.block_name(t, asg)
         # blocks are stored packed by their antisymmetric groups (for blocks of
-        # dense integral views this keeps the pair antisymmetry explicit)
-        self.decls[name] = ",".join("".join(spaces[x] for x in g) for g in groups)
+        # dense integral views this keeps the pair antisymmetry explicit),
+        # behind a leading batch slot (space b) over the vectors of one block
+        self.decls[name] = ",".join(["b"] + ["".join(spaces[x] for x in g) for g in groups])
         return name
 
     # ---------------------------------------------------------- dressing blocks
@@ -235,7 +245,7 @@ class Generator:
                 out_letters = "".join(letters[j] for j in range(len(spaces)) if j != k)
                 src_letters = letters[:k] + "z" + letters[k + 1:]
                 op = "+=" if coef > 0 else "-="
-                self.out_terms.append(f"{bname}[{out_letters}] {op} 1 * {rin}[z] * {src}[{src_letters}]")
+                self.out_terms.append(f"{bname}[{BATCH}{out_letters}] {op} 1 * {rin}[{BATCH}z] * {src}[{src_letters}]")
                 self.nonzero.add(bname)
                 self.zero_list.append(bname)
 
@@ -312,8 +322,8 @@ class Generator:
                 for h in set(fasg):
                     sgn *= move_to_end_sign(gf[h], [carried[j] for j in range(len(carried)) if fasg[j] == h])
                 oname = self.block_tensor(To, oasg)
-                new_lo = "".join(l for l in lo if l not in carried)
-                new_lf = "".join(l for l in lf if l not in carried)
+                new_lo = BATCH + "".join(l for l in lo if l not in carried)
+                new_lf = BATCH + "".join(l for l in lf if l not in carried)
                 cn = c * sgn
                 op = "+=" if cn > 0 else "-="
                 mag = "%g" % abs(cn)

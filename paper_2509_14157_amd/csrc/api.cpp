@@ -4,6 +4,7 @@
 
 #include "../../include/fnocc.h"
 #include "context.hpp"
+#include "eom_space.hpp"
 
 struct fno_ctx {
   fno::Context* c = nullptr;
@@ -129,6 +130,88 @@ void fno_eom_opts_default(fno_eom_opts* o) {
   o->prec = FNO_FP64;
   o->guess = 0;
   o->precond = 0;
+  o->block = 0;
+}
+
+namespace {
+fno::EOMOptions eom_options(const fno_eom_opts* opts) {
+  fno_eom_opts d;
+  fno_eom_opts_default(&d);
+  const fno_eom_opts& o = opts ? *opts : d;
+  FNO_REQUIRE(o.guess == 0 && o.precond == 0, FNO_EINVAL, "unsupported guess/preconditioner option");
+  FNO_REQUIRE(o.block >= 0 && o.block <= 16, FNO_EINVAL, "block must be in [0, 16]");
+  fno::EOMOptions eo;
+  eo.nroots = o.nroots;
+  eo.max_iter = o.max_iter;
+  eo.max_sub = o.max_sub;
+  eo.e_tol = o.e_tol;
+  eo.r_tol = o.r_tol;
+  eo.prec = to_prec(o.prec);
+  eo.block = o.block;
+  return eo;
+}
+}  // namespace
+
+int fno_batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts* opts, double* omega,
+                  double* res_norm, int* iters) {
+  if (n <= 0 || !ctxs || !omega) return FNO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i] || !ctxs[i]->c) return FNO_EINVAL;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (ctxs[i] == ctxs[j]) {
+        ctxs[i]->err = "a context appears twice in the batch";
+        return FNO_EINVAL;
+      }
+  std::vector<fno::Context::Davidson*> d(n, nullptr);
+  int failed = -1;
+  try {
+    FNO_REQUIRE(kind >= FNO_IP && kind <= FNO_DEA, FNO_EINVAL, "unknown EOM kind");
+    const fno::EOMOptions eo = eom_options(opts);
+    for (int i = 0; i < n; ++i) {
+      failed = i;
+      ctxs[i]->err.clear();
+      FNO_HIP(hipSetDevice(ctxs[i]->c->device));
+      FNO_REQUIRE(ctxs[i]->c->cc_done, FNO_ESTATE, "fno_batch_eom needs a converged fno_ccsdt on every context");
+      d[i] = ctxs[i]->c->dav_begin((int)kind, eo);
+    }
+    // lockstep: the sigma work of every instance is issued on its own stream
+    // before any host wait, then each instance does its subspace step
+    for (bool all_done = false; !all_done;) {
+      for (int i = 0; i < n; ++i) {
+        failed = i;
+        if (!d[i]->done) ctxs[i]->c->dav_sigma(*d[i]);
+      }
+      all_done = true;
+      for (int i = 0; i < n; ++i) {
+        failed = i;
+        if (!d[i]->done) ctxs[i]->c->dav_update(*d[i]);
+        all_done = all_done && d[i]->done;
+      }
+    }
+    int status = FNO_OK;
+    for (int i = 0; i < n; ++i) {
+      failed = i;
+      fno::EOMResult r;
+      const int st = ctxs[i]->c->dav_end(r);
+      for (int k = 0; k < eo.nroots; ++k) {
+        omega[(size_t)i * eo.nroots + k] = r.omega[k];
+        if (res_norm) res_norm[(size_t)i * eo.nroots + k] = r.res_norm[k];
+      }
+      if (iters) iters[i] = r.iters;
+      if (st != FNO_OK) status = FNO_ENOCONV;
+    }
+    return status;
+  } catch (const fno::Error& e) {
+    for (int i = 0; i < n; ++i) ctxs[i]->c->dav_release();
+    if (failed >= 0) ctxs[failed]->err = e.what();
+    if (failed != 0) ctxs[0]->err = std::string("instance ") + std::to_string(failed) + ": " + e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    for (int i = 0; i < n; ++i) ctxs[i]->c->dav_release();
+    ctxs[0]->err = e.what();
+    return FNO_EDEVICE;
+  }
 }
 
 int fno_eom(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, double* omega, double* e_tot,
@@ -136,21 +219,11 @@ int fno_eom(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, double* o
   return guard(ctx, [&](fno::Context& c) {
     FNO_REQUIRE(kind >= FNO_IP && kind <= FNO_DEA, FNO_EINVAL, "unknown EOM kind");
     FNO_REQUIRE(c.cc_done, FNO_ESTATE, "fno_eom needs a converged fno_ccsdt first");
-    fno_eom_opts d;
-    fno_eom_opts_default(&d);
-    const fno_eom_opts& o = opts ? *opts : d;
     FNO_REQUIRE(omega != nullptr, FNO_EINVAL, "omega is required");
-    FNO_REQUIRE(o.guess == 0 && o.precond == 0, FNO_EINVAL, "unsupported guess/preconditioner option");
-    fno::EOMOptions eo;
-    eo.nroots = o.nroots;
-    eo.max_iter = o.max_iter;
-    eo.max_sub = o.max_sub;
-    eo.e_tol = o.e_tol;
-    eo.r_tol = o.r_tol;
-    eo.prec = to_prec(o.prec);
+    const fno::EOMOptions eo = eom_options(opts);
     fno::EOMResult r;
     int st = c.eom((int)kind, eo, r);
-    for (int k = 0; k < o.nroots; ++k) {
+    for (int k = 0; k < eo.nroots; ++k) {
       omega[k] = r.omega[k];
       if (e_tot) e_tot[k] = c.e_ref + c.e_corr + r.omega[k];
       if (res_norm) res_norm[k] = r.res_norm[k];
@@ -236,6 +309,13 @@ int fno_profile(fno_ctx* ctx, int on) {
 int fno_profile_filter(fno_ctx* ctx, const char* substr) {
   return guard(ctx, [&](fno::Context& c) {
     c.eng->profile_filter = substr ? std::string(substr) : std::string();
+    return FNO_OK;
+  });
+}
+
+int fno_set_autotune(fno_ctx* ctx, int on) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.eng->autotune = on != 0;
     return FNO_OK;
   });
 }

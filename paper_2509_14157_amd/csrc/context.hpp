@@ -18,6 +18,7 @@ struct CCOptions {
 
 struct EOMOptions {
   int nroots = 4, max_iter = 60, max_sub = 0;
+  int block = 0;  // vectors per sigma evaluation (0 = nroots)
   double e_tol = 1e-8, r_tol = 1e-6;
   Prec prec = Prec::FP64;
 };
@@ -64,6 +65,13 @@ class Context {
   size_t eom_size(int kind);
   void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len);
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
+  // resumable Davidson (used by eom() and by batched solves over several contexts)
+  struct Davidson;
+  Davidson* dav_begin(int kind, const EOMOptions& opt);
+  void dav_sigma(Davidson& d);    // issue the pending sigma vectors (no host wait)
+  bool dav_update(Davidson& d);   // one iteration's host work; true when finished
+  int dav_end(EOMResult& res);    // results, releases the solver; status kOK / kENOCONV
+  void dav_release();
 
   double last_triples_flops = 0, last_all_flops = 0;
 
@@ -105,7 +113,8 @@ class Context {
 
   // EOM state
   std::unique_ptr<EomSpace> eom_;
-  void setup_eom(int kind);
+  std::unique_ptr<Davidson> dav_;
+  void setup_eom(int kind, int nb);
   void release_eom();
 
   double* alloc(int64_t n);

@@ -63,7 +63,7 @@ Engine::~Engine() {
   (void)hipDeviceSynchronize();
   for (auto& kv : reg_)
     if (kv.second->owner && kv.second->d) (void)hipFree(kv.second->d);
-  for (int i = 0; i < 6; ++i)
+  for (int i = 0; i < 7; ++i)
     if (ws_[i]) (void)hipFree(ws_[i]);
   for (auto ev : evpool_) (void)hipEventDestroy(ev);
   for (auto& kv : ecache_) {
@@ -227,7 +227,7 @@ std::string Engine::profile_report() {
     js += std::string(first ? "" : ", ") + "{\"term\": \"" + esc(kv.first) + "\", " + buf;
     first = false;
   }
-  js += "]}";
+  js += "], \"tuned\": " + tuned_report() + "}";
   prof_.clear();
   evnext_ = 0;
   return js;
@@ -1174,6 +1174,11 @@ void Engine::execute(const Plan& p, double scale) {
   auto timed_gemm = [&]() {
     g.split = gemm_split_factor(g);
     if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
+    if (autotune && !rec_ && g.tile < 0) {
+      g.tile = tuned_tile(g);
+      g.split = gemm_split_factor(g);
+      if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
+    }
     const std::string label = gemm_label(g);
     const double b = (double)esz * (double)(Msz * Ksz + Ksz * Nsz) * (prec == Prec::BF16X3 ? 2 : 1) +
                      (prec == Prec::FP64 ? 8.0 : 4.0) * (double)(Msz * Nsz);
@@ -1225,6 +1230,59 @@ void Engine::execute(const Plan& p, double scale) {
     }
   }
   if (record) stats.push_back({p.spec, Msz, Nsz, Ksz, p.flops});
+}
+
+int Engine::tuned_tile(const GemmArgs& g0) {
+  char key[160];
+  std::snprintf(key, sizeof(key), "%d|%lld|%lld|%lld|%d%d", (int)g0.prec, (long long)g0.M, (long long)g0.N,
+                (long long)g0.K, (int)g0.a_kfast, (int)g0.b_nfast);
+  auto it = tuned_.find(key);
+  if (it != tuned_.end()) return it->second.first;
+  const size_t esz = g0.prec == Prec::FP64 ? 8 : 4;
+  void* scratch = workspace(6, (size_t)(g0.M * g0.N) * esz);
+  hipEvent_t a = nullptr, b = nullptr;
+  FNO_HIP(hipEventCreate(&a));
+  FNO_HIP(hipEventCreate(&b));
+  int best = -1;
+  float best_ms = 0;
+  for (int t = 0; t < gemm_num_tiles(g0.prec); ++t) {
+    GemmArgs g = g0;
+    g.tile = t;
+    g.C = scratch;
+    g.ldc = g.N;
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    g.split = gemm_split_factor(g);
+    if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
+    launch_gemm(g, stream);  // warm-up
+    FNO_HIP(hipEventRecord(a, stream));
+    for (int r = 0; r < 2; ++r) launch_gemm(g, stream);
+    FNO_HIP(hipEventRecord(b, stream));
+    FNO_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    FNO_HIP(hipEventElapsedTime(&ms, a, b));
+    if (best < 0 || ms < best_ms) {
+      best = t;
+      best_ms = ms;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  GemmArgs g = g0;
+  g.tile = best;
+  tuned_[key] = {best, gemm_label(g)};
+  return best;
+}
+
+std::string Engine::tuned_report() const {
+  std::string js = "{";
+  bool first = true;
+  for (auto& kv : tuned_) {
+    if (!first) js += ", ";
+    first = false;
+    js += "\"" + kv.first + "\": \"" + kv.second.second + "\"";
+  }
+  return js + "}";
 }
 
 void Engine::cache_operands(const std::vector<std::string>& names) {

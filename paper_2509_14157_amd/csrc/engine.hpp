@@ -155,6 +155,13 @@ class Engine {
   bool recording() const { return rec_ != nullptr; }
   hipStream_t own_stream() const { return own_stream_; }
 
+  // --- GEMM tile autotuner: with autotune on, the first host-launched GEMM of
+  // each (precision, M, N, K, layout) times every tile configuration into a
+  // scratch output and keeps the fastest for that shape (per engine).
+  bool autotune = false;
+  int tuned_tile(const GemmArgs& g);
+  std::string tuned_report() const;  // JSON object: shape key -> tile label
+
   // --- per-kernel profiling with HIP events on `stream`; with a non-empty
   // filter only kernels whose label contains it are timed
   bool profile = false;
@@ -168,7 +175,11 @@ class Engine {
   std::string profile_report();  // JSON aggregate per kernel label; clears the records
 
   // workspace sizes (bytes) currently held
-  size_t workspace_bytes() const { return ws_bytes_[0] + ws_bytes_[1] + ws_bytes_[2] + ws_bytes_[3] + ws_bytes_[4] + ws_bytes_[5]; }
+  size_t workspace_bytes() const {
+    size_t b = 0;
+    for (size_t x : ws_bytes_) b += x;
+    return b;
+  }
   void* workspace(int slot, size_t bytes);
 
   // device buffers for tables
@@ -192,8 +203,9 @@ class Engine {
   bool is_cacheable(const std::string& name) const {
     return std::find(cacheable_.begin(), cacheable_.end(), name) != cacheable_.end();
   }
-  void* ws_[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
-  size_t ws_bytes_[6] = {0, 0, 0, 0, 0, 0};
+  void* ws_[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t ws_bytes_[7] = {0, 0, 0, 0, 0, 0, 0};
+  std::map<std::string, std::pair<int, std::string>> tuned_;  // shape key -> (tile, label)
   uint32_t* d_binom_ = nullptr;
   uint8_t* d_dec_[kMaxGroup + 1] = {};
   struct ProfRec {

@@ -66,13 +66,16 @@ void Context::release_eom() {
   eom_.reset();
 }
 
-void Context::setup_eom(int kind) {
+void Context::setup_eom(int kind, int nb) {
   FNO_REQUIRE(cc_ready, kESTATE, "EOM needs ground-state amplitudes");
-  if (eom_ && eom_->kind == kind && eom_->ready) return;
+  FNO_REQUIRE(nb >= 1, kEINVAL, "bad EOM block size");
+  if (eom_ && eom_->kind == kind && eom_->nb == nb && eom_->ready) return;
   release_eom();
   Engine& e = *eng;
+  sz_.n['b'] = nb;
   auto sp = std::make_unique<EomSpace>();
   sp->kind = kind;
+  sp->nb = nb;
   sp->tab = tables_for(kind);
   const EomTables& t = sp->tab;
   auto make = [&](const char* decl) {
@@ -109,7 +112,7 @@ void Context::setup_eom(int kind) {
     B.np = t.blocks[b][1];
     B.name = t.in[b];
     B.size = (int64_t)binom_host(nocc, B.nh) * (int64_t)binom_host(nvir, B.np);
-    FNO_REQUIRE(B.size == e.get(t.in[b])->elems && B.size == e.get(t.out[b])->elems, kEDEVICE,
+    FNO_REQUIRE(B.size * nb == e.get(t.in[b])->elems && B.size * nb == e.get(t.out[b])->elems, kEDEVICE,
                 "EOM block layout mismatch");
     B.offset = sp->dim;
     sp->dim += B.size;
@@ -171,48 +174,103 @@ size_t Context::eom_size(int kind) {
   return (size_t)d;
 }
 
-// sigma = (H-bar - E_CC) R on device vectors (packed R layout)
-static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double* r, double* sigma, Prec prec) {
+// sigma_j = (H-bar - E_CC) r_j for `count` <= nb device vectors (packed R
+// layout, leading dimensions ldr / lds); the block tensors hold nb vectors
+// each, those beyond `count` are zero.
+static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double* r, int64_t ldr, int count,
+                      double* sigma, int64_t lds, Prec prec) {
   const EomTables& t = sp.tab;
-  for (int b = 0; b < t.nblocks; ++b)
-    launch_axpby(e.get(t.in[b])->d, r + sp.blocks[b].offset, (double)t.sign[b], 0.0, sp.blocks[b].size, e.stream);
-  for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
-  e.stats.clear();
-  e.record = true;
-  // the R blocks are fixed during one sigma: share their expansions
-  std::vector<std::string> inputs;
-  for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
-  CacheScope cache(e, inputs);
-  for (int i = 0; i < t.nterms; ++i) {
-    std::string s(t.terms[i]);
-    // contractions that read or write the R3 block run in the requested precision
-    bool tri = false;
-    for (int b = 0; b < t.nblocks; ++b)
-      if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
-        tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
-        tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
-      }
-    e.prec = tri ? prec : Prec::FP64;
-    e.term(s);
+  FNO_REQUIRE(count >= 1 && count <= sp.nb, kEINVAL, "bad EOM block count");
+  for (int b = 0; b < t.nblocks; ++b) {
+    const int64_t sz = sp.blocks[b].size;
+    double* in = e.get(t.in[b])->d;
+    for (int j = 0; j < sp.nb; ++j) {
+      if (j < count)
+        launch_axpby(in + j * sz, r + j * ldr + sp.blocks[b].offset, (double)t.sign[b], 0.0, sz, e.stream);
+      else
+        launch_fill(in + j * sz, 0.0, sz, e.stream);
+    }
   }
-  e.prec = Prec::FP64;
-  e.record = false;
-  for (int b = 0; b < t.nblocks; ++b)
-    launch_axpby(sigma + sp.blocks[b].offset, e.get(t.out[b])->d, (double)t.sign[b], 0.0, sp.blocks[b].size,
-                 e.stream);
-  double tri = 0, all = 0;
-  for (auto& st : e.stats) {
-    all += st.flops;
-    for (int b = 0; b < t.nblocks; ++b)
-      if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
-          (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
-           st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
-        tri += st.flops;
-        break;
+  auto sweep = [&]() {
+    for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
+    e.stats.clear();
+    e.record = true;
+    // the R blocks are fixed during one sigma: share their expansions
+    std::vector<std::string> inputs;
+    for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
+    CacheScope cache(e, inputs);
+    for (int i = 0; i < t.nterms; ++i) {
+      std::string s(t.terms[i]);
+      // contractions that read or write the R3 block run in the requested precision
+      bool tri = false;
+      for (int b = 0; b < t.nblocks; ++b)
+        if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
+          tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
+          tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
+        }
+      e.prec = tri ? prec : Prec::FP64;
+      e.term(s);
+    }
+    e.prec = Prec::FP64;
+    e.record = false;
+    double tf = 0, af = 0;
+    for (auto& st : e.stats) {
+      af += st.flops;
+      for (int b = 0; b < t.nblocks; ++b)
+        if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
+            (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
+             st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
+          tf += st.flops;
+          break;
+        }
+    }
+    sp.sweep_tri = tf;
+    sp.sweep_all = af;
+  };
+  const bool graphs = c.use_graphs;
+  if (graphs && sp.prog.valid() && sp.prog.epoch == e.epoch && sp.prog.prec == (int)prec &&
+      sp.prog.profiled == e.profile && sp.prog.filter == e.profile_filter) {
+    e.replay(sp.prog);
+  } else {
+    sp.prog.clear();
+    bool done = false;
+    if (graphs && sp.stable && sp.stable_epoch == e.epoch && sp.stable_prec == (int)prec &&
+        sp.stable_profiled == e.profile && sp.stable_filter == e.profile_filter) {
+      e.begin_record(sp.prog);
+      sp.prog.prec = (int)prec;
+      bool recorded = false;
+      try {
+        sweep();
+        e.end_record(sp.prog);
+        recorded = true;
+      } catch (const Error&) {
+        e.abort_record();
+        e.prec = Prec::FP64;
+        sp.stable = false;
       }
+      if (recorded && sp.prog.valid()) {
+        e.replay(sp.prog);
+        done = true;
+      }
+    }
+    if (!done) {
+      const uint64_t before = e.epoch;
+      sweep();
+      sp.stable = e.epoch == before;
+      sp.stable_epoch = e.epoch;
+      sp.stable_prec = (int)prec;
+      sp.stable_profiled = e.profile;
+      sp.stable_filter = e.profile_filter;
+    }
   }
-  c.last_triples_flops = tri;
-  c.last_all_flops = all;
+  for (int b = 0; b < t.nblocks; ++b) {
+    const int64_t sz = sp.blocks[b].size;
+    const double* out = e.get(t.out[b])->d;
+    for (int j = 0; j < count; ++j)
+      launch_axpby(sigma + j * lds + sp.blocks[b].offset, out + j * sz, (double)t.sign[b], 0.0, sz, e.stream);
+  }
+  c.last_triples_flops = sp.sweep_tri;
+  c.last_all_flops = sp.sweep_all;
 }
 
 void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len) {
@@ -221,12 +279,12 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
   if (eom_) eom_->ready = eom_->ready && eom_->kind == kind;
   // amplitudes may have been changed through fno_set_amplitudes: rebuild the intermediates
   release_eom();
-  setup_eom(kind);
+  setup_eom(kind, 1);
   Engine& e = *eng;
   double* dr = alloc((int64_t)len);
   double* ds = alloc((int64_t)len);
   FNO_HIP(hipMemcpy(dr, r, len * sizeof(double), hipMemcpyHostToDevice));
-  eom_apply(*this, e, *eom_, dr, ds, p);
+  eom_apply(*this, e, *eom_, dr, (int64_t)len, 1, ds, (int64_t)len, p);
   FNO_HIP(hipMemcpy(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost));
   FNO_HIP(hipFree(dr));
   FNO_HIP(hipFree(ds));
@@ -237,44 +295,33 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
 // Block Davidson for the lowest right eigenpairs (by real part) of the
 // nonsymmetric EOM matrix.  Subspace vectors and sigma vectors live on the
 // device; the small projected matrix G = V^T S is diagonalised on the host.
-int Context::eom(int kind, const EOMOptions& opt, EOMResult& res) {
+// The solver is resumable: dav_sigma issues the sigma vectors of the pending
+// subspace vectors on the context's stream without waiting, dav_update does
+// one iteration's host work, so that several contexts can be driven in
+// lockstep with their device work overlapping (fno_batch_eom).
+
+Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   FNO_REQUIRE(cc_done, kESTATE, "fno_eom needs a converged fno_ccsdt first");
   FNO_REQUIRE(opt.nroots >= 1 && opt.max_iter >= 1, kEINVAL, "bad EOM options");
   release_eom();
-  setup_eom(kind);
+  // sigma vectors are computed in blocks of up to nroots (at most 16) vectors
+  setup_eom(kind, std::min(std::max(opt.block > 0 ? opt.block : opt.nroots, 1), 16));
   EomSpace& sp = *eom_;
   Engine& e = *eng;
-  const int64_t dim = sp.dim;
-  const int nroots = opt.nroots;
-  FNO_REQUIRE(nroots <= dim, kEINVAL, "more roots than the EOM space has states");
-  const int max_sub = std::min(std::max(opt.max_sub > 0 ? opt.max_sub : 8 * nroots, 2 * nroots), 512);
-  double* V = alloc((int64_t)max_sub * dim);
-  double* S = alloc((int64_t)max_sub * dim);
-  double* X = alloc((int64_t)nroots * dim);
-  double* W = alloc(dim);                 // work vector
-  double* dco = alloc(std::max(max_sub, nroots) + 8);
-  double* dots = alloc(std::max(max_sub, 1) + 8);
-  std::vector<double*> mine = {V, S, X, W, dco, dots};
-  auto release = [&]() {
-    FNO_HIP(hipStreamSynchronize(e.stream));
-    for (double* p : mine) {
-      owned_.erase(std::remove(owned_.begin(), owned_.end(), p), owned_.end());
-      (void)hipFree(p);
-    }
-  };
-  auto vec = [&](double* base, int j) { return base + (int64_t)j * dim; };
-  auto dots_with = [&](const double* xs, int nvec, const double* y, std::vector<double>& out) {
-    out.assign(nvec, 0.0);
-    if (nvec == 0) return;
-    launch_dots(xs, dim, nvec, y, dim, scratch_, dots, e.stream);
-    FNO_HIP(hipMemcpyAsync(out.data(), dots, nvec * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-    FNO_HIP(hipStreamSynchronize(e.stream));
-  };
-  auto combine = [&](double* y, const double* xs, const std::vector<double>& c, double alpha, double beta) {
-    FNO_HIP(hipMemcpyAsync(dco, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
-    launch_combine(y, xs, dim, dco, (int)c.size(), alpha, beta, dim, e.stream);
-    FNO_HIP(hipStreamSynchronize(e.stream));
-  };
+  auto d = std::make_unique<Davidson>();
+  d->kind = kind;
+  d->opt = opt;
+  d->dim = sp.dim;
+  d->nroots = opt.nroots;
+  FNO_REQUIRE(d->nroots <= d->dim, kEINVAL, "more roots than the EOM space has states");
+  d->max_sub = std::min(std::max(opt.max_sub > 0 ? opt.max_sub : 8 * d->nroots, 2 * d->nroots), 512);
+  const int64_t dim = d->dim;
+  d->V = alloc((int64_t)d->max_sub * dim);
+  d->S = alloc((int64_t)d->max_sub * dim);
+  d->X = alloc((int64_t)d->nroots * dim);
+  d->W = alloc(dim);
+  d->dco = alloc(std::max(d->max_sub, d->nroots) + 8);
+  d->dots = alloc(std::max(d->max_sub, 1) + 8);
   // guesses: unit vectors on the lowest zeroth-order diagonal entries of the
   // principal block, continued into the other blocks when it is too small
   std::vector<double> dall(dim);
@@ -287,115 +334,180 @@ int Context::eom(int kind, const EOMOptions& opt, EOMResult& res) {
     if (pa != pb) return pa;
     return dall[a] < dall[b];
   });
-  int nv = 0;
-  for (int k = 0; k < nroots; ++k) {
-    launch_fill(vec(V, nv), 0.0, dim, e.stream);
+  for (int k = 0; k < d->nroots; ++k) {
+    double* v = d->V + (int64_t)k * dim;
+    launch_fill(v, 0.0, dim, e.stream);
     double one = 1.0;
-    FNO_HIP(hipMemcpyAsync(vec(V, nv) + order[k], &one, sizeof(double), hipMemcpyHostToDevice, e.stream));
+    FNO_HIP(hipMemcpyAsync(v + order[k], &one, sizeof(double), hipMemcpyHostToDevice, e.stream));
     FNO_HIP(hipStreamSynchronize(e.stream));
-    ++nv;
   }
-  int ns = 0;  // sigma vectors computed
-  std::vector<double> G((size_t)max_sub * max_sub, 0.0);
-  std::vector<double> theta(nroots, 0.0), theta_old(nroots, INFINITY), rn(nroots, INFINITY);
-  int it = 0, status = kENOCONV;
-  for (it = 1; it <= opt.max_iter; ++it) {
-    for (; ns < nv; ++ns) eom_apply(*this, e, sp, vec(V, ns), vec(S, ns), opt.prec);
-    // G[i][j] = v_i . s_j (all entries; the subspace is small)
-    for (int j = 0; j < nv; ++j) {
-      std::vector<double> col;
-      dots_with(V, nv, vec(S, j), col);
-      for (int i = 0; i < nv; ++i) G[(size_t)i * max_sub + j] = col[i];
-    }
-    std::vector<double> Gs((size_t)nv * nv);
-    for (int i = 0; i < nv; ++i)
-      for (int j = 0; j < nv; ++j) Gs[(size_t)i * nv + j] = G[(size_t)i * max_sub + j];
-    std::vector<double> wr, wi;
-    FNO_REQUIRE(nonsym_eigvals(nv, Gs, wr, wi), kENOCONV, "subspace eigenproblem failed");
-    std::vector<int> idx(nv);
-    for (int i = 0; i < nv; ++i) idx[i] = i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return wr[a] < wr[b]; });
-    // Ritz vectors and residuals
-    std::vector<std::vector<double>> Y(nroots);
+  d->nv = d->nroots;
+  d->G.assign((size_t)d->max_sub * d->max_sub, 0.0);
+  d->theta.assign(d->nroots, 0.0);
+  d->theta_old.assign(d->nroots, INFINITY);
+  d->rn.assign(d->nroots, INFINITY);
+  dav_ = std::move(d);
+  return dav_.get();
+}
+
+void Context::dav_sigma(Davidson& d) {
+  if (d.done) return;
+  EomSpace& sp = *eom_;
+  Engine& e = *eng;
+  while (d.ns < d.nv) {
+    const int cnt = std::min(sp.nb, d.nv - d.ns);
+    eom_apply(*this, e, sp, d.V + (int64_t)d.ns * d.dim, d.dim, cnt, d.S + (int64_t)d.ns * d.dim, d.dim, d.opt.prec);
+    d.ns += cnt;
+  }
+}
+
+bool Context::dav_update(Davidson& d) {
+  if (d.done) return true;
+  EomSpace& sp = *eom_;
+  Engine& e = *eng;
+  const int64_t dim = d.dim;
+  const int nroots = d.nroots, max_sub = d.max_sub;
+  auto vec = [&](double* base, int j) { return base + (int64_t)j * dim; };
+  auto dots_with = [&](const double* xs, int nvec, const double* y, std::vector<double>& out) {
+    out.assign(nvec, 0.0);
+    if (nvec == 0) return;
+    launch_dots(xs, dim, nvec, y, dim, scratch_, d.dots, e.stream);
+    FNO_HIP(hipMemcpyAsync(out.data(), d.dots, nvec * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  };
+  auto combine = [&](double* y, const double* xs, const std::vector<double>& c, double alpha, double beta) {
+    FNO_HIP(hipMemcpyAsync(d.dco, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
+    launch_combine(y, xs, dim, d.dco, (int)c.size(), alpha, beta, dim, e.stream);
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  };
+  ++d.it;
+  const int nv = d.nv;
+  // G[i][j] = v_i . s_j (all entries; the subspace is small)
+  for (int j = 0; j < nv; ++j) {
+    std::vector<double> col;
+    dots_with(d.V, nv, vec(d.S, j), col);
+    for (int i = 0; i < nv; ++i) d.G[(size_t)i * max_sub + j] = col[i];
+  }
+  std::vector<double> Gs((size_t)nv * nv);
+  for (int i = 0; i < nv; ++i)
+    for (int j = 0; j < nv; ++j) Gs[(size_t)i * nv + j] = d.G[(size_t)i * max_sub + j];
+  std::vector<double> wr, wi;
+  FNO_REQUIRE(nonsym_eigvals(nv, Gs, wr, wi), kENOCONV, "subspace eigenproblem failed");
+  std::vector<int> idx(nv);
+  for (int i = 0; i < nv; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return wr[a] < wr[b]; });
+  // Ritz vectors and residuals
+  std::vector<std::vector<double>> Y(nroots);
+  for (int k = 0; k < nroots; ++k) {
+    d.theta[k] = wr[idx[k]];
+    inverse_iteration(nv, Gs, d.theta[k], Y[k]);
+    combine(vec(d.X, k), d.V, Y[k], 1.0, 0.0);
+    std::vector<double> nn;
+    dots_with(vec(d.X, k), 1, vec(d.X, k), nn);
+    const double nrm = std::sqrt(nn[0]);
+    for (double& y : Y[k]) y /= nrm;
+    launch_axpby(vec(d.X, k), vec(d.X, k), 1.0 / nrm, 0.0, dim, e.stream);
+  }
+  bool all_conv = true;
+  for (int k = 0; k < nroots; ++k) {
+    // W = S y - theta x
+    combine(d.W, d.S, Y[k], 1.0, 0.0);
+    launch_axpby(d.W, vec(d.X, k), -d.theta[k], 1.0, dim, e.stream);
+    std::vector<double> nn;
+    dots_with(d.W, 1, d.W, nn);
+    d.rn[k] = std::sqrt(nn[0]);
+    all_conv = all_conv && d.rn[k] < d.opt.r_tol && std::fabs(d.theta[k] - d.theta_old[k]) < d.opt.e_tol;
+    if (!std::isfinite(d.rn[k])) throw Error(kENONFINITE, "non-finite EOM residual");
+  }
+  d.theta_old = d.theta;
+  if (all_conv) {
+    d.status = kOK;
+    d.done = true;
+    return true;
+  }
+  if (d.it >= d.opt.max_iter) {
+    d.done = true;
+    return true;
+  }
+  if (d.nv + nroots > max_sub) {
+    // collapse onto the orthonormalised Ritz vectors
+    int m = 0;
     for (int k = 0; k < nroots; ++k) {
-      theta[k] = wr[idx[k]];
-      inverse_iteration(nv, Gs, theta[k], Y[k]);
-      combine(vec(X, k), V, Y[k], 1.0, 0.0);
-      std::vector<double> nn;
-      dots_with(vec(X, k), 1, vec(X, k), nn);
-      const double nrm = std::sqrt(nn[0]);
-      for (double& y : Y[k]) y /= nrm;
-      launch_axpby(vec(X, k), vec(X, k), 1.0 / nrm, 0.0, dim, e.stream);
-    }
-    bool all_conv = true;
-    std::vector<bool> conv(nroots);
-    for (int k = 0; k < nroots; ++k) {
-      // W = S y - theta x
-      combine(W, S, Y[k], 1.0, 0.0);
-      launch_axpby(W, vec(X, k), -theta[k], 1.0, dim, e.stream);
-      std::vector<double> nn;
-      dots_with(W, 1, W, nn);
-      rn[k] = std::sqrt(nn[0]);
-      conv[k] = rn[k] < opt.r_tol && std::fabs(theta[k] - theta_old[k]) < opt.e_tol;
-      all_conv = all_conv && conv[k];
-      if (!std::isfinite(rn[k])) {
-        release();
-        throw Error(kENONFINITE, "non-finite EOM residual");
-      }
-    }
-    theta_old = theta;
-    if (all_conv) {
-      status = kOK;
-      break;
-    }
-    if (nv + nroots > max_sub) {
-      // collapse onto the orthonormalised Ritz vectors
-      int m = 0;
-      for (int k = 0; k < nroots; ++k) {
-        launch_axpby(vec(V, m), vec(X, k), 1.0, 0.0, dim, e.stream);
-        for (int pass = 0; pass < 2; ++pass) {
-          std::vector<double> c;
-          dots_with(V, m, vec(V, m), c);
-          if (m) combine(vec(V, m), V, c, -1.0, 1.0);
-        }
-        std::vector<double> nn;
-        dots_with(vec(V, m), 1, vec(V, m), nn);
-        if (std::sqrt(nn[0]) > 1e-10) {
-          launch_axpby(vec(V, m), vec(V, m), 1.0 / std::sqrt(nn[0]), 0.0, dim, e.stream);
-          ++m;
-        }
-      }
-      nv = m;
-      ns = 0;
-      continue;
-    }
-    // preconditioned residuals, orthogonalised twice (classical Gram-Schmidt)
-    for (int k = 0; k < nroots; ++k) {
-      if (rn[k] < opt.r_tol) continue;
-      if (nv >= max_sub) break;
-      combine(W, S, Y[k], 1.0, 0.0);
-      launch_axpby(W, vec(X, k), -theta[k], 1.0, dim, e.stream);
-      launch_precond(vec(V, nv), W, sp.diag, theta[k], dim, e.stream);
+      launch_axpby(vec(d.V, m), vec(d.X, k), 1.0, 0.0, dim, e.stream);
       for (int pass = 0; pass < 2; ++pass) {
         std::vector<double> c;
-        dots_with(V, nv, vec(V, nv), c);
-        combine(vec(V, nv), V, c, -1.0, 1.0);
+        dots_with(d.V, m, vec(d.V, m), c);
+        if (m) combine(vec(d.V, m), d.V, c, -1.0, 1.0);
       }
       std::vector<double> nn;
-      dots_with(vec(V, nv), 1, vec(V, nv), nn);
-      const double nrm = std::sqrt(nn[0]);
-      if (nrm > 1e-10) {
-        launch_axpby(vec(V, nv), vec(V, nv), 1.0 / nrm, 0.0, dim, e.stream);
-        ++nv;
+      dots_with(vec(d.V, m), 1, vec(d.V, m), nn);
+      if (std::sqrt(nn[0]) > 1e-10) {
+        launch_axpby(vec(d.V, m), vec(d.V, m), 1.0 / std::sqrt(nn[0]), 0.0, dim, e.stream);
+        ++m;
       }
     }
+    d.nv = m;
+    d.ns = 0;
+    return false;
   }
-  res.omega = theta;
-  res.res_norm = rn;
-  res.iters = std::min(it, opt.max_iter);
-  res.converged = status == kOK;
-  release();
-  return status;
+  // preconditioned residuals, orthogonalised twice (classical Gram-Schmidt)
+  for (int k = 0; k < nroots; ++k) {
+    if (d.rn[k] < d.opt.r_tol) continue;
+    if (d.nv >= max_sub) break;
+    combine(d.W, d.S, Y[k], 1.0, 0.0);
+    launch_axpby(d.W, vec(d.X, k), -d.theta[k], 1.0, dim, e.stream);
+    launch_precond(vec(d.V, d.nv), d.W, sp.diag, d.theta[k], dim, e.stream);
+    for (int pass = 0; pass < 2; ++pass) {
+      std::vector<double> c;
+      dots_with(d.V, d.nv, vec(d.V, d.nv), c);
+      combine(vec(d.V, d.nv), d.V, c, -1.0, 1.0);
+    }
+    std::vector<double> nn;
+    dots_with(vec(d.V, d.nv), 1, vec(d.V, d.nv), nn);
+    const double nrm = std::sqrt(nn[0]);
+    if (nrm > 1e-10) {
+      launch_axpby(vec(d.V, d.nv), vec(d.V, d.nv), 1.0 / nrm, 0.0, dim, e.stream);
+      ++d.nv;
+    }
+  }
+  return false;
+}
+
+int Context::dav_end(EOMResult& res) {
+  if (!dav_) return kESTATE;
+  Davidson& d = *dav_;
+  res.omega = d.theta;
+  res.res_norm = d.rn;
+  res.iters = std::min(d.it, d.opt.max_iter);
+  res.converged = d.status == kOK;
+  const int st = d.status;
+  dav_release();
+  return st;
+}
+
+void Context::dav_release() {
+  if (!dav_) return;
+  Davidson& d = *dav_;
+  (void)hipStreamSynchronize(eng->stream);
+  for (double* p : {d.V, d.S, d.X, d.W, d.dco, d.dots}) {
+    owned_.erase(std::remove(owned_.begin(), owned_.end(), p), owned_.end());
+    (void)hipFree(p);
+  }
+  dav_.reset();
+}
+
+int Context::eom(int kind, const EOMOptions& opt, EOMResult& res) {
+  Davidson* d = dav_begin(kind, opt);
+  try {
+    for (;;) {
+      dav_sigma(*d);
+      if (dav_update(*d)) break;
+    }
+  } catch (...) {
+    dav_release();
+    throw;
+  }
+  return dav_end(res);
 }
 
 }  // namespace fno

@@ -1,5 +1,6 @@
 // State of one EOM variant: R-space layout, tensors of the sigma terms, Davidson storage.
 #pragma once
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -32,9 +33,31 @@ struct Context::EomSpace {
   EomTables tab{};
   std::vector<Block> blocks;   // (nh, np), packed sizes and offsets in the R vector
   int64_t dim = 0;
+  int nb = 1;                  // vectors per sigma evaluation (batch slot of every R-derived tensor)
   double* diag = nullptr;      // zeroth-order diagonal sum e_particles - sum e_holes
   std::vector<std::string> created;  // engine tensors owned by this variant
   bool ready = false;
+  // the sigma sweep (zeroing + terms) replayed from hipGraphs once a
+  // host-launched sweep allocated nothing (same rules as the CC residual)
+  Program prog;
+  bool stable = false;
+  uint64_t stable_epoch = 0;
+  int stable_prec = -1;
+  bool stable_profiled = false;
+  std::string stable_filter;
+  double sweep_tri = 0, sweep_all = 0;  // algorithmic flops of one sweep
+};
+
+// State of one resumable Davidson solve (eom.cpp).
+struct Context::Davidson {
+  int kind = 0;
+  EOMOptions opt;
+  int64_t dim = 0;
+  int nroots = 0, max_sub = 0;
+  double *V = nullptr, *S = nullptr, *X = nullptr, *W = nullptr, *dco = nullptr, *dots = nullptr;
+  int nv = 0, ns = 0, it = 0, status = kENOCONV;
+  bool done = false;
+  std::vector<double> G, theta, theta_old, rn;
 };
 
 }  // namespace fno

@@ -1,0 +1,82 @@
+"""Batched EOM over uneven-size instances, Davidson root blocks, graph replay of
+the sigma sweep and the GEMM tile autotuner, against the unbatched paths.
+
+Batched instances compute exactly what the single-instance solver computes (same
+kernels in the same order on each context): roots and iteration counts must be
+bitwise equal.  Root blocks change GEMM shapes (rounding only): 1e-10 Eh.
+"""
+import numpy as np
+import pytest
+
+from synthetic import make_hamiltonian
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2509_14157_amd as P
+    return P
+
+
+def _solved(P, o, v, seed):
+    h = make_hamiltonian(o, v, seed)
+    c = P.Context(0)
+    c.load_hamiltonian(h.fock, h.eri, o)
+    c.ccsdt(r_tol=1e-9, e_tol=1e-11)
+    return c
+
+
+@pytest.mark.parametrize("kind", ["IP", "EA", "DIP", "DEA"])
+def test_batch_matches_single(P, kind):
+    print(f"batched {kind}", flush=True)
+    ctxs = [_solved(P, o, v, s) for o, v, s in [(4, 8, 41), (5, 6, 42), (4, 9, 43)]]
+    try:
+        single = [c.eom(kind, nroots=3, r_tol=1e-7, e_tol=1e-10) for c in ctxs]
+        batch = P.batch_eom(ctxs, kind, nroots=3, r_tol=1e-7, e_tol=1e-10)
+        for s, b in zip(single, batch):
+            assert s["converged"] and b["converged"]
+            assert b["iters"] == s["iters"]
+            assert np.array_equal(b["omega"], s["omega"])
+    finally:
+        for c in ctxs:
+            c.close()
+
+
+@pytest.mark.parametrize("kind", ["EA", "DIP"])
+def test_root_block_matches_single_vectors(P, kind):
+    print(f"root block {kind}", flush=True)
+    c = _solved(P, 5, 8, 44)
+    with c:
+        one = c.eom(kind, nroots=4, r_tol=1e-8, e_tol=1e-11, block=1)
+        blk = c.eom(kind, nroots=4, r_tol=1e-8, e_tol=1e-11, block=4)
+    assert one["converged"] and blk["converged"]
+    assert np.abs(np.sort(one["omega"]) - np.sort(blk["omega"])).max() < 1e-10
+
+
+@pytest.mark.parametrize("kind,prec", [("IP", "fp64"), ("DEA", "fp32")])
+def test_sigma_graph_replay_matches_host_launches(P, kind, prec):
+    print(f"sigma graph replay {kind} {prec}", flush=True)
+    c = _solved(P, 4, 7, 45)
+    with c:
+        c.set_graphs(False)
+        ref = c.eom(kind, nroots=3, r_tol=1e-7, e_tol=1e-10, prec=prec, allow_noconv=True)
+        c.set_graphs(True)
+        got = c.eom(kind, nroots=3, r_tol=1e-7, e_tol=1e-10, prec=prec, allow_noconv=True)
+    assert got["iters"] == ref["iters"]
+    assert np.array_equal(got["omega"], ref["omega"])
+
+
+def test_autotuned_tiles_give_the_same_energy(P):
+    print("autotune", flush=True)
+    h = make_hamiltonian(6, 20, 46)
+    with P.Context(0) as c:
+        c.load_hamiltonian(h.fock, h.eri, 6)
+        e0 = c.ccsdt(r_tol=1e-9, e_tol=1e-11)["e_tot"]
+        c.set_autotune(True)
+        c.profile(True)
+        e1 = c.ccsdt(r_tol=1e-9, e_tol=1e-11)["e_tot"]
+        rep = c.profile_report()
+        c.profile(False)
+    assert abs(e1 - e0) < 1e-10
+    assert len(rep["tuned"]) > 0
