@@ -24,6 +24,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -101,6 +103,68 @@ def copy_calibration(nbytes=512 << 20, reps=5):
     print(json.dumps({"copy_bytes": nbytes, "reads_bytes": nbytes, "writes_bytes": nbytes, "reps": reps}), flush=True)
 
 
+def bench_batched(args, nroots=4, eom_prec="fp32"):
+    """16 uneven-size FNO instances (o ~ U{6..12}, v ~ U{24..48} kept of ceil(5v/3)), ground state in
+    FP64 (at most 30 iterations: the sigma cost does not depend on how far they converged), then
+    DIP (4h2p) and DEA (4p2h) roots with FP32 triples contractions and FP64 Davidson:
+    once through fno_batch_eom, once one instance after another.  value = algorithmic R3-sigma
+    flops of the batched solve / its wall time."""
+    import paper_2509_14157_amd as P
+    from synthetic import batch_instance_shapes, full_virtuals_for, make_hamiltonian
+
+    shapes = batch_instance_shapes()
+    ctxs = []
+    t0 = time.perf_counter()
+    for o, v, seed in shapes:
+        h = make_hamiltonian(o, full_virtuals_for(v), seed)
+        c = P.Context(0)
+        c.load_hamiltonian(h.fock, h.eri, o)
+        kept, _, _ = c.truncate(1.0, v)
+        assert kept == v
+        g = c.ccsdt(r_tol=1e-8, e_tol=1e-10, max_iter=30, allow_noconv=True)
+        ctxs.append(c)
+        _log(f"[bench] instance o={o} v={v} (v_full={full_virtuals_for(v)}) ground state: "
+             f"{g['iters']} iterations, residual {g['res_norm']:.1e}")
+    t_gs = time.perf_counter() - t0
+    kinds = {}
+    # roots to 1e-6 Eh; the residual norm of FP32 sigma vectors has a floor near 1e-5 at these sizes
+    opts = dict(nroots=nroots, prec=eom_prec, r_tol=1e-3, e_tol=1e-6, max_iter=40, allow_noconv=True)
+    for kind in ("DIP", "DEA"):
+        # warm-up (plans, workspaces, graph recordings) on every context
+        P.batch_eom(ctxs, kind, **dict(opts, max_iter=2))
+        t0 = time.perf_counter()
+        bres = P.batch_eom(ctxs, kind, **opts)
+        t_batch = time.perf_counter() - t0
+        flops = sum(c.last_flops()[0] for c in ctxs)
+        t0 = time.perf_counter()
+        sres = [c.eom(kind, **opts) for c in ctxs]
+        t_seq = time.perf_counter() - t0
+        same = all(np.array_equal(b["omega"], s_["omega"]) and b["iters"] == s_["iters"]
+                   for b, s_ in zip(bres, sres))
+        kinds[kind] = {"batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
+                       "speedup": round(t_seq / t_batch, 3), "triples_gflop": round(flops / 1e9, 2),
+                       "tflops_batched": round(flops / t_batch / 1e12, 3),
+                       "iters": [b["iters"] for b in bres], "converged": all(b["converged"] for b in bres),
+                       "identical_to_sequential": bool(same)}
+        _log(f"[bench] {kind}: batched {t_batch:.3f} s, sequential {t_seq:.3f} s, "
+             f"{flops / 1e9:.1f} GF -> {flops / t_batch / 1e12:.2f} TFLOP/s")
+    for c in ctxs:
+        c.close()
+    tot_f = sum(k["triples_gflop"] for k in kinds.values()) * 1e9
+    tot_t = sum(k["batched_s"] for k in kinds.values())
+    line = {
+        "metric": "triples-contraction TFLOP/s (% MFMA peak) and s/iteration, FP64 vs mixed",
+        "value": round(tot_f / tot_t / 1e12, 4), "unit": "TFLOP/s", "n_gpus": 1,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched FNO-DIP/DEA-EOM-CCSDT: 16 instances o~U{6..12}, v~U{24..48} "
+                               f"(seeds 400-415), {nroots} roots, FP32 triples, FP64 Davidson",
+                   "instances": [[o, v] for o, v, _ in shapes], "ground_state_s": round(t_gs, 3)},
+        "per_kind": kinds,
+        "pct_fp32_mfma_peak": round(100 * tot_f / tot_t / 1e12 / PEAK_TFLOPS["fp32"], 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,9 +176,18 @@ def main():
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
+    ap.add_argument("--workload", default="ccsdt", choices=["ccsdt", "batched"],
+                    help="ccsdt: the o=10/v=59 FNO-CCSDT iteration (default); batched: 16 uneven FNO instances, "
+                         "DIP and DEA roots, batched against one instance after another")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "batched":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        bench_batched(args)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

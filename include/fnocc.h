@@ -177,8 +177,10 @@ int fno_cc_residual(fno_ctx *ctx, fno_prec prec, double *r1, double *r2, double 
 size_t fno_eom_size(const fno_ctx *ctx, fno_eom_kind kind);
 int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *r, double *sigma, size_t len);
 
-/* Kernel-level statistics of the last residual/sigma evaluation: algorithmic
- * GEMM flops (packed forms) of the triples contractions and of all terms. */
+/* Algorithmic GEMM flops (packed forms) of the triples contractions and of all
+ * terms: of one residual evaluation after fno_ccsdt / fno_cc_residual, of the
+ * sigma sweep after fno_eom_sigma, and summed over every sigma sweep of the
+ * solve after fno_eom / fno_batch_eom (per context). */
 int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops);
 
 /*

@@ -269,8 +269,8 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
     for (int j = 0; j < count; ++j)
       launch_axpby(sigma + j * lds + sp.blocks[b].offset, out + j * sz, (double)t.sign[b], 0.0, sz, e.stream);
   }
-  c.last_triples_flops = sp.sweep_tri;
-  c.last_all_flops = sp.sweep_all;
+  c.last_triples_flops += sp.sweep_tri;  // summed over the sweeps of a solve (reset by the caller)
+  c.last_all_flops += sp.sweep_all;
 }
 
 void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len) {
@@ -284,6 +284,7 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
   double* dr = alloc((int64_t)len);
   double* ds = alloc((int64_t)len);
   FNO_HIP(hipMemcpy(dr, r, len * sizeof(double), hipMemcpyHostToDevice));
+  last_triples_flops = last_all_flops = 0;
   eom_apply(*this, e, *eom_, dr, (int64_t)len, 1, ds, (int64_t)len, p);
   FNO_HIP(hipMemcpy(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost));
   FNO_HIP(hipFree(dr));
@@ -342,6 +343,7 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
     FNO_HIP(hipStreamSynchronize(e.stream));
   }
   d->nv = d->nroots;
+  last_triples_flops = last_all_flops = 0;  // summed over the sigma sweeps of this solve
   d->G.assign((size_t)d->max_sub * d->max_sub, 0.0);
   d->theta.assign(d->nroots, 0.0);
   d->theta_old.assign(d->nroots, INFINITY);

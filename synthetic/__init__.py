@@ -6,7 +6,7 @@ none of the coupled-cluster arithmetic; both the CPU oracle and the GPU
 library consume its output bytes.
 """
 from .hamiltonian import (SyntheticHamiltonian, make_hamiltonian, config_hamiltonian,
-                          CONFIGS, batch_instance_shapes)
+                          CONFIGS, batch_instance_shapes, full_virtuals_for)
 
 __all__ = ["SyntheticHamiltonian", "make_hamiltonian", "config_hamiltonian", "CONFIGS",
-           "batch_instance_shapes"]
+           "batch_instance_shapes", "full_virtuals_for"]
