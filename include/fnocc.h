@@ -90,7 +90,8 @@ typedef struct {
   int diis_n;       /* DIIS history length (0 disables), default 8 */
   int diis_start;   /* first iteration that extrapolates, default 3 */
   fno_prec prec;    /* precision of the triples contractions; solver stays FP64 */
-  int guess;        /* 0 = zero amplitudes (first step gives MP2) */
+  int guess;        /* 0 = zero amplitudes (first step gives MP2); 1 = learned T3 guess
+                       (needs fno_set_guess_model; see below) */
 } fno_cc_opts;
 void fno_cc_opts_default(fno_cc_opts *o);
 
@@ -237,6 +238,47 @@ size_t fno_debug_tensor_size(fno_ctx *ctx, const char *name);
 int fno_debug_tensor(fno_ctx *ctx, const char *name, double *buf, size_t len);
 int fno_debug_gemm(fno_ctx *ctx, fno_prec prec, int tile, long M, long N, long K, int a_kfast, int b_nfast,
                    double alpha, double beta, const double *A, const double *B, double *Cmat);
+
+/*
+ * Learned initial guess (CCSDT starting amplitudes).
+ *
+ * A small network (9 -> 256 -> 256 -> 2, SiLU) maps per-element features of
+ * the MP-style T3 guess x (two Jacobi steps from zero: T2 = MP2, T3 from its
+ * drivers) -- x and |x| in units of their RMS, the denominator, the six
+ * orbital energies -- to a correction of the guess (t3 = x + rms(x) y0) and a
+ * shift y1 of that element's Jacobi denominator (kept within [2D, D/2]).
+ * With fno_cc_opts.guess = 1 and a model set on the context, fno_ccsdt applies
+ * it after its second iteration; if the next residual norm is not smaller
+ * than the previous one, the plain guess and denominators are restored.
+ * Training (FP32, Adam) and inference (single-BF16 operands, FP32
+ * accumulation) run on the device with the library's kernels.
+ */
+typedef struct fno_mlp fno_mlp;
+long fno_mlp_num_params(void);                      /* float parameters of the network */
+int fno_mlp_create(int hip_device, fno_mlp **out);  /* deterministic initial weights */
+void fno_mlp_destroy(fno_mlp *net);
+const char *fno_mlp_last_error(const fno_mlp *net);
+/* append up to max_samples T3 elements (evenly strided) of a context holding
+ * a converged fno_ccsdt: features and targets (converged T3 and dressed
+ * one-body diagonal); the context's amplitudes are left as they were */
+int fno_mlp_collect(fno_mlp *net, fno_ctx *ctx, long max_samples);
+long fno_mlp_samples(const fno_mlp *net);
+/* minibatch Adam on the collected samples; loss = mean of the last 20 steps */
+int fno_mlp_train(fno_mlp *net, int steps, int batch, double lr, unsigned long seed, double *loss);
+int fno_mlp_save(fno_mlp *net, const char *path);   /* raw little-endian float32 with a header */
+int fno_mlp_load(fno_mlp *net, const char *path);
+/* copy the parameters out (set = 0) or in (set = 1); len = fno_mlp_num_params() */
+int fno_mlp_params(fno_mlp *net, float *buf, size_t len, int set);
+/* loss and parameter gradient of one batch (host arrays X[B][9], T[B][2]), FP32 */
+int fno_mlp_loss_grad(fno_mlp *net, const float *X, const float *T, long B, float *grad, double *loss);
+/* outputs Y[n][2] of the BF16 inference path for host features X[n][9] */
+int fno_mlp_predict(fno_mlp *net, const float *X, long n, float *Y);
+/* copy the first n collected samples out (host arrays X[n][9], T[n][2]) */
+int fno_mlp_dataset(fno_mlp *net, float *X, float *T, long n);
+/* network used by fno_ccsdt with guess = 1 (not owned; NULL clears) */
+int fno_set_guess_model(fno_ctx *ctx, fno_mlp *net);
+/* 1 if the last fno_ccsdt kept the learned guess, 0 if not (or none was tried) */
+int fno_last_guess_accepted(const fno_ctx *ctx);
 
 #ifdef __cplusplus
 }

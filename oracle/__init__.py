@@ -7,5 +7,6 @@ implementation of what the GPU library computes and shares no code with it:
 * ``det``  -- determinant-space brute force of the definitions (eqs 1-7) and FCI;
 * ``wick`` -- Wick's-theorem expansion of eq (5) and of the EOM sigma vectors;
 * ``cc``   -- CCSDT residuals/energy, Jacobi+DIIS, EOM sigma, Davidson, dense EOM;
-* ``fno``  -- MP2 amplitudes, virtual density and FNO truncation (eqs 8-10).
+* ``fno``  -- MP2 amplitudes, virtual density and FNO truncation (eqs 8-10);
+* ``mlp``  -- the learned-guess network (forward, backpropagation) and its training data.
 """

@@ -23,7 +23,10 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_profile_filter",
-           "fno_set_graphs", "fno_set_autotune", "fno_batch_eom", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
+           "fno_set_graphs", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
+           "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
+           "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
+           "fno_set_guess_model", "fno_last_guess_accepted", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
 
 
 class FnoError(RuntimeError):
@@ -83,6 +86,26 @@ def library() -> C.CDLL:
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_set_graphs.argtypes = [C.c_void_p, C.c_int]
         lib.fno_set_autotune.argtypes = [C.c_void_p, C.c_int]
+        fp = C.POINTER(C.c_float)
+        lib.fno_mlp_num_params.argtypes = []
+        lib.fno_mlp_num_params.restype = C.c_long
+        lib.fno_mlp_create.argtypes = [C.c_int, C.POINTER(C.c_void_p)]
+        lib.fno_mlp_destroy.argtypes = [C.c_void_p]
+        lib.fno_mlp_destroy.restype = None
+        lib.fno_mlp_last_error.argtypes = [C.c_void_p]
+        lib.fno_mlp_last_error.restype = C.c_char_p
+        lib.fno_mlp_collect.argtypes = [C.c_void_p, C.c_void_p, C.c_long]
+        lib.fno_mlp_samples.argtypes = [C.c_void_p]
+        lib.fno_mlp_samples.restype = C.c_long
+        lib.fno_mlp_train.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_double, C.c_ulong, dp]
+        lib.fno_mlp_save.argtypes = [C.c_void_p, C.c_char_p]
+        lib.fno_mlp_load.argtypes = [C.c_void_p, C.c_char_p]
+        lib.fno_mlp_params.argtypes = [C.c_void_p, fp, C.c_size_t, C.c_int]
+        lib.fno_mlp_loss_grad.argtypes = [C.c_void_p, fp, fp, C.c_long, fp, dp]
+        lib.fno_mlp_predict.argtypes = [C.c_void_p, fp, C.c_long, fp]
+        lib.fno_mlp_dataset.argtypes = [C.c_void_p, fp, fp, C.c_long]
+        lib.fno_set_guess_model.argtypes = [C.c_void_p, C.c_void_p]
+        lib.fno_last_guess_accepted.argtypes = [C.c_void_p]
         lib.fno_batch_eom.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(EOMOpts), dp, dp,
                                       C.POINTER(C.c_int)]
         lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
@@ -161,11 +184,12 @@ class Context:
 
     # ---- ground state
     def ccsdt(self, max_iter=100, r_tol=1e-8, e_tol=1e-10, diis_n=8, diis_start=3, prec="fp64",
-              allow_noconv=False):
+              allow_noconv=False, guess=0):
         o = CCOpts()
         self._lib.fno_cc_opts_default(C.byref(o))
         o.max_iter, o.r_tol, o.e_tol, o.diis_n, o.diis_start = max_iter, r_tol, e_tol, diis_n, diis_start
         o.prec = PREC[prec]
+        o.guess = guess
         ec, et, rn = C.c_double(), C.c_double(), C.c_double()
         it = C.c_int()
         st = self._check(self._lib.fno_ccsdt(self._h, C.byref(o), C.byref(ec), C.byref(et), C.byref(it),
@@ -202,6 +226,14 @@ class Context:
         """Time kernels with HIP events; `only` restricts it to names containing that text."""
         self._check(self._lib.fno_profile_filter(self._h, (only or "").encode()))
         self._check(self._lib.fno_profile(self._h, int(bool(on))))
+
+    def set_guess_model(self, net) -> None:
+        """Network used by ccsdt(guess=1); None clears it."""
+        self._check(self._lib.fno_set_guess_model(self._h, None if net is None else net._h))
+        self._guess_model = net  # keep it alive while the context may use it
+
+    def last_guess_accepted(self) -> bool:
+        return self._lib.fno_last_guess_accepted(self._h) == 1
 
     def set_autotune(self, on: bool = True) -> None:
         """Pick GEMM tiles per shape by timing every configuration on first use."""
@@ -267,6 +299,95 @@ class Context:
         st = self._check(self._lib.fno_eom(self._h, KIND[kind], C.byref(o), _dp(om), _dp(et), _dp(rn), C.byref(it)),
                          allow=(FNO_ENOCONV,) if allow_noconv else ())
         return dict(omega=om, e_tot=et, res_norm=rn, iters=it.value, converged=(st == FNO_OK))
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """The learned-guess network (fno_mlp): collect samples, train, save/load, predict."""
+
+    def __init__(self, device: int = 0):
+        self._lib = library()
+        h = C.c_void_p()
+        st = self._lib.fno_mlp_create(device, C.byref(h))
+        if st != FNO_OK:
+            raise FnoError(st, f"fno_mlp_create failed on device {device}")
+        self._h = h
+        self.num_params = int(self._lib.fno_mlp_num_params())
+
+    def close(self):
+        if self._h is not None:
+            self._lib.fno_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != FNO_OK:
+            raise FnoError(st, self._lib.fno_mlp_last_error(self._h).decode())
+        return st
+
+    def collect(self, ctx, max_samples: int = 1 << 16) -> None:
+        st = self._lib.fno_mlp_collect(self._h, ctx._h, int(max_samples))
+        if st != FNO_OK:
+            raise FnoError(st, ctx._lib.fno_last_error(ctx._h).decode())
+
+    @property
+    def samples(self) -> int:
+        return int(self._lib.fno_mlp_samples(self._h))
+
+    def train(self, steps: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0) -> float:
+        loss = C.c_double()
+        self._check(self._lib.fno_mlp_train(self._h, steps, batch, lr, seed, C.byref(loss)))
+        return loss.value
+
+    def save(self, path: str) -> None:
+        self._check(self._lib.fno_mlp_save(self._h, path.encode()))
+
+    def load(self, path: str) -> None:
+        self._check(self._lib.fno_mlp_load(self._h, path.encode()))
+
+    def params(self) -> np.ndarray:
+        buf = np.zeros(self.num_params, dtype=np.float32)
+        self._check(self._lib.fno_mlp_params(self._h, _fp(buf), buf.size, 0))
+        return buf
+
+    def set_params(self, p) -> None:
+        buf = np.ascontiguousarray(p, dtype=np.float32)
+        self._check(self._lib.fno_mlp_params(self._h, _fp(buf), buf.size, 1))
+
+    def loss_grad(self, X, T):
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        T = np.ascontiguousarray(T, dtype=np.float32)
+        g = np.zeros(self.num_params, dtype=np.float32)
+        loss = C.c_double()
+        self._check(self._lib.fno_mlp_loss_grad(self._h, _fp(X), _fp(T), X.shape[0], _fp(g), C.byref(loss)))
+        return loss.value, g
+
+    def dataset(self, n: int | None = None):
+        n = self.samples if n is None else n
+        X = np.zeros((n, 9), dtype=np.float32)
+        T = np.zeros((n, 2), dtype=np.float32)
+        self._check(self._lib.fno_mlp_dataset(self._h, _fp(X), _fp(T), n))
+        return X, T
+
+    def predict(self, X) -> np.ndarray:
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        Y = np.zeros((X.shape[0], 2), dtype=np.float32)
+        self._check(self._lib.fno_mlp_predict(self._h, _fp(X), X.shape[0], _fp(Y)))
+        return Y
 
 
 def batch_eom(contexts, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",

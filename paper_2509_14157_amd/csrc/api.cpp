@@ -5,6 +5,7 @@
 #include "../../include/fnocc.h"
 #include "context.hpp"
 #include "eom_space.hpp"
+#include "mlp.hpp"
 
 struct fno_ctx {
   fno::Context* c = nullptr;
@@ -40,6 +41,34 @@ fno::Prec to_prec(fno_prec p) {
   throw fno::Error(FNO_EINVAL, "unknown precision");
 }
 }  // namespace
+
+// ---------------------------------------------------------------- learned guess
+struct fno_mlp {
+  fno::Mlp* m = nullptr;
+  std::string err;
+};
+
+namespace {
+template <typename F>
+int mguard(fno_mlp* h, F&& f) {
+  if (!h || !h->m) return FNO_EINVAL;
+  try {
+    FNO_HIP(hipSetDevice(h->m->device));
+    h->err.clear();
+    return f(*h->m);
+  } catch (const fno::Error& e) {
+    h->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    h->err = "host allocation failed";
+    return FNO_ENOMEM;
+  } catch (const std::exception& e) {
+    h->err = e.what();
+    return FNO_EDEVICE;
+  }
+}
+}  // namespace
+
 
 extern "C" {
 
@@ -106,7 +135,7 @@ int fno_ccsdt(fno_ctx* ctx, const fno_cc_opts* opts, double* e_corr, double* e_t
     fno_cc_opts d;
     fno_cc_opts_default(&d);
     const fno_cc_opts& o = opts ? *opts : d;
-    FNO_REQUIRE(o.guess == 0, FNO_EINVAL, "only the zero-amplitude (MP2 first step) guess is available");
+    FNO_REQUIRE(o.guess == 0 || o.guess == 1, FNO_EINVAL, "guess must be 0 (zero amplitudes) or 1 (learned)");
     fno::CCOptions co;
     co.max_iter = o.max_iter;
     co.r_tol = o.r_tol;
@@ -114,6 +143,7 @@ int fno_ccsdt(fno_ctx* ctx, const fno_cc_opts* opts, double* e_corr, double* e_t
     co.diis_n = o.diis_n;
     co.diis_start = o.diis_start;
     co.prec = to_prec(o.prec);
+    co.guess = o.guess;
     int st = c.ccsdt(co, e_corr, e_tot, iters, res_norm);
     if (st == FNO_ENOCONV) ctx->err = "CCSDT did not converge within max_iter";
     return st;
@@ -361,4 +391,131 @@ int fno_debug_gemm(fno_ctx* ctx, fno_prec prec, int tile, long M, long N, long K
   });
 }
 
+
+long fno_mlp_num_params(void) { return (long)fno::Mlp::num_params(); }
+
+int fno_mlp_create(int hip_device, fno_mlp** out) {
+  if (!out) return FNO_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return FNO_EDEVICE;
+  try {
+    auto* h = new fno_mlp;
+    h->m = new fno::Mlp(hip_device);
+    *out = h;
+    return FNO_OK;
+  } catch (const fno::Error& e) {
+    return e.code;
+  } catch (...) {
+    return FNO_EDEVICE;
+  }
+}
+
+void fno_mlp_destroy(fno_mlp* h) {
+  if (!h) return;
+  delete h->m;
+  delete h;
+}
+
+const char* fno_mlp_last_error(const fno_mlp* h) { return h ? h->err.c_str() : "null network handle"; }
+
+long fno_mlp_samples(const fno_mlp* h) { return (h && h->m) ? (long)h->m->samples() : 0; }
+
+int fno_mlp_collect(fno_mlp* h, fno_ctx* ctx, long max_samples) {
+  if (!h || !h->m) return FNO_EINVAL;
+  return guard(ctx, [&](fno::Context& c) {
+    c.ml_collect(*h->m, (int64_t)max_samples);
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_train(fno_mlp* h, int steps, int batch, double lr, unsigned long seed, double* loss) {
+  return mguard(h, [&](fno::Mlp& m) {
+    const double l = m.train(steps, batch, lr, (uint64_t)seed);
+    if (loss) *loss = l;
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_save(fno_mlp* h, const char* path) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(path != nullptr, FNO_EINVAL, "null path");
+    m.save(path);
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_load(fno_mlp* h, const char* path) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(path != nullptr, FNO_EINVAL, "null path");
+    m.load(path);
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_params(fno_mlp* h, float* buf, size_t len, int set) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(buf != nullptr && len == (size_t)fno::Mlp::num_params(), FNO_EINVAL,
+                "buffer must hold fno_mlp_num_params() floats");
+    if (set)
+      m.set_params(buf);
+    else
+      m.get_params(buf);
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_loss_grad(fno_mlp* h, const float* X, const float* T, long B, float* grad, double* loss) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(X && T && grad && B > 0, FNO_EINVAL, "bad arguments");
+    float *dX = nullptr, *dT = nullptr;
+    FNO_HIP(hipMalloc(&dX, (size_t)B * fno::Mlp::F * sizeof(float)));
+    FNO_HIP(hipMalloc(&dT, (size_t)B * fno::Mlp::O * sizeof(float)));
+    FNO_HIP(hipMemcpy(dX, X, (size_t)B * fno::Mlp::F * sizeof(float), hipMemcpyHostToDevice));
+    FNO_HIP(hipMemcpy(dT, T, (size_t)B * fno::Mlp::O * sizeof(float), hipMemcpyHostToDevice));
+    const double l = m.loss_grad(dX, dT, B);
+    FNO_HIP(hipMemcpy(grad, m.grad(), (size_t)fno::Mlp::num_params() * sizeof(float), hipMemcpyDeviceToHost));
+    (void)hipFree(dX);
+    (void)hipFree(dT);
+    if (loss) *loss = l;
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_predict(fno_mlp* h, const float* X, long n, float* Y) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(X && Y && n > 0, FNO_EINVAL, "bad arguments");
+    float *dX = nullptr, *dY = nullptr;
+    FNO_HIP(hipMalloc(&dX, (size_t)n * fno::Mlp::F * sizeof(float)));
+    FNO_HIP(hipMalloc(&dY, (size_t)n * fno::Mlp::O * sizeof(float)));
+    FNO_HIP(hipMemcpy(dX, X, (size_t)n * fno::Mlp::F * sizeof(float), hipMemcpyHostToDevice));
+    m.predict_bf16(dX, n, dY, m.stream);
+    FNO_HIP(hipStreamSynchronize(m.stream));
+    FNO_HIP(hipMemcpy(Y, dY, (size_t)n * fno::Mlp::O * sizeof(float), hipMemcpyDeviceToHost));
+    (void)hipFree(dX);
+    (void)hipFree(dY);
+    return FNO_OK;
+  });
+}
+
+int fno_mlp_dataset(fno_mlp* h, float* X, float* T, long n) {
+  return mguard(h, [&](fno::Mlp& m) {
+    FNO_REQUIRE(X && T, FNO_EINVAL, "null buffers");
+    m.read_samples(X, T, (int64_t)n);
+    return FNO_OK;
+  });
+}
+
+int fno_set_guess_model(fno_ctx* ctx, fno_mlp* h) {
+  return guard(ctx, [&](fno::Context& c) {
+    if (h) FNO_REQUIRE(h->m && h->m->device == c.device, FNO_EINVAL, "the network lives on another device");
+    c.guess_model = h ? h->m : nullptr;
+    return FNO_OK;
+  });
+}
+
+int fno_last_guess_accepted(const fno_ctx* ctx) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  return ctx->c->last_guess_accepted ? 1 : 0;
+}
 }  // extern "C"

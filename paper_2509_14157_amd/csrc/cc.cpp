@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "context.hpp"
+#include "mlp.hpp"
 #include "linalg.hpp"
 
 namespace fno {
@@ -343,6 +344,134 @@ void Context::cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec
   FNO_HIP(hipStreamSynchronize(eng->stream));
 }
 
+// MP-style starting amplitudes: two Jacobi steps from zero.  The first gives
+// MP2 doubles; the second gives T3 = R3(T2 = MP2) / D3 (the MP2 drivers of the
+// triples equations) and the next correction of T2.
+void Context::plain_guess() {
+  Engine& e = *eng;
+  launch_fill(amp_, 0.0, nt_, e.stream);
+  for (int s = 0; s < 2; ++s) {
+    residual();
+    launch_jacobi(amp_, res_, den_, nullptr, nt_, e.stream);
+  }
+}
+
+double Context::t3_rms(const double* x) {
+  const int64_t n3 = tblocks_[2].size;
+  const double s = n3 ? std::sqrt(dot(x, x, n3) / (double)n3) : 0.0;
+  return s > 0 ? s : 1.0;
+}
+
+namespace {
+// device copy of the working-space orbital energies (occupied then virtual)
+double* upload_eps(const std::vector<double>& fock, int n) {
+  std::vector<double> eps(n);
+  for (int p = 0; p < n; ++p) eps[p] = fock[(size_t)p * n + p];
+  double* d = nullptr;
+  FNO_HIP(hipMalloc(&d, n * sizeof(double)));
+  FNO_HIP(hipMemcpy(d, eps.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  return d;
+}
+}  // namespace
+
+// t3 = x + sx y0 and the shifted T3 denominators from the network (BF16
+// inference), in chunks of 2^20 elements
+void Context::learned_t3(const double* x, double sx, double* t3, double* den3) {
+  Engine& e = *eng;
+  Mlp& m = *guess_model;
+  FNO_REQUIRE(m.device == device, kEINVAL, "the guess model lives on another device");
+  const int64_t n3 = tblocks_[2].size, chunk = 1 << 20;
+  const int64_t cn = std::max<int64_t>(std::min(n3, chunk), 1);
+  float *feat = nullptr, *Y = nullptr;
+  double* deps = nullptr;
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(e.stream);
+    if (feat) (void)hipFree(feat);
+    if (Y) (void)hipFree(Y);
+    if (deps) (void)hipFree(deps);
+  };
+  try {
+    FNO_HIP(hipMalloc(&feat, (size_t)cn * Mlp::F * sizeof(float)));
+    FNO_HIP(hipMalloc(&Y, (size_t)cn * Mlp::O * sizeof(float)));
+    deps = upload_eps(fock, nocc + nvir);
+    for (int64_t r0 = 0; r0 < n3; r0 += chunk) {
+      const int64_t c = std::min(chunk, n3 - r0);
+      mlp::features(e.tables, nocc, nvir, x, den3, deps, sx, nullptr, r0, c, feat, nullptr, nullptr, nullptr,
+                    e.stream);
+      m.predict_bf16(feat, c, Y, e.stream);
+      mlp::apply_guess(t3 + r0, x + r0, den3 + r0, Y, sx, c, e.stream);
+    }
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
+void Context::ml_collect(Mlp& m, int64_t max_samples) {
+  FNO_REQUIRE(cc_done, kESTATE, "training samples need a converged fno_ccsdt");
+  FNO_REQUIRE(m.device == device, kEINVAL, "the network lives on another device");
+  FNO_REQUIRE(max_samples > 0, kEINVAL, "max_samples must be positive");
+  Engine& e = *eng;
+  const Block& b3 = tblocks_[2];
+  const int64_t n3 = b3.size;
+  const int n = nocc + nvir;
+  std::vector<double*> tmp;
+  auto dalloc = [&](int64_t k) {
+    double* p = nullptr;
+    FNO_HIP(hipMalloc(&p, (size_t)std::max<int64_t>(k, 1) * sizeof(double)));
+    tmp.push_back(p);
+    return p;
+  };
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(e.stream);
+    for (double* p : tmp) (void)hipFree(p);
+  };
+  try {
+    double* conv = dalloc(nt_);
+    FNO_HIP(hipMemcpyAsync(conv, amp_, nt_ * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+    // dressed one-body diagonal at the converged amplitudes (F3_oo, F3_vv)
+    residual();
+    std::vector<double> foo((size_t)nocc * nocc), fvv((size_t)nvir * nvir), fd(n);
+    FNO_HIP(hipMemcpyAsync(foo.data(), e.get("F3_oo")->d, foo.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           e.stream));
+    FNO_HIP(hipMemcpyAsync(fvv.data(), e.get("F3_vv")->d, fvv.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    for (int i = 0; i < nocc; ++i) fd[i] = foo[(size_t)i * nocc + i];
+    for (int a = 0; a < nvir; ++a) fd[nocc + a] = fvv[(size_t)a * nvir + a];
+    double* dfd = dalloc(n);
+    FNO_HIP(hipMemcpy(dfd, fd.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    double* deps = upload_eps(fock, n);
+    tmp.push_back(deps);
+    // the MP-style guess x
+    plain_guess();
+    double* x = dalloc(n3);
+    FNO_HIP(hipMemcpyAsync(x, amp_ + b3.offset, n3 * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+    FNO_HIP(hipMemcpyAsync(amp_, conv, nt_ * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+    const double sx = t3_rms(x);
+    // evenly strided sample of the elements
+    const int64_t ns = std::min(max_samples, n3);
+    int64_t* idx = nullptr;
+    if (ns < n3) {
+      std::vector<int64_t> h(ns);
+      for (int64_t r = 0; r < ns; ++r) h[r] = (int64_t)((double)r * (double)n3 / (double)ns);
+      idx = (int64_t*)dalloc(ns);
+      FNO_HIP(hipMemcpy(idx, h.data(), ns * sizeof(int64_t), hipMemcpyHostToDevice));
+    }
+    float *X = nullptr, *T = nullptr;
+    m.reserve(ns, &X, &T);
+    mlp::features(e.tables, nocc, nvir, x, den_ + b3.offset, deps, sx, idx, 0, ns, X, conv + b3.offset, dfd, T,
+                  e.stream);
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    m.commit(ns);
+  } catch (...) {
+    cleanup();
+    throw;
+  }
+  cleanup();
+}
+
 int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, double* rn) {
   FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
   FNO_REQUIRE(opt.max_iter > 0 && opt.diis_n >= 0 && opt.diis_n <= 16, kEINVAL, "bad solver options");
@@ -365,7 +494,41 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   e.prec = opt.prec;
   double* dres = alloc(2 + 16);  // |r|^2, then the overlaps of the new error vector
   const int mm = std::max(m, 1);
+  // learned guess: after two plain Jacobi iterations the amplitudes are the
+  // MP-style guess; the network corrects its T3 block and the T3 Jacobi
+  // denominators.  The next residual judges it against the previous one; a
+  // worse (or non-finite) residual restores the plain guess.
+  FNO_REQUIRE(opt.guess == 0 || (opt.guess == 1 && guess_model != nullptr), kEINVAL,
+              "guess = 1 needs a guess model (fno_set_guess_model)");
+  const Block& b3 = tblocks_[2];
+  double* xg = nullptr;    // plain T3 guess
+  double* dkeep = nullptr;  // plain T3 denominators
+  bool learned_now = false;
+  double rn_prev = INFINITY;
+  last_guess_accepted = false;
+  auto restore_den = [&]() {
+    if (dkeep) FNO_HIP(hipMemcpyAsync(den_ + b3.offset, dkeep, b3.size * sizeof(double), hipMemcpyDeviceToDevice,
+                                      e.stream));
+  };
+  auto release_guess = [&]() {
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    for (double* q : {xg, dkeep})
+      if (q) {
+        owned_.erase(std::remove(owned_.begin(), owned_.end(), q), owned_.end());
+        FNO_HIP(hipFree(q));
+      }
+    xg = dkeep = nullptr;
+  };
   for (it = 1; it <= opt.max_iter; ++it) {
+    if (opt.guess == 1 && it == 3 && b3.size > 0) {
+      xg = alloc(b3.size);
+      dkeep = alloc(b3.size);
+      FNO_HIP(hipMemcpyAsync(xg, amp_ + b3.offset, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+      FNO_HIP(hipMemcpyAsync(dkeep, den_ + b3.offset, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+      learned_t3(xg, t3_rms(xg), amp_ + b3.offset, den_ + b3.offset);
+      order.clear();  // restart the DIIS history from the learned guess
+      learned_now = true;
+    }
     residual();
     int slot;
     if ((int)order.size() < mm) {
@@ -384,8 +547,23 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     FNO_HIP(hipMemcpyAsync(hv, dres, (2 + (m > 0 ? mm : 0)) * sizeof(double), hipMemcpyDeviceToHost, e.stream));
     FNO_HIP(hipStreamSynchronize(e.stream));
     rnorm = std::sqrt(hv[0]);
+    if (learned_now) {
+      learned_now = false;
+      if (!(rnorm < rn_prev)) {
+        // the plain guess wins: restore it and evaluate again next iteration
+        FNO_HIP(hipMemcpyAsync(amp_ + b3.offset, xg, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+        restore_den();
+        release_guess();
+        order.clear();
+        continue;
+      }
+      last_guess_accepted = true;
+    }
+    rn_prev = rnorm;
     if (!std::isfinite(rnorm)) {
       e.prec = Prec::FP64;
+      restore_den();
+      release_guess();
       throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
     }
     bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
@@ -424,6 +602,8 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     }
   }
   e.prec = Prec::FP64;
+  restore_den();
+  release_guess();
   // release the DIIS history
   FNO_HIP(hipStreamSynchronize(e.stream));
   owned_.erase(std::remove(owned_.begin(), owned_.end(), hist), owned_.end());

@@ -14,7 +14,10 @@ struct CCOptions {
   double r_tol = 1e-8, e_tol = 1e-10;
   int diis_n = 8, diis_start = 3;
   Prec prec = Prec::FP64;
+  int guess = 0;  // 0: zero amplitudes; 1: learned correction of the MP-style T3 guess (guess_model)
 };
+
+class Mlp;
 
 struct EOMOptions {
   int nroots = 4, max_iter = 60, max_sub = 0;
@@ -75,6 +78,13 @@ class Context {
 
   double last_triples_flops = 0, last_all_flops = 0;
 
+  // learned guess: the network used when CCOptions::guess == 1 (not owned)
+  Mlp* guess_model = nullptr;
+  bool last_guess_accepted = false;
+  // append training samples (features of every selected T3 element and the
+  // targets from the converged amplitudes) to the network's data set
+  void ml_collect(Mlp& m, int64_t max_samples);
+
   // launch mode: replay the residual sweep from a recorded hipGraph program
   bool use_graphs = true;
   hipStream_t user_stream = nullptr;  // caller's stream (fno_set_stream), kept across engine rebuilds
@@ -91,6 +101,9 @@ class Context {
   double energy();
   void residual();
   void residual_body(Prec tri);
+  void plain_guess();
+  double t3_rms(const double* x);
+  void learned_t3(const double* x, double sx, double* t3, double* den3);
   Program cc_prog_;              // recorded residual sweep
   // the last host-launched sweep allocated nothing; the settings it ran with
   bool cc_stable_ = false;

@@ -741,3 +741,213 @@ void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos,
 }
 
 }  // namespace fno
+
+// ---------------------------------------------------------------- learned guess (MLP)
+namespace fno {
+namespace mlp {
+
+__device__ __forceinline__ float sigm(float z) { return 1.0f / (1.0f + expf(-z)); }
+
+// Z[r][c] += b[c]; A = silu(Z) (act != 0) or A = Z
+__global__ void __launch_bounds__(256) bias_act_kernel(float* __restrict__ Z, const float* __restrict__ b,
+                                                       float* __restrict__ A, int64_t rows, int cols, int act) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const float z = Z[e] + b[e % cols];
+    Z[e] = z;
+    A[e] = act ? z * sigm(z) : z;
+  }
+}
+
+// dZ = dA * silu'(Z)
+__global__ void __launch_bounds__(256) act_grad_kernel(const float* __restrict__ Z, const float* __restrict__ dA,
+                                                       float* __restrict__ dZ, int64_t total) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const float s = sigm(Z[e]);
+    dZ[e] = dA[e] * s * (1.0f + Z[e] * (1.0f - s));
+  }
+}
+
+// column sums of a rows x cols matrix (bias gradients); one thread per column
+__global__ void __launch_bounds__(256) colsum_kernel(const float* __restrict__ X, float* __restrict__ out, int64_t rows,
+                                                     int cols) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.0f;
+  for (int64_t r = 0; r < rows; ++r) s += X[r * cols + c];
+  out[c] = s;
+}
+
+// weighted MSE: loss_part[block] partial sums of sum_o w_o (Y - T)^2 / rows, dY = 2 w (Y - T) / rows
+__global__ void __launch_bounds__(256) mse_kernel(const float* __restrict__ Y, const float* __restrict__ T,
+                                                  const float* __restrict__ w, float* __restrict__ dY,
+                                                  float* __restrict__ part, int64_t rows, int cols) {
+  __shared__ float red[256];
+  const int64_t total = rows * cols;
+  float acc = 0.0f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const float d = Y[e] - T[e];
+    const float wo = w[e % cols];
+    acc += wo * d * d;
+    dY[e] = 2.0f * wo * d / (float)rows;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] / (float)rows;
+}
+
+// Adam (bias-corrected) on a flat parameter vector
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
+                                                   float b1, float b2, float eps, float c1, float c2) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.0f - b1) * gi;
+    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    p[e] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// FP32 -> BF16 (round to nearest even), lo part zero: single-BF16 operands for
+// the BF16 MFMA path
+__global__ void __launch_bounds__(256) to_bf16_kernel(const float* __restrict__ x, __hip_bfloat16* __restrict__ hi,
+                                                      __hip_bfloat16* __restrict__ lo, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    hi[e] = __float2bfloat16(x[e]);
+    lo[e] = __float2bfloat16(0.0f);
+  }
+}
+
+static int64_t nblocks(int64_t n) { return std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 65536)); }
+
+void bias_act(float* Z, const float* b, float* A, int64_t rows, int cols, bool act, hipStream_t s) {
+  if (rows * cols == 0) return;
+  bias_act_kernel<<<dim3((unsigned)nblocks(rows * cols)), 256, 0, s>>>(Z, b, A, rows, cols, act ? 1 : 0);
+  FNO_HIP(hipGetLastError());
+}
+void act_grad(const float* Z, const float* dA, float* dZ, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  act_grad_kernel<<<dim3((unsigned)nblocks(n)), 256, 0, s>>>(Z, dA, dZ, n);
+  FNO_HIP(hipGetLastError());
+}
+void colsum(const float* X, float* out, int64_t rows, int cols, hipStream_t s) {
+  colsum_kernel<<<dim3((unsigned)((cols + 255) / 256)), 256, 0, s>>>(X, out, rows, cols);
+  FNO_HIP(hipGetLastError());
+}
+int mse_blocks(int64_t n) { return (int)std::min<int64_t>(nblocks(n), 1024); }
+void mse(const float* Y, const float* T, const float* w, float* dY, float* part, int64_t rows, int cols,
+         hipStream_t s) {
+  mse_kernel<<<dim3((unsigned)mse_blocks(rows * cols)), 256, 0, s>>>(Y, T, w, dY, part, rows, cols);
+  FNO_HIP(hipGetLastError());
+}
+void adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, int step,
+          hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  adam_kernel<<<dim3((unsigned)nblocks(n)), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  FNO_HIP(hipGetLastError());
+}
+void to_bf16(const float* x, void* hi, void* lo, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  to_bf16_kernel<<<dim3((unsigned)nblocks(n)), 256, 0, s>>>(x, (__hip_bfloat16*)hi, (__hip_bfloat16*)lo, n);
+  FNO_HIP(hipGetLastError());
+}
+
+}  // namespace mlp
+}  // namespace fno
+
+namespace fno {
+namespace mlp {
+
+// Features of T3 elements for the learned guess (one row of kFeat per element):
+//   x / sx, |x| / sx, D / 10, e_i, e_j, e_k, e_a, e_b, e_c
+// x the MP-style guess (two Jacobi steps from zero), D the denominator
+// sum e_holes - sum e_particles, e the orbital energies (occupied then
+// virtual).  With t3c the targets are (t3c - x) / sx and the dressed-diagonal
+// shift (sum fo_holes - sum fv_particles) - D.  idx selects elements (null:
+// row r of the output is element e0 + r of T3).
+__global__ void __launch_bounds__(256) features_kernel(IndexTables tb, int nocc, int nvir, const double* __restrict__ x,
+                                                       const double* __restrict__ den, const double* __restrict__ eps,
+                                                       double inv_sx, const int64_t* __restrict__ idx, int64_t e0,
+                                                       int64_t ns,
+                                                       float* __restrict__ feat, const double* __restrict__ t3c,
+                                                       const double* __restrict__ fdiag, float* __restrict__ targ) {
+  const int64_t cv3 = (int64_t)nvir * (nvir - 1) * (nvir - 2) / 6;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < ns; r += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = idx ? idx[r] : e0 + r;
+    const int64_t h = e / cv3, p = e - h * cv3;
+    const uint8_t* hh = tb.dec[3] + h * 3;
+    const uint8_t* pp = tb.dec[3] + p * 3;
+    const double xv = x[e], dv = den[e];
+    float* f = feat + r * kFeat;
+    f[0] = (float)(xv * inv_sx);
+    f[1] = (float)(fabs(xv) * inv_sx);
+    f[2] = (float)(dv * 0.1);
+    for (int t = 0; t < 3; ++t) {
+      f[3 + t] = (float)eps[hh[t]];
+      f[6 + t] = (float)eps[nocc + pp[t]];
+    }
+    if (targ) {
+      double dd = 0.0;
+      for (int t = 0; t < 3; ++t) dd += fdiag[hh[t]] - fdiag[nocc + pp[t]];
+      targ[r * 2 + 0] = (float)((t3c[e] - xv) * inv_sx);
+      targ[r * 2 + 1] = (float)(dd - dv);
+    }
+  }
+}
+
+// Apply the network outputs Y (n x 2, FP32) to the guess: t3 = x + sx y0, and
+// the T3 Jacobi denominator D' = D + y1 kept within [2 D, D / 2] (D < 0).
+__global__ void __launch_bounds__(256) apply_guess_kernel(double* __restrict__ t3, const double* __restrict__ x,
+                                                          double* __restrict__ den, const float* __restrict__ Y,
+                                                          double sx, int64_t n) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+    t3[e] = x[e] + sx * (double)Y[e * 2 + 0];
+    const double d = den[e];
+    const double s = d + (double)Y[e * 2 + 1];
+    den[e] = fmin(fmax(s, 2.0 * d), 0.5 * d);
+  }
+}
+
+// rows of X gathered by a counter-based hash of (seed, row): minibatch sampling
+__global__ void __launch_bounds__(256) gather_kernel(const float* __restrict__ X, const float* __restrict__ T,
+                                                     float* __restrict__ Xb, float* __restrict__ Tb, int64_t n,
+                                                     int64_t rows, uint64_t seed) {
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < rows; r += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t)r * 0xBF58476D1CE4E5B9ull + 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    z *= 0xD6E8FEB86659FD93ull;
+    z ^= z >> 29;
+    const int64_t src = (int64_t)(z % (uint64_t)n);
+    for (int c = 0; c < kFeat; ++c) Xb[r * kFeat + c] = X[src * kFeat + c];
+    Tb[r * 2 + 0] = T[src * 2 + 0];
+    Tb[r * 2 + 1] = T[src * 2 + 1];
+  }
+}
+
+void features(const IndexTables& tb, int nocc, int nvir, const double* x, const double* den, const double* eps,
+              double sx, const int64_t* idx, int64_t e0, int64_t ns, float* feat, const double* t3c,
+              const double* fdiag, float* targ, hipStream_t s) {
+  if (ns == 0) return;
+  features_kernel<<<dim3((unsigned)nblocks(ns)), 256, 0, s>>>(tb, nocc, nvir, x, den, eps, 1.0 / sx, idx, e0, ns,
+                                                              feat, t3c, fdiag, targ);
+  FNO_HIP(hipGetLastError());
+}
+void apply_guess(double* t3, const double* x, double* den, const float* Y, double sx, int64_t n, hipStream_t s) {
+  if (n == 0) return;
+  apply_guess_kernel<<<dim3((unsigned)nblocks(n)), 256, 0, s>>>(t3, x, den, Y, sx, n);
+  FNO_HIP(hipGetLastError());
+}
+void gather(const float* X, const float* T, float* Xb, float* Tb, int64_t n, int64_t rows, uint64_t seed,
+            hipStream_t s) {
+  gather_kernel<<<dim3((unsigned)nblocks(rows)), 256, 0, s>>>(X, T, Xb, Tb, n, rows, seed);
+  FNO_HIP(hipGetLastError());
+}
+
+}  // namespace mlp
+}  // namespace fno

@@ -81,4 +81,25 @@ void launch_gemm(const GemmArgs& g, hipStream_t s);
 std::string gemm_label(const GemmArgs& g);
 int gemm_num_tiles(Prec p);
 
+
+// ---- learned guess: MLP building blocks (FP32) and T3 feature / guess kernels
+namespace mlp {
+constexpr int kFeat = 9;  // features per T3 element
+void bias_act(float* Z, const float* b, float* A, int64_t rows, int cols, bool act, hipStream_t s);
+void act_grad(const float* Z, const float* dA, float* dZ, int64_t n, hipStream_t s);
+void colsum(const float* X, float* out, int64_t rows, int cols, hipStream_t s);
+int mse_blocks(int64_t n);
+void mse(const float* Y, const float* T, const float* w, float* dY, float* part, int64_t rows, int cols,
+         hipStream_t s);
+void adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps, int step,
+          hipStream_t s);
+void to_bf16(const float* x, void* hi, void* lo, int64_t n, hipStream_t s);
+void features(const IndexTables& tb, int nocc, int nvir, const double* x, const double* den, const double* eps,
+              double sx, const int64_t* idx, int64_t e0, int64_t ns, float* feat, const double* t3c,
+              const double* fdiag, float* targ, hipStream_t s);
+void apply_guess(double* t3, const double* x, double* den, const float* Y, double sx, int64_t n, hipStream_t s);
+void gather(const float* X, const float* T, float* Xb, float* Tb, int64_t n, int64_t rows, uint64_t seed,
+            hipStream_t s);
+}  // namespace mlp
+
 }  // namespace fno
