@@ -165,6 +165,93 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
     print(json.dumps(line), flush=True)
 
 
+def _train_hamiltonian(seed):
+    from synthetic import config_hamiltonian
+    h = config_hamiltonian("C5train", seed=seed)
+    return h.fock, h.eri
+
+
+def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
+    """Learned CCSDT start: collect T3 samples from converged FNO-CCSDT runs at o=8, v=32
+    (54 virtuals truncated to 32, seeds 1000..), train the network on the GPU, then solve the
+    o=14, v=56 FNO problem (94 virtuals, seed 5) to 1e-6 Eh from the plain and the learned guess,
+    followed by FNO-EOM-EA-CCSDT with 8 roots (FP32 triples, FP64 Davidson) on the converged state."""
+    import concurrent.futures as cf
+
+    import paper_2509_14157_amd as P
+    from synthetic import CONFIGS, config_hamiltonian
+
+    import multiprocessing as mp
+
+    keep = CONFIGS["C5train"]["keep"]
+    o_tr = CONFIGS["C5train"]["nocc"]
+    seeds = [CONFIGS["C5train"]["seed"] + k for k in range(args.train_runs)]
+    t0 = time.perf_counter()
+    conv = 0
+    # the host workers that draw the training Hamiltonians are forked, and all
+    # their tasks submitted, before this process makes its first GPU call
+    with cf.ProcessPoolExecutor(max_workers=4, mp_context=mp.get_context("fork")) as pool:
+        futures = [pool.submit(_train_hamiltonian, sd) for sd in seeds]
+        net = P.Mlp(0)
+        for k, fut in enumerate(futures):
+            fock, eri = fut.result()
+            futures[k] = None
+            with P.Context(0) as c:
+                c.load_hamiltonian(fock, eri, o_tr)
+                c.truncate(1.0, keep)
+                r = c.ccsdt(r_tol=1e-8, e_tol=1e-10, max_iter=60, allow_noconv=True)
+                conv += int(r["converged"])
+                net.collect(c, samples_per_run)
+            if (k + 1) % 20 == 0:
+                _log(f"[bench] {k + 1} training runs collected ({net.samples} samples)")
+    t_collect = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    loss0 = net.train(20, batch=batch, lr=0.0, seed=1)
+    loss = net.train(steps, batch=batch, lr=lr, seed=2)
+    t_train = time.perf_counter() - t0
+    _log(f"[bench] trained {steps} steps in {t_train:.2f} s: loss {loss0:.3e} -> {loss:.3e}")
+
+    h = config_hamiltonian("C5eval")
+    o, kv = CONFIGS["C5eval"]["nocc"], CONFIGS["C5eval"]["keep"]
+    res = {}
+    eom = None
+    for name, guess in (("plain", 0), ("learned", 1)):
+        with P.Context(0) as c:
+            c.load_hamiltonian(h.fock, h.eri, o)
+            c.truncate(1.0, kv)
+            c.set_guess_model(net)
+            # warm-up of plans and graph recordings, not timed
+            c.ccsdt(max_iter=3, allow_noconv=True, guess=guess)
+            t0 = time.perf_counter()
+            r = c.ccsdt(r_tol=1e-4, e_tol=1e-6, max_iter=300, allow_noconv=True, guess=guess)
+            dt = time.perf_counter() - t0
+            res[name] = {"iters": r["iters"], "s": round(dt, 3), "e_tot": r["e_tot"], "converged": r["converged"],
+                         "res_norm": r["res_norm"]}
+            if guess == 1:
+                res[name]["guess_accepted"] = c.last_guess_accepted()
+            _log(f"[bench] {name}: {r['iters']} iterations, {dt:.2f} s, E={r['e_tot']:.8f}")
+            if guess == 0:
+                t0 = time.perf_counter()
+                e = c.eom("EA", nroots=8, prec="fp32", r_tol=1e-3, e_tol=1e-6, max_iter=30, allow_noconv=True)
+                eom = {"s": round(time.perf_counter() - t0, 3), "iters": e["iters"], "converged": e["converged"],
+                       "omega": [round(float(w), 8) for w in np.sort(e["omega"])]}
+                _log(f"[bench] EOM-EA 8 roots: {eom['iters']} iterations, {eom['s']:.2f} s")
+    net.close()
+    line = {
+        "metric": "CCSDT iterations and time to 1e-6 Eh, learned vs plain guess",
+        "value": res["learned"]["iters"], "unit": "iterations", "n_gpus": 1, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "learned start: train on FNO-CCSDT o=8, v=32 (of 54), seeds "
+                               f"{seeds[0]}-{seeds[-1]}; evaluate FNO-EOM-EA-CCSDT o=14, v=56 (of 94), seed 5, 8 roots",
+                   "train_runs": len(seeds), "converged_train_runs": conv, "samples": samples_per_run,
+                   "steps": steps, "batch": batch, "lr": lr},
+        "collect_s": round(t_collect, 2), "train_s": round(t_train, 2), "loss_initial": loss0, "loss_final": loss,
+        "ground_state": res, "eom_ea": eom,
+        "energy_difference": abs(res["learned"]["e_tot"] - res["plain"]["e_tot"]),
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,12 +263,20 @@ def main():
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--workload", default="ccsdt", choices=["ccsdt", "batched"],
+    ap.add_argument("--workload", default="ccsdt", choices=["ccsdt", "batched", "learned"],
                     help="ccsdt: the o=10/v=59 FNO-CCSDT iteration (default); batched: 16 uneven FNO instances, "
-                         "DIP and DEA roots, batched against one instance after another")
+                         "DIP and DEA roots, batched against one instance after another; learned: train the "
+                         "learned guess on 200 o=8/v=32 runs, evaluate at o=14/v=56 against the plain guess")
+    ap.add_argument("--train-runs", type=int, default=200)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "learned":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        bench_learned(args)
         return
     if args.workload == "batched":
         if args.gpus != 1:

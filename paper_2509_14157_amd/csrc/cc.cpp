@@ -495,16 +495,15 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   double* dres = alloc(2 + 16);  // |r|^2, then the overlaps of the new error vector
   const int mm = std::max(m, 1);
   // learned guess: after two plain Jacobi iterations the amplitudes are the
-  // MP-style guess; the network corrects its T3 block and the T3 Jacobi
-  // denominators.  The next residual judges it against the previous one; a
-  // worse (or non-finite) residual restores the plain guess.
+  // MP-style guess.  At the third iteration the residual is evaluated at the
+  // plain guess and at the learned one (the network corrects the T3 block and
+  // shifts the T3 Jacobi denominators); the smaller residual norm wins and the
+  // iteration continues from it.  The extra evaluation counts as an iteration.
   FNO_REQUIRE(opt.guess == 0 || (opt.guess == 1 && guess_model != nullptr), kEINVAL,
               "guess = 1 needs a guess model (fno_set_guess_model)");
   const Block& b3 = tblocks_[2];
   double* xg = nullptr;    // plain T3 guess
   double* dkeep = nullptr;  // plain T3 denominators
-  bool learned_now = false;
-  double rn_prev = INFINITY;
   last_guess_accepted = false;
   auto restore_den = [&]() {
     if (dkeep) FNO_HIP(hipMemcpyAsync(den_ + b3.offset, dkeep, b3.size * sizeof(double), hipMemcpyDeviceToDevice,
@@ -520,16 +519,36 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     xg = dkeep = nullptr;
   };
   for (it = 1; it <= opt.max_iter; ++it) {
-    if (opt.guess == 1 && it == 3 && b3.size > 0) {
+    if (opt.guess == 1 && it == 3 && b3.size > 0 && it + 1 <= opt.max_iter) {
+      // residual at the plain guess, kept aside
+      residual();
+      double* rplain = alloc(nt_);
+      FNO_HIP(hipMemcpyAsync(rplain, res_, nt_ * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+      const double rn_plain = std::sqrt(dot(res_, res_, nt_));
+      // residual at the learned guess
       xg = alloc(b3.size);
       dkeep = alloc(b3.size);
       FNO_HIP(hipMemcpyAsync(xg, amp_ + b3.offset, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
       FNO_HIP(hipMemcpyAsync(dkeep, den_ + b3.offset, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
       learned_t3(xg, t3_rms(xg), amp_ + b3.offset, den_ + b3.offset);
-      order.clear();  // restart the DIIS history from the learned guess
-      learned_now = true;
+      residual();
+      const double rn_learned = std::sqrt(dot(res_, res_, nt_));
+      if (rn_learned < rn_plain) {
+        last_guess_accepted = true;
+      } else {
+        // the plain guess wins: its amplitudes, denominators and residual
+        FNO_HIP(hipMemcpyAsync(amp_ + b3.offset, xg, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+        restore_den();
+        FNO_HIP(hipMemcpyAsync(res_, rplain, nt_ * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+      }
+      FNO_HIP(hipStreamSynchronize(e.stream));
+      owned_.erase(std::remove(owned_.begin(), owned_.end(), rplain), owned_.end());
+      FNO_HIP(hipFree(rplain));
+      order.clear();  // the DIIS history restarts from the chosen guess
+      ++it;           // the judge's extra residual evaluation
+    } else {
+      residual();
     }
-    residual();
     int slot;
     if ((int)order.size() < mm) {
       slot = (int)order.size();
@@ -547,19 +566,6 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     FNO_HIP(hipMemcpyAsync(hv, dres, (2 + (m > 0 ? mm : 0)) * sizeof(double), hipMemcpyDeviceToHost, e.stream));
     FNO_HIP(hipStreamSynchronize(e.stream));
     rnorm = std::sqrt(hv[0]);
-    if (learned_now) {
-      learned_now = false;
-      if (!(rnorm < rn_prev)) {
-        // the plain guess wins: restore it and evaluate again next iteration
-        FNO_HIP(hipMemcpyAsync(amp_ + b3.offset, xg, b3.size * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
-        restore_den();
-        release_guess();
-        order.clear();
-        continue;
-      }
-      last_guess_accepted = true;
-    }
-    rn_prev = rnorm;
     if (!std::isfinite(rnorm)) {
       e.prec = Prec::FP64;
       restore_den();
