@@ -165,6 +165,53 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
     print(json.dumps(line), flush=True)
 
 
+def bench_eom(args, nroots=8):
+    """FNO-EOM-IP and EA-CCSDT at o=12, v=48 (80 virtuals truncated, seed 3): ground state in FP64,
+    then 8-root block Davidson with FP64 / FP32 / split-BF16 triples contractions (FP64 subspace
+    and orthogonalisation).  Per variant and precision: time, iterations, s per iteration,
+    R3-sigma TFLOP/s, and the roots' largest difference from FP64."""
+    import paper_2509_14157_amd as P
+    from synthetic import CONFIGS, config_hamiltonian
+
+    h = config_hamiltonian("C3")
+    o, kv = CONFIGS["C3"]["nocc"], CONFIGS["C3"]["keep"]
+    out = {}
+    with P.Context(0) as c:
+        c.load_hamiltonian(h.fock, h.eri, o)
+        c.truncate(1.0, kv)
+        t0 = time.perf_counter()
+        g = c.ccsdt(r_tol=1e-8, e_tol=1e-10, max_iter=300, allow_noconv=True)
+        out["ground_state"] = {"iters": g["iters"], "s": round(time.perf_counter() - t0, 3), "e_tot": g["e_tot"],
+                               "converged": g["converged"], "res_norm": g["res_norm"]}
+        _log(f"[bench] ground state: {g['iters']} iterations, E={g['e_tot']:.10f}, converged={g['converged']}")
+        for kind in ("IP", "EA"):
+            ref = None
+            out[kind] = {}
+            for pr in ("fp64", "fp32", "bf16x3"):
+                c.eom(kind, nroots=nroots, prec=pr, max_iter=2, allow_noconv=True)  # plans and recordings
+                t0 = time.perf_counter()
+                r = c.eom(kind, nroots=nroots, prec=pr, r_tol=1e-5 if pr == "fp64" else 1e-3, e_tol=1e-7,
+                          max_iter=60, allow_noconv=True)
+                dt = time.perf_counter() - t0
+                trp, _ = c.last_flops()
+                w = np.sort(r["omega"])
+                if ref is None:
+                    ref = w
+                out[kind][pr] = {"s": round(dt, 3), "iters": r["iters"], "s_per_iter": round(dt / r["iters"], 4),
+                                 "converged": r["converged"], "triples_gflop": round(trp / 1e9, 2),
+                                 "tflops": round(trp / dt / 1e12, 3),
+                                 "max_root_diff_vs_fp64": float(np.abs(w - ref).max()),
+                                 "omega": [round(float(x), 9) for x in w]}
+                _log(f"[bench] EOM-{kind} {pr}: {r['iters']} iterations in {dt:.2f} s "
+                     f"({trp / dt / 1e12:.2f} TFLOP/s), max |dw| vs fp64 {np.abs(w - ref).max():.2e}")
+    line = {"metric": "triples-contraction TFLOP/s (% MFMA peak) and s/iteration, FP64 vs mixed",
+            "value": out["EA"]["fp64"]["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "FNO-EOM-IP/EA-CCSDT o=12, v=48 (of 80, seed 3), 8 roots, block Davidson"},
+            "results": out}
+    print(json.dumps(line), flush=True)
+
+
 def _train_hamiltonian(seed):
     from synthetic import config_hamiltonian
     h = config_hamiltonian("C5train", seed=seed)
@@ -175,7 +222,7 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
     """Learned CCSDT start: collect T3 samples from converged FNO-CCSDT runs at o=8, v=32
     (54 virtuals truncated to 32, seeds 1000..), train the network on the GPU, then solve the
     o=14, v=56 FNO problem (94 virtuals, seed 5) to 1e-6 Eh from the plain and the learned guess,
-    followed by FNO-EOM-EA-CCSDT with 8 roots (FP32 triples, FP64 Davidson) on the converged state."""
+    followed by FNO-EOM-EA-CCSDT with 8 roots (FP64) on the converged state."""
     import concurrent.futures as cf
 
     import paper_2509_14157_amd as P
@@ -232,7 +279,7 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
             _log(f"[bench] {name}: {r['iters']} iterations, {dt:.2f} s, E={r['e_tot']:.8f}")
             if guess == 0:
                 t0 = time.perf_counter()
-                e = c.eom("EA", nroots=8, prec="fp32", r_tol=1e-3, e_tol=1e-6, max_iter=30, allow_noconv=True)
+                e = c.eom("EA", nroots=8, r_tol=1e-4, e_tol=1e-6, max_iter=60, allow_noconv=True)
                 eom = {"s": round(time.perf_counter() - t0, 3), "iters": e["iters"], "converged": e["converged"],
                        "omega": [round(float(w), 8) for w in np.sort(e["omega"])]}
                 _log(f"[bench] EOM-EA 8 roots: {eom['iters']} iterations, {eom['s']:.2f} s")
@@ -263,14 +310,21 @@ def main():
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
-    ap.add_argument("--workload", default="ccsdt", choices=["ccsdt", "batched", "learned"],
+    ap.add_argument("--workload", default="ccsdt", choices=["ccsdt", "batched", "learned", "eom"],
                     help="ccsdt: the o=10/v=59 FNO-CCSDT iteration (default); batched: 16 uneven FNO instances, "
                          "DIP and DEA roots, batched against one instance after another; learned: train the "
-                         "learned guess on 200 o=8/v=32 runs, evaluate at o=14/v=56 against the plain guess")
+                         "learned guess on 200 o=8/v=32 runs, evaluate at o=14/v=56 against the plain guess; "
+                         "eom: FNO-EOM-IP/EA-CCSDT at o=12, v=48 (of 80), 8 roots, FP64 vs FP32 vs split-BF16")
     ap.add_argument("--train-runs", type=int, default=200)
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.workload == "eom":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1"}))
+            sys.exit(2)
+        bench_eom(args)
         return
     if args.workload == "learned":
         if args.gpus != 1:
@@ -344,6 +398,36 @@ def main():
     breakdown = sorted(wrep["kernels"], key=lambda k: -k["total_ms"])[:6]
     kernel_ms_iter = sum(k["total_ms"] for k in wrep["kernels"]) / witers
 
+    # FP64 vs mixed: per-iteration time of the same sweep with FP32 / split-BF16
+    # triples contractions (graph replay, nothing timed per kernel), and the
+    # converged energies of the three precisions (mixed runs converge on the
+    # FP64-updated residual to 1e-6, FP64 to 1e-8)
+    mixed = {}
+    if args.prec == "fp64":
+        ctx.set_graphs(True)
+        e_conv = {}
+        for pr in ("fp64", "fp32", "bf16x3"):
+            if pr != "fp64":
+                ctx.ccsdt(max_iter=max(args.warmup, 1), prec=pr, allow_noconv=True)
+                t0 = time.perf_counter()
+                r = ctx.ccsdt(max_iter=args.steps, prec=pr, allow_noconv=True)
+                dt = (time.perf_counter() - t0) / r["iters"]
+                trp, _ = ctx.last_flops()
+                mixed[pr] = {"ms_per_step": round(1e3 * dt, 4), "value": round(trp / dt / 1e12, 4),
+                             "pct_peak_whole_iteration": round(100 * trp / dt / 1e12 * (3 if pr == "bf16x3" else 1)
+                                                               / PEAK_TFLOPS[pr], 2)}
+            rc = ctx.ccsdt(r_tol=1e-8 if pr == "fp64" else 1e-6, e_tol=1e-10 if pr == "fp64" else 1e-9,
+                           max_iter=300, prec=pr, allow_noconv=True)
+            e_conv[pr] = (rc["e_tot"], rc["iters"], rc["converged"])
+        for pr in ("fp32", "bf16x3"):
+            mixed[pr].update({"energy_minus_fp64": e_conv[pr][0] - e_conv["fp64"][0], "iters_to_converge": e_conv[pr][1],
+                              "converged": e_conv[pr][2]})
+        mixed["fp64_converged"] = {"energy": e_conv["fp64"][0], "iters": e_conv["fp64"][1],
+                                   "converged": e_conv["fp64"][2]}
+        _log(f"[bench] mixed: fp32 {mixed['fp32']['ms_per_step']} ms/iter, bf16x3 {mixed['bf16x3']['ms_per_step']} "
+             f"ms/iter; dE fp32 {mixed['fp32']['energy_minus_fp64']:.2e}, bf16x3 "
+             f"{mixed['bf16x3']['energy_minus_fp64']:.2e}")
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("[bench] timing the CPU oracle on a bounded sample")
@@ -373,6 +457,7 @@ def main():
         "kernel_ms_per_iter": {k["name"]: round(k["total_ms"] / witers, 4) for k in breakdown},
         "kernel_ms_per_iter_total": round(kernel_ms_iter, 4),
         "gpu_busy_frac": round(kernel_ms_iter / (1e3 * s_iter), 4),
+        "mixed": mixed,
         "energy": res["e_tot"],
     }
     print(json.dumps(line), flush=True)
