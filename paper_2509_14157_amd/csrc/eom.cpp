@@ -8,6 +8,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 
 #include "eom_space.hpp"
 #include "linalg.hpp"
@@ -118,12 +120,28 @@ void Context::setup_eom(int kind, int nb) {
     sp->dim += B.size;
     sp->blocks.push_back(B);
   }
-  // zeroth-order diagonal: sum e_particles - sum e_holes
+  // ground-state intermediates at the current amplitudes, then the T-only
+  // intermediates of the quadruples projection (DIP, DEA)
+  residual();
+  e.prec = Prec::FP64;
+  {
+    CacheScope cache(e, {"T2", "T3"});
+    for (int i = 0; i < t.nprep; ++i)
+      if (t.prep[i][0]) e.term(t.prep[i]);
+  }
+  // diagonal for the preconditioner and the guesses: the one-body part of
+  // H-bar at the CC amplitudes (the dressed Fock blocks F3_oo, F3_vv of the
+  // triples equations), summed over a block's particles minus its holes
   sp->diag = alloc(sp->dim);
   const int n = nocc + nvir;
   std::vector<double> eo(nocc), ev(nvir);
-  for (int i = 0; i < nocc; ++i) eo[i] = fock[(size_t)i * n + i];
-  for (int a = 0; a < nvir; ++a) ev[a] = fock[(size_t)(nocc + a) * n + (nocc + a)];
+  {
+    std::vector<double> foo((size_t)nocc * nocc), fvv((size_t)nvir * nvir);
+    FNO_HIP(hipMemcpy(foo.data(), e.get("F3_oo")->d, foo.size() * sizeof(double), hipMemcpyDeviceToHost));
+    FNO_HIP(hipMemcpy(fvv.data(), e.get("F3_vv")->d, fvv.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int i = 0; i < nocc; ++i) eo[i] = foo[(size_t)i * nocc + i];
+    for (int a = 0; a < nvir; ++a) ev[a] = fvv[(size_t)a * nvir + a];
+  }
   double* d_e = alloc(n);
   FNO_HIP(hipMemcpy(d_e, eo.data(), nocc * sizeof(double), hipMemcpyHostToDevice));
   FNO_HIP(hipMemcpy(d_e + nocc, ev.data(), nvir * sizeof(double), hipMemcpyHostToDevice));
@@ -152,15 +170,6 @@ void Context::setup_eom(int kind, int nb) {
   owned_.erase(std::remove(owned_.begin(), owned_.end(), d_e), owned_.end());
   FNO_HIP(hipStreamSynchronize(e.stream));
   FNO_HIP(hipFree(d_e));
-  // ground-state intermediates at the current amplitudes, then the T-only
-  // intermediates of the quadruples projection (DIP, DEA)
-  residual();
-  e.prec = Prec::FP64;
-  {
-    CacheScope cache(e, {"T2", "T3"});
-    for (int i = 0; i < t.nprep; ++i)
-      if (t.prep[i][0]) e.term(t.prep[i]);
-  }
   sp->ready = true;
   eom_ = std::move(sp);
 }
@@ -321,6 +330,7 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   d->S = alloc((int64_t)d->max_sub * dim);
   d->X = alloc((int64_t)d->nroots * dim);
   d->W = alloc(dim);
+  d->T = alloc((int64_t)2 * d->nroots * dim);
   d->dco = alloc(std::max(d->max_sub, d->nroots) + 8);
   d->dots = alloc(std::max(d->max_sub, 1) + 8);
   // guesses: unit vectors on the lowest zeroth-order diagonal entries of the
@@ -345,7 +355,9 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   d->nv = d->nroots;
   last_triples_flops = last_all_flops = 0;  // summed over the sigma sweeps of this solve
   d->G.assign((size_t)d->max_sub * d->max_sub, 0.0);
+  d->trace = std::getenv("FNO_TRACE") != nullptr;
   d->theta.assign(d->nroots, 0.0);
+  d->theta_imag.assign(d->nroots, 0.0);
   d->theta_old.assign(d->nroots, INFINITY);
   d->rn.assign(d->nroots, INFINITY);
   dav_ = std::move(d);
@@ -383,34 +395,61 @@ bool Context::dav_update(Davidson& d) {
     FNO_HIP(hipStreamSynchronize(e.stream));
   };
   ++d.it;
-  const int nv = d.nv;
-  // G[i][j] = v_i . s_j (all entries; the subspace is small)
+  int nv = d.nv;
+  // G[i][j] = v_i . s_j; only the rows and columns of the vectors added since
+  // the last iteration are new
   for (int j = 0; j < nv; ++j) {
+    const int i0 = j < d.gn ? d.gn : 0;
+    if (i0 >= nv) continue;
     std::vector<double> col;
-    dots_with(d.V, nv, vec(d.S, j), col);
-    for (int i = 0; i < nv; ++i) d.G[(size_t)i * max_sub + j] = col[i];
+    dots_with(vec(d.V, i0), nv - i0, vec(d.S, j), col);
+    for (int i = i0; i < nv; ++i) d.G[(size_t)i * max_sub + j] = col[i - i0];
   }
+  d.gn = nv;
   std::vector<double> Gs((size_t)nv * nv);
+  double gscale = 0;
   for (int i = 0; i < nv; ++i)
-    for (int j = 0; j < nv; ++j) Gs[(size_t)i * nv + j] = d.G[(size_t)i * max_sub + j];
+    for (int j = 0; j < nv; ++j) {
+      Gs[(size_t)i * nv + j] = d.G[(size_t)i * max_sub + j];
+      gscale = std::max(gscale, std::fabs(Gs[(size_t)i * nv + j]));
+    }
   std::vector<double> wr, wi;
   FNO_REQUIRE(nonsym_eigvals(nv, Gs, wr, wi), kENOCONV, "subspace eigenproblem failed");
   std::vector<int> idx(nv);
   for (int i = 0; i < nv; ++i) idx[i] = i;
   std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return wr[a] < wr[b]; });
-  // Ritz vectors and residuals
+  // Ritz coefficients (unit norm: the basis is orthonormal).  A real
+  // eigenvalue takes its eigenvector; the two members of a complex-conjugate
+  // pair (adjacent after the sort) take the real and the imaginary part of
+  // the pair's eigenvector, which span the same real invariant subspace.
+  const double imag_tol = 1e-12 * std::max(gscale, 1.0);
   std::vector<std::vector<double>> Y(nroots);
+  std::vector<std::complex<double>> yc;
+  int yc_root = -2;
   for (int k = 0; k < nroots; ++k) {
-    d.theta[k] = wr[idx[k]];
-    inverse_iteration(nv, Gs, d.theta[k], Y[k]);
+    const int j = idx[k];
+    d.theta[k] = wr[j];
+    d.theta_imag[k] = wi[j];
+    if (std::fabs(wi[j]) <= imag_tol) {
+      inverse_iteration(nv, Gs, wr[j], Y[k]);
+    } else if (yc_root == k - 1 && wr[idx[k - 1]] == wr[j] && wi[idx[k - 1]] == -wi[j]) {
+      Y[k].resize(nv);
+      for (int i = 0; i < nv; ++i) Y[k][i] = yc[i].imag();
+    } else {
+      inverse_iteration_c(nv, Gs, {wr[j], wi[j]}, yc);
+      yc_root = k;
+      Y[k].resize(nv);
+      for (int i = 0; i < nv; ++i) Y[k][i] = yc[i].real();
+    }
+    double nrm = 0;
+    for (double y : Y[k]) nrm += y * y;
+    nrm = std::sqrt(nrm);
+    if (nrm > 0)
+      for (double& y : Y[k]) y /= nrm;
     combine(vec(d.X, k), d.V, Y[k], 1.0, 0.0);
-    std::vector<double> nn;
-    dots_with(vec(d.X, k), 1, vec(d.X, k), nn);
-    const double nrm = std::sqrt(nn[0]);
-    for (double& y : Y[k]) y /= nrm;
-    launch_axpby(vec(d.X, k), vec(d.X, k), 1.0 / nrm, 0.0, dim, e.stream);
   }
   bool all_conv = true;
+  int pending = 0;
   for (int k = 0; k < nroots; ++k) {
     // W = S y - theta x
     combine(d.W, d.S, Y[k], 1.0, 0.0);
@@ -419,7 +458,15 @@ bool Context::dav_update(Davidson& d) {
     dots_with(d.W, 1, d.W, nn);
     d.rn[k] = std::sqrt(nn[0]);
     all_conv = all_conv && d.rn[k] < d.opt.r_tol && std::fabs(d.theta[k] - d.theta_old[k]) < d.opt.e_tol;
+    pending += d.rn[k] >= d.opt.r_tol;
     if (!std::isfinite(d.rn[k])) throw Error(kENONFINITE, "non-finite EOM residual");
+  }
+  if (d.trace) {
+    std::fprintf(stderr, "[fno] davidson it %d nv %d", d.it, nv);
+    for (int k = 0; k < nroots; ++k)
+      std::fprintf(stderr, " | %.10f%s r %.1e", d.theta[k], std::fabs(d.theta_imag[k]) > imag_tol ? "(c)" : "",
+                   d.rn[k]);
+    std::fprintf(stderr, "\n");
   }
   d.theta_old = d.theta;
   if (all_conv) {
@@ -431,27 +478,67 @@ bool Context::dav_update(Davidson& d) {
     d.done = true;
     return true;
   }
-  if (d.nv + nroots > max_sub) {
-    // collapse onto the orthonormalised Ritz vectors
-    int m = 0;
-    for (int k = 0; k < nroots; ++k) {
-      launch_axpby(vec(d.V, m), vec(d.X, k), 1.0, 0.0, dim, e.stream);
-      for (int pass = 0; pass < 2; ++pass) {
-        std::vector<double> c;
-        dots_with(d.V, m, vec(d.V, m), c);
-        if (m) combine(vec(d.V, m), d.V, c, -1.0, 1.0);
+  if (nv + pending > max_sub) {
+    // thick restart: keep the Ritz vectors and those of the previous
+    // iteration, orthonormalised in coefficient space; the sigma vectors
+    // follow by the same combinations, so nothing is recomputed
+    std::vector<std::vector<double>> C;
+    const size_t cap = (size_t)std::max(nroots, max_sub - pending);
+    auto keep = [&](std::vector<double> c) {
+      if (C.size() >= cap) return;
+      c.resize(nv, 0.0);
+      for (int pass = 0; pass < 2; ++pass)
+        for (const auto& q : C) {
+          double t = 0;
+          for (int i = 0; i < nv; ++i) t += q[i] * c[i];
+          for (int i = 0; i < nv; ++i) c[i] -= t * q[i];
+        }
+      double nrm = 0;
+      for (double x : c) nrm += x * x;
+      nrm = std::sqrt(nrm);
+      if (nrm > 1e-8) {
+        for (double& x : c) x /= nrm;
+        C.push_back(std::move(c));
       }
-      std::vector<double> nn;
-      dots_with(vec(d.V, m), 1, vec(d.V, m), nn);
-      if (std::sqrt(nn[0]) > 1e-10) {
-        launch_axpby(vec(d.V, m), vec(d.V, m), 1.0 / std::sqrt(nn[0]), 0.0, dim, e.stream);
-        ++m;
-      }
+    };
+    for (int k = 0; k < nroots; ++k) keep(Y[k]);
+    for (const auto& y : d.yold) keep(y);
+    const int m = (int)C.size();
+    for (double* base : {d.V, d.S}) {
+      for (int j = 0; j < m; ++j) combine(vec(d.T, j), base, C[j], 1.0, 0.0);
+      FNO_HIP(hipMemcpyAsync(base, d.T, (size_t)m * dim * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
     }
-    d.nv = m;
-    d.ns = 0;
-    return false;
+    // G' = C^T G C
+    std::vector<double> GC((size_t)nv * m, 0.0), Gn((size_t)m * m, 0.0);
+    for (int i = 0; i < nv; ++i)
+      for (int b = 0; b < m; ++b) {
+        double t = 0;
+        for (int j = 0; j < nv; ++j) t += Gs[(size_t)i * nv + j] * C[b][j];
+        GC[(size_t)i * m + b] = t;
+      }
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) {
+        double t = 0;
+        for (int i = 0; i < nv; ++i) t += C[a][i] * GC[(size_t)i * m + b];
+        Gn[(size_t)a * m + b] = t;
+      }
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) d.G[(size_t)a * max_sub + b] = Gn[(size_t)a * m + b];
+    // Ritz coefficients in the new basis
+    for (int k = 0; k < nroots; ++k) {
+      std::vector<double> y(m);
+      for (int a = 0; a < m; ++a) {
+        double t = 0;
+        for (int i = 0; i < nv; ++i) t += C[a][i] * Y[k][i];
+        y[a] = t;
+      }
+      Y[k] = std::move(y);
+    }
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    d.nv = d.ns = d.gn = nv = m;
+    if (d.trace) std::fprintf(stderr, "[fno] davidson restart: %d vectors kept\n", m);
   }
+  d.yold = Y;
   // preconditioned residuals, orthogonalised twice (classical Gram-Schmidt)
   for (int k = 0; k < nroots; ++k) {
     if (d.rn[k] < d.opt.r_tol) continue;
@@ -491,7 +578,7 @@ void Context::dav_release() {
   if (!dav_) return;
   Davidson& d = *dav_;
   (void)hipStreamSynchronize(eng->stream);
-  for (double* p : {d.V, d.S, d.X, d.W, d.dco, d.dots}) {
+  for (double* p : {d.V, d.S, d.X, d.W, d.T, d.dco, d.dots}) {
     owned_.erase(std::remove(owned_.begin(), owned_.end(), p), owned_.end());
     (void)hipFree(p);
   }

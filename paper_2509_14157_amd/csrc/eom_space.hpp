@@ -54,10 +54,14 @@ struct Context::Davidson {
   EOMOptions opt;
   int64_t dim = 0;
   int nroots = 0, max_sub = 0;
-  double *V = nullptr, *S = nullptr, *X = nullptr, *W = nullptr, *dco = nullptr, *dots = nullptr;
+  // V: orthonormal basis, S: its sigma vectors, X: Ritz vectors, W: one
+  // residual, T: restart staging (2 * nroots vectors)
+  double *V = nullptr, *S = nullptr, *X = nullptr, *W = nullptr, *T = nullptr, *dco = nullptr, *dots = nullptr;
   int nv = 0, ns = 0, it = 0, status = kENOCONV;
-  bool done = false;
-  std::vector<double> G, theta, theta_old, rn;
+  int gn = 0;  // G = V^T S is valid for the first gn basis vectors
+  bool done = false, trace = false;
+  std::vector<double> G, theta, theta_imag, theta_old, rn;
+  std::vector<std::vector<double>> yold;  // previous iteration's Ritz coefficients
 };
 
 }  // namespace fno

@@ -3,7 +3,7 @@
 // * symmetric eigenproblem: cyclic Jacobi rotations (Golub & Van Loan, 8.5)
 // * nonsymmetric eigenvalues: Householder reduction to upper Hessenberg form
 //   followed by the Francis implicit double-shift QR iteration (GVL 7.5)
-// * eigenvectors of selected real eigenvalues: inverse iteration
+// * eigenvectors of selected eigenvalues: inverse iteration (real or complex shift)
 // * linear systems: Gaussian elimination with partial pivoting
 #include "linalg.hpp"
 
@@ -271,6 +271,55 @@ void inverse_iteration(int n, const std::vector<double>& a, double lambda, std::
     }
     double nrm = 0;
     for (double v : b) nrm += v * v;
+    nrm = std::sqrt(nrm);
+    if (nrm == 0) break;
+    for (int i = 0; i < n; ++i) x[i] = b[i] / nrm;
+  }
+}
+
+bool solve_c(int n, std::vector<std::complex<double>> a, std::vector<std::complex<double>>& b) {
+  auto A = [&](int i, int j) -> std::complex<double>& { return a[(size_t)i * n + j]; };
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::abs(A(r, c)) > std::abs(A(p, c))) p = r;
+    if (std::abs(A(p, c)) < 1e-300) return false;
+    if (p != c) {
+      for (int k = 0; k < n; ++k) std::swap(A(p, k), A(c, k));
+      std::swap(b[p], b[c]);
+    }
+    for (int r = c + 1; r < n; ++r) {
+      const std::complex<double> f = A(r, c) / A(c, c);
+      if (f == 0.0) continue;
+      for (int k = c; k < n; ++k) A(r, k) -= f * A(c, k);
+      b[r] -= f * b[c];
+    }
+  }
+  for (int r = n - 1; r >= 0; --r) {
+    std::complex<double> s = b[r];
+    for (int k = r + 1; k < n; ++k) s -= A(r, k) * b[k];
+    b[r] = s / A(r, r);
+  }
+  return true;
+}
+
+void inverse_iteration_c(int n, const std::vector<double>& a, std::complex<double> lambda,
+                         std::vector<std::complex<double>>& x) {
+  double scale = 0;
+  for (double v : a) scale = std::max(scale, std::fabs(v));
+  const std::complex<double> shift = lambda + 1e-10 * std::max(scale, 1.0);
+  std::vector<std::complex<double>> m(a.begin(), a.end());
+  for (int i = 0; i < n; ++i) m[(size_t)i * n + i] -= shift;
+  x.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) x[i] = 1.0 + 0.01 * i;
+  for (int it = 0; it < 4; ++it) {
+    std::vector<std::complex<double>> b = x;
+    if (!solve_c(n, m, b)) {
+      for (int i = 0; i < n; ++i) m[(size_t)i * n + i] -= 1e-12 * std::max(scale, 1.0);
+      continue;
+    }
+    double nrm = 0;
+    for (auto v : b) nrm += std::norm(v);
     nrm = std::sqrt(nrm);
     if (nrm == 0) break;
     for (int i = 0; i < n; ++i) x[i] = b[i] / nrm;

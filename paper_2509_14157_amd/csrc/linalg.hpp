@@ -1,5 +1,6 @@
 // Small dense host linear algebra used by the solvers.
 #pragma once
+#include <complex>
 #include <vector>
 
 namespace fno {
@@ -11,4 +12,9 @@ bool solve(int n, std::vector<double> a, std::vector<double>& b);
 bool nonsym_eigvals(int n, std::vector<double> a, std::vector<double>& wr, std::vector<double>& wi);
 // Right eigenvector of a for the (real) eigenvalue lambda, unit 2-norm.
 void inverse_iteration(int n, const std::vector<double>& a, double lambda, std::vector<double>& x);
+// Complex versions: solve in place, and the right eigenvector of a real matrix
+// for a complex eigenvalue (unit 2-norm).
+bool solve_c(int n, std::vector<std::complex<double>> a, std::vector<std::complex<double>>& b);
+void inverse_iteration_c(int n, const std::vector<double>& a, std::complex<double> lambda,
+                         std::vector<std::complex<double>>& x);
 }  // namespace fno
