@@ -90,6 +90,28 @@ def cpu_baseline(ham, occt, triples_flops):
     }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "gemm_f64_128x128_ccsdt_o10_v59_hbm_traffic.md")
+
+
+def measured_traffic(kernel, prec):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (copy-calibrated), or None when it covers another kernel or precision, or when
+    the kernel's sources changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        rec = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if rec.get("kernel") != kernel or prec != "fp64":
+        return None
+    for path, digest in rec["sources_sha256"].items():
+        with open(os.path.join(ROOT, path), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def copy_calibration(nbytes=512 << 20, reps=5):
     """A plain copy kernel of known size: under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its
     per-dispatch reading against nbytes gives the scale factor of those counters."""
@@ -177,6 +199,7 @@ def bench_eom(args, nroots=8):
     o, kv = CONFIGS["C3"]["nocc"], CONFIGS["C3"]["keep"]
     out = {}
     with P.Context(0) as c:
+        c.set_graphs(not args.no_graphs)
         c.load_hamiltonian(h.fock, h.eri, o)
         c.truncate(1.0, kv)
         t0 = time.perf_counter()
@@ -307,6 +330,9 @@ def main():
     ap.add_argument("--prec", default="fp64", choices=list(PEAK_TFLOPS))
     ap.add_argument("--occt", type=float, default=0.99)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / split-BF16 section")
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="launch every kernel from the host instead of replaying hipGraphs (for tracers)")
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
@@ -368,7 +394,7 @@ def main():
 
     # timed region: graph replay of the residual sweep; only the dominant GEMM
     # is bracketed by HIP events (it runs between graph segments)
-    ctx.set_graphs(True)
+    ctx.set_graphs(not args.no_graphs)
     ctx.profile(True, only=dom_name)
     t0 = time.perf_counter()
     res = ctx.ccsdt(max_iter=args.steps, prec=args.prec, allow_noconv=True)
@@ -392,7 +418,8 @@ def main():
     peak = PEAK_TFLOPS[args.prec]
     hw = achieved * (3.0 if args.prec == "bf16x3" else 1.0)
     roofline = {"bound": "mfma", "achieved": round(hw, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(hw / peak, 4), "traffic": None, "kernel": dom["name"],
+                "frac": round(hw / peak, 4), "traffic": measured_traffic(dom["name"], args.prec),
+                "algorithmic_bytes": round(dom["bytes"] / dom["launches"]), "kernel": dom["name"],
                 "launches": dom["launches"], "avg_us": round(1e3 * dom["total_ms"] / dom["launches"], 3)}
     witers = wres["iters"]
     breakdown = sorted(wrep["kernels"], key=lambda k: -k["total_ms"])[:6]
@@ -403,8 +430,8 @@ def main():
     # converged energies of the three precisions (mixed runs converge on the
     # FP64-updated residual to 1e-6, FP64 to 1e-8)
     mixed = {}
-    if args.prec == "fp64":
-        ctx.set_graphs(True)
+    if args.prec == "fp64" and not args.no_mixed:
+        ctx.set_graphs(not args.no_graphs)
         e_conv = {}
         for pr in ("fp64", "fp32", "bf16x3"):
             if pr != "fp64":
