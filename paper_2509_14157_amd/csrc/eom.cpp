@@ -324,15 +324,18 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   d->dim = sp.dim;
   d->nroots = opt.nroots;
   FNO_REQUIRE(d->nroots <= d->dim, kEINVAL, "more roots than the EOM space has states");
+  FNO_REQUIRE(d->nroots <= 256, kEINVAL, "at most 256 roots");
   d->max_sub = std::min(std::max(opt.max_sub > 0 ? opt.max_sub : 8 * d->nroots, 2 * d->nroots), 512);
   const int64_t dim = d->dim;
   d->V = alloc((int64_t)d->max_sub * dim);
   d->S = alloc((int64_t)d->max_sub * dim);
   d->X = alloc((int64_t)d->nroots * dim);
-  d->W = alloc(dim);
   d->T = alloc((int64_t)2 * d->nroots * dim);
-  d->dco = alloc(std::max(d->max_sub, d->nroots) + 8);
-  d->dots = alloc(std::max(d->max_sub, 1) + 8);
+  const int64_t small = (int64_t)2 * d->nroots * d->max_sub + 64;
+  d->gres = alloc(small);
+  d->cm = alloc(small);
+  d->gws_bytes = (size_t)256 * (size_t)d->nroots * (size_t)d->max_sub * sizeof(double);
+  d->gws = alloc((int64_t)(d->gws_bytes / sizeof(double)));
   // guesses: unit vectors on the lowest zeroth-order diagonal entries of the
   // principal block, continued into the other blocks when it is too small
   std::vector<double> dall(dim);
@@ -375,35 +378,135 @@ void Context::dav_sigma(Davidson& d) {
   }
 }
 
+namespace {
+// Block operations of the Davidson solver as FP64 MFMA GEMMs over vectors
+// stored one after another (stride dim): each pass streams a block of
+// vectors once, whatever the number of roots.
+struct DavBlock {
+  Engine& e;
+  Context::Davidson& d;
+  int64_t dim;
+  // gres[i][j] = x_i . y_j (i < a, j < b, row-major), a split-K GEMM over dim
+  void gram_dev(const double* X, int a, const double* Y, int b) {
+    GemmArgs g{};
+    g.prec = Prec::FP64;
+    g.M = a;
+    g.N = b;
+    g.K = dim;
+    g.A = X;
+    g.lda = dim;
+    g.a_kfast = true;
+    g.B = Y;
+    g.ldb = dim;
+    g.b_nfast = false;
+    g.C = d.gres;
+    g.ldc = b;
+    g.alpha = 1.0;
+    g.beta = 0.0;
+    g.tile = -1;
+    g.split = gemm_split_factor(g);
+    if (g.split > 1) {
+      FNO_REQUIRE(gemm_split_bytes(g, g.split) <= d.gws_bytes, kEINVAL, "Davidson split-K workspace too small");
+      g.ws = d.gws;
+    }
+    launch_gemm(g, e.stream);
+  }
+  void gram(const double* X, int a, const double* Y, int b, std::vector<double>& out) {
+    out.assign((size_t)a * b, 0.0);
+    if (a == 0 || b == 0) return;
+    gram_dev(X, a, Y, b);
+    FNO_HIP(hipMemcpyAsync(out.data(), d.gres, out.size() * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  }
+  // Y_j = alpha * sum_k c[j][k] x_k + beta * Y_j for j < m, k < n (c row-major
+  // m x n on the device)
+  void combine_dev(double* Y, int m, const double* X, int n, const double* c, double alpha, double beta) {
+    if (m == 0) return;
+    GemmArgs g{};
+    g.prec = Prec::FP64;
+    g.M = m;
+    g.N = dim;
+    g.K = n;
+    g.A = c;
+    g.lda = n;
+    g.a_kfast = true;
+    g.B = X;
+    g.ldb = dim;
+    g.b_nfast = true;
+    g.C = Y;
+    g.ldc = dim;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.tile = -1;
+    g.split = 1;
+    launch_gemm(g, e.stream);
+  }
+  void combine(double* Y, int m, const double* X, int n, const std::vector<double>& c, double alpha, double beta) {
+    if (m == 0) return;
+    FNO_REQUIRE((int64_t)c.size() == (int64_t)m * n, kEINVAL, "coefficient block size");
+    FNO_HIP(hipMemcpyAsync(d.cm, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
+    combine_dev(Y, m, X, n, d.cm, alpha, beta);
+    FNO_HIP(hipStreamSynchronize(e.stream));
+  }
+};
+
+// Cholesky-QR of a block of u vectors with Gram matrix M (u x u): rows of
+// the returned q x u matrix T give orthonormal vectors T w; a vector whose
+// part outside the span of the earlier ones is below tol times its reference
+// norm sqrt(ref[p]) is dropped.
+std::vector<double> chol_qr(const std::vector<double>& M, int u, const std::vector<double>& ref, double tol,
+                            int& q) {
+  std::vector<std::vector<double>> rows;
+  for (int p = 0; p < u; ++p) {
+    std::vector<double> c(rows.size());
+    for (size_t s = 0; s < rows.size(); ++s) {
+      double t = 0;
+      for (int r = 0; r < u; ++r) t += rows[s][r] * M[(size_t)r * u + p];
+      c[s] = t;
+    }
+    double res2 = M[(size_t)p * u + p];
+    for (double x : c) res2 -= x * x;
+    if (!(res2 > tol * tol * ref[p]) || !(res2 > 1e-300)) continue;
+    std::vector<double> t(u, 0.0);
+    t[p] = 1.0;
+    for (size_t s = 0; s < rows.size(); ++s)
+      for (int r = 0; r < u; ++r) t[r] -= c[s] * rows[s][r];
+    const double inv = 1.0 / std::sqrt(res2);
+    for (double& x : t) x *= inv;
+    rows.push_back(std::move(t));
+  }
+  q = (int)rows.size();
+  std::vector<double> out((size_t)q * u);
+  for (int s = 0; s < q; ++s)
+    for (int r = 0; r < u; ++r) out[(size_t)s * u + r] = rows[s][r];
+  return out;
+}
+}  // namespace
+
 bool Context::dav_update(Davidson& d) {
   if (d.done) return true;
   EomSpace& sp = *eom_;
   Engine& e = *eng;
   const int64_t dim = d.dim;
   const int nroots = d.nroots, max_sub = d.max_sub;
+  DavBlock blk{e, d, dim};
   auto vec = [&](double* base, int j) { return base + (int64_t)j * dim; };
-  auto dots_with = [&](const double* xs, int nvec, const double* y, std::vector<double>& out) {
-    out.assign(nvec, 0.0);
-    if (nvec == 0) return;
-    launch_dots(xs, dim, nvec, y, dim, scratch_, d.dots, e.stream);
-    FNO_HIP(hipMemcpyAsync(out.data(), d.dots, nvec * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-    FNO_HIP(hipStreamSynchronize(e.stream));
-  };
-  auto combine = [&](double* y, const double* xs, const std::vector<double>& c, double alpha, double beta) {
-    FNO_HIP(hipMemcpyAsync(d.dco, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
-    launch_combine(y, xs, dim, d.dco, (int)c.size(), alpha, beta, dim, e.stream);
-    FNO_HIP(hipStreamSynchronize(e.stream));
-  };
   ++d.it;
   int nv = d.nv;
   // G[i][j] = v_i . s_j; only the rows and columns of the vectors added since
   // the last iteration are new
-  for (int j = 0; j < nv; ++j) {
-    const int i0 = j < d.gn ? d.gn : 0;
-    if (i0 >= nv) continue;
-    std::vector<double> col;
-    dots_with(vec(d.V, i0), nv - i0, vec(d.S, j), col);
-    for (int i = i0; i < nv; ++i) d.G[(size_t)i * max_sub + j] = col[i - i0];
+  if (d.gn < nv) {
+    const int a = nv - d.gn;
+    std::vector<double> rows;
+    blk.gram(vec(d.V, d.gn), a, d.S, nv, rows);
+    for (int r = 0; r < a; ++r)
+      for (int j = 0; j < nv; ++j) d.G[(size_t)(d.gn + r) * max_sub + j] = rows[(size_t)r * nv + j];
+    if (d.gn > 0) {
+      std::vector<double> cols;
+      blk.gram(vec(d.S, d.gn), a, d.V, d.gn, cols);
+      for (int r = 0; r < a; ++r)
+        for (int i = 0; i < d.gn; ++i) d.G[(size_t)i * max_sub + d.gn + r] = cols[(size_t)r * d.gn + i];
+    }
   }
   d.gn = nv;
   std::vector<double> Gs((size_t)nv * nv);
@@ -446,44 +549,13 @@ bool Context::dav_update(Davidson& d) {
     nrm = std::sqrt(nrm);
     if (nrm > 0)
       for (double& y : Y[k]) y /= nrm;
-    combine(vec(d.X, k), d.V, Y[k], 1.0, 0.0);
   }
-  bool all_conv = true;
-  int pending = 0;
-  for (int k = 0; k < nroots; ++k) {
-    // W = S y - theta x
-    combine(d.W, d.S, Y[k], 1.0, 0.0);
-    launch_axpby(d.W, vec(d.X, k), -d.theta[k], 1.0, dim, e.stream);
-    std::vector<double> nn;
-    dots_with(d.W, 1, d.W, nn);
-    d.rn[k] = std::sqrt(nn[0]);
-    all_conv = all_conv && d.rn[k] < d.opt.r_tol && std::fabs(d.theta[k] - d.theta_old[k]) < d.opt.e_tol;
-    pending += d.rn[k] >= d.opt.r_tol;
-    if (!std::isfinite(d.rn[k])) throw Error(kENONFINITE, "non-finite EOM residual");
-  }
-  if (d.trace) {
-    std::fprintf(stderr, "[fno] davidson it %d nv %d", d.it, nv);
-    for (int k = 0; k < nroots; ++k)
-      std::fprintf(stderr, " | %.10f%s r %.1e", d.theta[k], std::fabs(d.theta_imag[k]) > imag_tol ? "(c)" : "",
-                   d.rn[k]);
-    std::fprintf(stderr, "\n");
-  }
-  d.theta_old = d.theta;
-  if (all_conv) {
-    d.status = kOK;
-    d.done = true;
-    return true;
-  }
-  if (d.it >= d.opt.max_iter) {
-    d.done = true;
-    return true;
-  }
-  if (nv + pending > max_sub) {
+  if (nv + nroots > max_sub) {
     // thick restart: keep the Ritz vectors and those of the previous
     // iteration, orthonormalised in coefficient space; the sigma vectors
     // follow by the same combinations, so nothing is recomputed
     std::vector<std::vector<double>> C;
-    const size_t cap = (size_t)std::max(nroots, max_sub - pending);
+    const size_t cap = (size_t)std::max(nroots, max_sub - nroots);
     auto keep = [&](std::vector<double> c) {
       if (C.size() >= cap) return;
       c.resize(nv, 0.0);
@@ -504,12 +576,15 @@ bool Context::dav_update(Davidson& d) {
     for (int k = 0; k < nroots; ++k) keep(Y[k]);
     for (const auto& y : d.yold) keep(y);
     const int m = (int)C.size();
+    std::vector<double> Cf((size_t)m * nv);
+    for (int a = 0; a < m; ++a)
+      for (int i = 0; i < nv; ++i) Cf[(size_t)a * nv + i] = C[a][i];
     for (double* base : {d.V, d.S}) {
-      for (int j = 0; j < m; ++j) combine(vec(d.T, j), base, C[j], 1.0, 0.0);
+      blk.combine(d.T, m, base, nv, Cf, 1.0, 0.0);
       FNO_HIP(hipMemcpyAsync(base, d.T, (size_t)m * dim * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
     }
-    // G' = C^T G C
-    std::vector<double> GC((size_t)nv * m, 0.0), Gn((size_t)m * m, 0.0);
+    // G' = C G C^T
+    std::vector<double> GC((size_t)nv * m, 0.0);
     for (int i = 0; i < nv; ++i)
       for (int b = 0; b < m; ++b) {
         double t = 0;
@@ -520,10 +595,8 @@ bool Context::dav_update(Davidson& d) {
       for (int b = 0; b < m; ++b) {
         double t = 0;
         for (int i = 0; i < nv; ++i) t += C[a][i] * GC[(size_t)i * m + b];
-        Gn[(size_t)a * m + b] = t;
+        d.G[(size_t)a * max_sub + b] = t;
       }
-    for (int a = 0; a < m; ++a)
-      for (int b = 0; b < m; ++b) d.G[(size_t)a * max_sub + b] = Gn[(size_t)a * m + b];
     // Ritz coefficients in the new basis
     for (int k = 0; k < nroots; ++k) {
       std::vector<double> y(m);
@@ -538,27 +611,71 @@ bool Context::dav_update(Davidson& d) {
     d.nv = d.ns = d.gn = nv = m;
     if (d.trace) std::fprintf(stderr, "[fno] davidson restart: %d vectors kept\n", m);
   }
-  d.yold = Y;
-  // preconditioned residuals, orthogonalised twice (classical Gram-Schmidt)
+  // Ritz vectors X = V y and residuals T = S y - theta V y, for all roots in
+  // three passes over the basis
+  std::vector<double> Yf((size_t)nroots * nv), Yt((size_t)nroots * nv);
+  for (int k = 0; k < nroots; ++k)
+    for (int i = 0; i < nv; ++i) {
+      Yf[(size_t)k * nv + i] = Y[k][i];
+      Yt[(size_t)k * nv + i] = -d.theta[k] * Y[k][i];
+    }
+  blk.combine(d.X, nroots, d.V, nv, Yf, 1.0, 0.0);
+  blk.combine(d.T, nroots, d.S, nv, Yf, 1.0, 0.0);
+  blk.combine(d.T, nroots, d.V, nv, Yt, 1.0, 1.0);
+  std::vector<double> rr;
+  blk.gram(d.T, nroots, d.T, nroots, rr);
+  bool all_conv = true;
   for (int k = 0; k < nroots; ++k) {
-    if (d.rn[k] < d.opt.r_tol) continue;
-    if (d.nv >= max_sub) break;
-    combine(d.W, d.S, Y[k], 1.0, 0.0);
-    launch_axpby(d.W, vec(d.X, k), -d.theta[k], 1.0, dim, e.stream);
-    launch_precond(vec(d.V, d.nv), d.W, sp.diag, d.theta[k], dim, e.stream);
-    for (int pass = 0; pass < 2; ++pass) {
-      std::vector<double> c;
-      dots_with(d.V, d.nv, vec(d.V, d.nv), c);
-      combine(vec(d.V, d.nv), d.V, c, -1.0, 1.0);
-    }
-    std::vector<double> nn;
-    dots_with(vec(d.V, d.nv), 1, vec(d.V, d.nv), nn);
-    const double nrm = std::sqrt(nn[0]);
-    if (nrm > 1e-10) {
-      launch_axpby(vec(d.V, d.nv), vec(d.V, d.nv), 1.0 / nrm, 0.0, dim, e.stream);
-      ++d.nv;
-    }
+    d.rn[k] = std::sqrt(std::max(rr[(size_t)k * nroots + k], 0.0));
+    if (!std::isfinite(d.rn[k])) throw Error(kENONFINITE, "non-finite EOM residual");
+    all_conv = all_conv && d.rn[k] < d.opt.r_tol && std::fabs(d.theta[k] - d.theta_old[k]) < d.opt.e_tol;
   }
+  if (d.trace) {
+    std::fprintf(stderr, "[fno] davidson it %d nv %d", d.it, nv);
+    for (int k = 0; k < nroots; ++k)
+      std::fprintf(stderr, " | %.10f%s r %.1e", d.theta[k], std::fabs(d.theta_imag[k]) > imag_tol ? "(c)" : "",
+                   d.rn[k]);
+    std::fprintf(stderr, "\n");
+  }
+  d.theta_old = d.theta;
+  if (all_conv) {
+    d.status = kOK;
+    d.done = true;
+    return true;
+  }
+  if (d.it >= d.opt.max_iter) {
+    d.done = true;
+    return true;
+  }
+  d.yold = Y;
+  // new directions: preconditioned residuals of the unconverged roots,
+  // orthogonalised against the basis and among themselves (twice: block
+  // Gram-Schmidt against V, then Cholesky-QR within the block)
+  int u = 0;
+  for (int k = 0; k < nroots && nv + u < max_sub; ++k) {
+    if (d.rn[k] < d.opt.r_tol) continue;
+    launch_precond(vec(d.V, nv + u), vec(d.T, k), sp.diag, d.theta[k], dim, e.stream);
+    ++u;
+  }
+  if (u == 0) return false;
+  double* P = vec(d.V, nv);
+  std::vector<double> M;
+  blk.gram(P, u, P, u, M);
+  std::vector<double> ref(u);
+  for (int p = 0; p < u; ++p) ref[p] = M[(size_t)p * u + p];
+  for (int pass = 0; pass < 2 && u > 0; ++pass) {
+    blk.gram_dev(P, u, d.V, nv);
+    blk.combine_dev(P, u, d.V, nv, d.gres, -1.0, 1.0);
+    blk.gram(P, u, P, u, M);
+    int q = 0;
+    const std::vector<double> Tq = chol_qr(M, u, ref, pass == 0 ? 1e-8 : 1e-6, q);
+    blk.combine(d.T, q, P, u, Tq, 1.0, 0.0);
+    FNO_HIP(hipMemcpyAsync(P, d.T, (size_t)q * dim * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+    u = q;
+    ref.assign(u, 1.0);
+  }
+  FNO_HIP(hipStreamSynchronize(e.stream));
+  d.nv = nv + u;
   return false;
 }
 
@@ -578,7 +695,7 @@ void Context::dav_release() {
   if (!dav_) return;
   Davidson& d = *dav_;
   (void)hipStreamSynchronize(eng->stream);
-  for (double* p : {d.V, d.S, d.X, d.W, d.T, d.dco, d.dots}) {
+  for (double* p : {d.V, d.S, d.X, d.T, d.gres, d.cm, d.gws}) {
     owned_.erase(std::remove(owned_.begin(), owned_.end(), p), owned_.end());
     (void)hipFree(p);
   }

@@ -54,9 +54,11 @@ struct Context::Davidson {
   EOMOptions opt;
   int64_t dim = 0;
   int nroots = 0, max_sub = 0;
-  // V: orthonormal basis, S: its sigma vectors, X: Ritz vectors, W: one
-  // residual, T: restart staging (2 * nroots vectors)
-  double *V = nullptr, *S = nullptr, *X = nullptr, *W = nullptr, *T = nullptr, *dco = nullptr, *dots = nullptr;
+  // V: orthonormal basis, S: its sigma vectors, X: Ritz vectors, T: residuals
+  // and staging (2 * nroots vectors); small device matrices: gres (products
+  // of vector blocks), cm (combination coefficients), gws (split-K partials)
+  double *V = nullptr, *S = nullptr, *X = nullptr, *T = nullptr, *gres = nullptr, *cm = nullptr, *gws = nullptr;
+  size_t gws_bytes = 0;
   int nv = 0, ns = 0, it = 0, status = kENOCONV;
   int gn = 0;  // G = V^T S is valid for the first gn basis vectors
   bool done = false, trace = false;
