@@ -496,9 +496,9 @@ struct TileCfg {
   int bm, bn;
   int bk;  // double-buffered k-tile depth (FP64 / FP32); 0 = single-buffered BK = 16
 };
-static const TileCfg kTiles[] = {{64, 64, 0},    {128, 64, 0},  {64, 128, 0},  {128, 128, 0}, {32, 64, 0},
+static const TileCfg kTiles[] = {{64, 64, 0},    {128, 64, 0},   {64, 128, 0},   {128, 128, 0}, {32, 64, 0},
                                  {64, 32, 0},    {128, 128, 16}, {128, 128, 32}, {128, 64, 32}, {64, 128, 32},
-                                 {64, 64, 32}};
+                                 {64, 64, 32},   {256, 64, 0},   {64, 256, 0}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(Prec) { return kNumTiles; }
@@ -613,6 +613,18 @@ static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
     launch_b3<BM, BN>(g, s);
 }
 
+// Tall and wide single-buffered tiles (one operand re-read fewer times when
+// the other extent is small); split-BF16 runs them as 128 x 64.
+template <int BM, int BN>
+static void dispatch_tall(const GemmArgs& g, hipStream_t s) {
+  if (g.prec == Prec::FP64)
+    launch_k4<double, BM, BN>(g, s);
+  else if (g.prec == Prec::FP32)
+    launch_k4<float, BM, BN>(g, s);
+  else
+    launch_b3<128, 64>(g, s);
+}
+
 template <typename T, int BM, int BN, int BK>
 static void launch_db(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
@@ -676,7 +688,10 @@ std::string gemm_label(const GemmArgs& g) {
   int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
   std::string bm = std::to_string(kTiles[t].bm), bn = std::to_string(kTiles[t].bn);
   std::string lay = std::string(g.a_kfast ? "true" : "false") + ", " + (g.b_nfast ? "true" : "false");
-  if (g.prec == Prec::BF16X3) return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ">";
+  if (g.prec == Prec::BF16X3) {
+    if (kTiles[t].bm == 256 || kTiles[t].bn == 256) bm = "128", bn = "64";
+    return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ">";
+  }
   if (kTiles[t].bk > 0)
     return std::string("fno::gemm_db_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " +
            bn + ", " + std::to_string(kTiles[t].bk) + ", " + lay + ">";
@@ -698,7 +713,9 @@ void launch_gemm(const GemmArgs& g, hipStream_t s) {
     case 7: dispatch_db<128, 128, 32>(g, s); break;
     case 8: dispatch_db<128, 64, 32>(g, s); break;
     case 9: dispatch_db<64, 128, 32>(g, s); break;
-    default: dispatch_db<64, 64, 32>(g, s); break;
+    case 10: dispatch_db<64, 64, 32>(g, s); break;
+    case 11: dispatch_tall<256, 64>(g, s); break;
+    default: dispatch_tall<64, 256>(g, s); break;
   }
   FNO_HIP(hipGetLastError());
 }

@@ -8,6 +8,15 @@
 
 namespace fno {
 
+// Workgroup b of a launch runs on XCD b % 8.  xcd_chunk maps b to a logical
+// block so that each XCD walks one contiguous range of the n blocks:
+// neighbouring blocks, which share source rows and cache lines, then meet in
+// the same L2.  A bijection on [0, n).
+__device__ __forceinline__ int64_t xcd_chunk(int64_t b, int64_t n) {
+  const int64_t q = n / 8, r = n % 8, x = b % 8, k = b / 8;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // ---------------------------------------------------------------- expand
 // dst[r, c] (rows x cols, row-major when col_fast, else column-major) =
 //   sign * src[operand(r, c)], converted to the GEMM operand precision.
@@ -497,14 +506,16 @@ void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, con
 template <typename Out>
 __global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const double* __restrict__ src,
                                                          Out* __restrict__ dst) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t L = xcd_chunk((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+  const int64_t bx = L % gridDim.x, by = L / gridDim.x;
+  const int64_t c = bx * blockDim.x + threadIdx.x;
   if (c >= t.cols) return;
   const int64_t co = t.col_off[c];
   const int cs = t.col_sign[c];
   int32_t csub0 = 0, csub1 = 0;
   if (t.nmixed > 0) csub0 = t.col_sub[0][c];
   if (t.nmixed > 1) csub1 = t.col_sub[1][c];
-  for (int64_t r = blockIdx.y; r < t.rows; r += gridDim.y) {
+  for (int64_t r = by; r < t.rows; r += gridDim.y) {
     int64_t o = t.row_off[r] + co;
     int s = t.row_sign[r] * cs;
     if (t.nmixed > 0) {
@@ -525,14 +536,16 @@ __global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const doub
 __global__ void __launch_bounds__(256) expand_tab_bf16_kernel(ExpandTab t, const double* __restrict__ src,
                                                               __hip_bfloat16* __restrict__ hi,
                                                               __hip_bfloat16* __restrict__ lo) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t L = xcd_chunk((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
+  const int64_t bx = L % gridDim.x, by = L / gridDim.x;
+  const int64_t c = bx * blockDim.x + threadIdx.x;
   if (c >= t.cols) return;
   const int64_t co = t.col_off[c];
   const int cs = t.col_sign[c];
   int32_t csub0 = 0, csub1 = 0;
   if (t.nmixed > 0) csub0 = t.col_sub[0][c];
   if (t.nmixed > 1) csub1 = t.col_sub[1][c];
-  for (int64_t r = blockIdx.y; r < t.rows; r += gridDim.y) {
+  for (int64_t r = by; r < t.rows; r += gridDim.y) {
     int64_t o = t.row_off[r] + co;
     int s = t.row_sign[r] * cs;
     if (t.nmixed > 0) {
@@ -557,7 +570,8 @@ template <int MODE>  // 0 = FP64, 1 = FP32, 2 = split-BF16
 __global__ void __launch_bounds__(256) expand_tab_flat_kernel(ExpandTab t, const double* __restrict__ src, void* dst,
                                                               void* dst_lo) {
   const int64_t total = t.rows * t.cols;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t first = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = first; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = t.cols == 1 ? i : i / t.cols;
     const int64_t c = i - r * t.cols;
     int64_t o = t.row_off[r] + t.col_off[c];
@@ -612,7 +626,8 @@ void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* d
 template <typename XT>
 __global__ void __launch_bounds__(256) fold_tab_kernel(FoldTab t, const XT* __restrict__ X, double* __restrict__ out,
                                                        double alpha, int64_t total) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+  const int64_t first = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  for (int64_t e = first; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     int64_t u[kMaxOutGroups];
     int64_t idx = e;
     for (int k = t.ngroups - 1; k >= 0; --k) {
