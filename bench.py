@@ -301,7 +301,7 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
             _log(f"[bench] {name}: {r['iters']} iterations, {dt:.2f} s, E={r['e_tot']:.8f}")
             if guess == 0:
                 t0 = time.perf_counter()
-                e = c.eom("EA", nroots=8, r_tol=1e-4, e_tol=1e-6, max_iter=60, allow_noconv=True)
+                e = c.eom("EA", nroots=8, r_tol=1e-4, e_tol=1e-6, max_iter=100, allow_noconv=True)
                 eom = {"s": round(time.perf_counter() - t0, 3), "iters": e["iters"], "converged": e["converged"],
                        "omega": [round(float(w), 8) for w in np.sort(e["omega"])]}
                 _log(f"[bench] EOM-EA 8 roots: {eom['iters']} iterations, {eom['s']:.2f} s")

@@ -108,12 +108,14 @@ typedef enum { FNO_IP = 1, FNO_DIP = 2, FNO_EA = 3, FNO_DEA = 4 } fno_eom_kind;
 typedef struct {
   int nroots;       /* number of roots (lowest real parts) */
   int max_iter;     /* Davidson iterations, default 60 */
-  int max_sub;      /* subspace size before collapse, default 8 * nroots */
+  int max_sub;      /* subspace size before a thick restart (the Ritz vectors of this
+                       and the previous iteration are kept), default 8 * nroots */
   double e_tol;     /* |Delta omega| tolerance */
   double r_tol;     /* residual-norm tolerance */
   fno_prec prec;    /* precision of the R3 sigma contractions */
   int guess;        /* 0 = unit vectors on the lowest principal-block diagonal */
-  int precond;      /* 0 = (omega - D)^-1 with the zeroth-order diagonal D */
+  int precond;      /* 0 = (omega - D)^-1, D the one-body H-bar diagonal (dressed
+                       Fock diagonal at the CC amplitudes, particles minus holes) */
   int block;        /* sigma vectors evaluated together (the R-derived tensors hold a
                        block of vectors; every contraction covers the block in one
                        GEMM); 0 = nroots, at most 16 */
@@ -248,8 +250,9 @@ int fno_debug_gemm(fno_ctx *ctx, fno_prec prec, int tile, long M, long N, long K
  * orbital energies -- to a correction of the guess (t3 = x + rms(x) y0) and a
  * shift y1 of that element's Jacobi denominator (kept within [2D, D/2]).
  * With fno_cc_opts.guess = 1 and a model set on the context, fno_ccsdt applies
- * it after its second iteration; if the next residual norm is not smaller
- * than the previous one, the plain guess and denominators are restored.
+ * it after its second iteration and evaluates the residual at both starts
+ * (that extra evaluation counts as an iteration); the start with the smaller
+ * residual norm is kept, so a poor network falls back to the plain guess.
  * Training (FP32, Adam) and inference (single-BF16 operands, FP32
  * accumulation) run on the device with the library's kernels.
  */
