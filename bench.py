@@ -140,6 +140,7 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
     for o, v, seed in shapes:
         h = make_hamiltonian(o, full_virtuals_for(v), seed)
         c = P.Context(0)
+        c.set_graphs(not args.no_graphs)
         c.load_hamiltonian(h.fock, h.eri, o)
         kept, _, _ = c.truncate(1.0, v)
         assert kept == v
@@ -266,6 +267,7 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
             fock, eri = fut.result()
             futures[k] = None
             with P.Context(0) as c:
+                c.set_graphs(not args.no_graphs)
                 c.load_hamiltonian(fock, eri, o_tr)
                 c.truncate(1.0, keep)
                 r = c.ccsdt(r_tol=1e-8, e_tol=1e-10, max_iter=60, allow_noconv=True)
@@ -286,6 +288,7 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
     eom = None
     for name, guess in (("plain", 0), ("learned", 1)):
         with P.Context(0) as c:
+            c.set_graphs(not args.no_graphs)
             c.load_hamiltonian(h.fock, h.eri, o)
             c.truncate(1.0, kv)
             c.set_guess_model(net)

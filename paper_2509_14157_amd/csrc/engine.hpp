@@ -82,14 +82,21 @@ struct GemmStats {
   double flops = 0;
 };
 
-// A recorded sequence of launches: graph segments, and between them the
-// kernels kept out of the graphs so that they can be timed with events.
+// A recorded sequence of launches (one instantiated hipGraph; empty when
+// nothing was captured), with the kernels timed inside it.
 struct Program {
   struct Item {
     hipGraphExec_t exec = nullptr;
-    std::function<void()> run;
   };
   std::vector<Item> items;
+  // kernels timed inside the graph: event-record nodes around them, read
+  // after every replay
+  struct Timer {
+    std::string label, spec;
+    double flops, bytes;
+    hipEvent_t a, b;
+  };
+  std::vector<Timer> timers;
   uint64_t epoch = 0;  // engine epoch the recording is valid for
   int prec = -1;
   bool profiled = false;
@@ -99,6 +106,11 @@ struct Program {
     for (auto& it : items)
       if (it.exec) (void)hipGraphExecDestroy(it.exec);
     items.clear();
+    for (auto& t : timers) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    timers.clear();
   }
   ~Program() { clear(); }
 };
@@ -146,8 +158,8 @@ class Engine {
   bool record = false;
   std::vector<GemmStats> stats;
 
-  // --- recording into a Program (hipGraph segments); nothing executes while
-  // recording: replay the program to run it
+  // --- recording into a Program (stream capture into a hipGraph); nothing
+  // executes while recording: replay the program to run it
   void begin_record(Program& prog);
   void end_record(Program& prog);
   void abort_record();  // after an error while recording: discard the capture
@@ -189,7 +201,6 @@ class Engine {
   std::map<std::string, std::shared_ptr<Plan>> plans_;
   hipStream_t own_stream_ = nullptr;
   Program* rec_ = nullptr;
-  void split_record(std::function<void()> run);
   struct CacheEntry {
     std::string tensor;
     void* hi = nullptr;
@@ -212,6 +223,7 @@ class Engine {
     std::string label, spec;
     double flops, bytes;
     hipEvent_t a, b;
+    float ms = -1.0f;  // already read (graph timers), else from the events
   };
   std::vector<ProfRec> prof_;
   std::vector<hipEvent_t> evpool_;

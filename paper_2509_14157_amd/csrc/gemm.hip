@@ -684,6 +684,8 @@ size_t gemm_split_bytes(const GemmArgs& g, int split) {
   return (size_t)split * (size_t)(g.M * g.N) * (g.prec == Prec::FP64 ? 8 : 4);
 }
 
+int gemm_default_tile(const GemmArgs& g) { return default_tile(g); }
+
 std::string gemm_label(const GemmArgs& g) {
   int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
   std::string bm = std::to_string(kTiles[t].bm), bn = std::to_string(kTiles[t].bn);

@@ -289,6 +289,21 @@ __global__ void __launch_bounds__(256) dot_final_kernel(const double* __restrict
   if (threadIdx.x == 0) out[j] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
+__global__ void __launch_bounds__(256) dot_final_acc_kernel(const double* __restrict__ partial, int nblk,
+                                                            double* __restrict__ out, double alpha, double beta) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  __shared__ double wsum[4];
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double d = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    out[0] = beta != 0.0 ? alpha * d + beta * out[0] : alpha * d;
+  }
+}
+
 int dot_partial_blocks(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > kDotBlocks) b = kDotBlocks;
@@ -303,6 +318,15 @@ void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64
   dot_partial_kernel<<<dim3(nb, nvec), dim3(256), 0, s>>>(xs, ldx, y, n, partial);
   FNO_HIP(hipGetLastError());
   dot_final_kernel<<<dim3(nvec), dim3(256), 0, s>>>(partial, nb, out);
+  FNO_HIP(hipGetLastError());
+}
+
+void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial, double* out, double alpha,
+                    double beta, hipStream_t s) {
+  int nb = dot_partial_blocks(n);
+  dot_partial_kernel<<<dim3(nb, 1), dim3(256), 0, s>>>(x, n, y, n, partial);
+  FNO_HIP(hipGetLastError());
+  dot_final_acc_kernel<<<dim3(1), dim3(256), 0, s>>>(partial, nb, out, alpha, beta);
   FNO_HIP(hipGetLastError());
 }
 
@@ -515,7 +539,11 @@ __global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const doub
   int32_t csub0 = 0, csub1 = 0;
   if (t.nmixed > 0) csub0 = t.col_sub[0][c];
   if (t.nmixed > 1) csub1 = t.col_sub[1][c];
-  for (int64_t r = by; r < t.rows; r += gridDim.y) {
+  // a contiguous range of rows per block: neighbouring rows gather from
+  // neighbouring source elements, so the cache lines are reused
+  const int64_t per = (t.rows + gridDim.y - 1) / gridDim.y;
+  const int64_t r_end = (by + 1) * per < t.rows ? (by + 1) * per : t.rows;
+  for (int64_t r = by * per; r < r_end; ++r) {
     int64_t o = t.row_off[r] + co;
     int s = t.row_sign[r] * cs;
     if (t.nmixed > 0) {
@@ -545,7 +573,11 @@ __global__ void __launch_bounds__(256) expand_tab_bf16_kernel(ExpandTab t, const
   int32_t csub0 = 0, csub1 = 0;
   if (t.nmixed > 0) csub0 = t.col_sub[0][c];
   if (t.nmixed > 1) csub1 = t.col_sub[1][c];
-  for (int64_t r = by; r < t.rows; r += gridDim.y) {
+  // a contiguous range of rows per block: neighbouring rows gather from
+  // neighbouring source elements, so the cache lines are reused
+  const int64_t per = (t.rows + gridDim.y - 1) / gridDim.y;
+  const int64_t r_end = (by + 1) * per < t.rows ? (by + 1) * per : t.rows;
+  for (int64_t r = by * per; r < r_end; ++r) {
     int64_t o = t.row_off[r] + co;
     int s = t.row_sign[r] * cs;
     if (t.nmixed > 0) {
@@ -648,14 +680,68 @@ __global__ void __launch_bounds__(256) fold_tab_kernel(FoldTab t, const XT* __re
   }
 }
 
+// Same fold with the group and combo counts fixed at compile time: the loops
+// unroll, so every table entry and every X element of one output is requested
+// before the first is used (two memory round trips per output instead of a
+// chain of dependent ones).  Summation order as in fold_tab_kernel.
+template <typename XT, int NG, int NC>
+__global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT* __restrict__ X,
+                                                             double* __restrict__ out, double alpha, int64_t total) {
+  const int64_t first = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  for (int64_t e = first; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    int64_t u[NG];
+    int64_t idx = e;
+#pragma unroll
+    for (int k = NG - 1; k >= 0; --k) {
+      u[k] = idx % t.count[k];
+      idx /= t.count[k];
+    }
+    int64_t addr[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      int64_t r = 0, col = 0;
+#pragma unroll
+      for (int k = 0; k < NG; ++k) {
+        const int64_t j = (int64_t)t.combo[c][k] * t.count[k] + u[k];
+        r += t.rowc[k][j];
+        col += t.colc[k][j];
+      }
+      addr[c] = r * t.xcols + col;
+    }
+    double v[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = (double)X[addr[c]];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc += t.csign[c] * v[c];
+    out[e] += alpha * acc;
+  }
+}
+
+template <typename XT>
+static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha, int64_t total, hipStream_t s) {
+  const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
+#define FNO_FOLD_CASE(NG, NC)                                                                  \
+  if (t.ngroups == NG && t.ncombo == NC) {                                                     \
+    fold_tab_fixed_kernel<XT, NG, NC><<<grid, 256, 0, s>>>(t, X, out, alpha, total);           \
+    return;                                                                                    \
+  }
+  FNO_FOLD_CASE(1, 1) FNO_FOLD_CASE(1, 2) FNO_FOLD_CASE(1, 3) FNO_FOLD_CASE(1, 4) FNO_FOLD_CASE(1, 6)
+  FNO_FOLD_CASE(2, 1) FNO_FOLD_CASE(2, 2) FNO_FOLD_CASE(2, 3) FNO_FOLD_CASE(2, 4) FNO_FOLD_CASE(2, 6)
+  FNO_FOLD_CASE(2, 9) FNO_FOLD_CASE(2, 12) FNO_FOLD_CASE(2, 18)
+  FNO_FOLD_CASE(3, 1) FNO_FOLD_CASE(3, 2) FNO_FOLD_CASE(3, 3) FNO_FOLD_CASE(3, 4) FNO_FOLD_CASE(3, 6)
+  FNO_FOLD_CASE(3, 9)
+#undef FNO_FOLD_CASE
+  fold_tab_kernel<XT><<<grid, 256, 0, s>>>(t, X, out, alpha, total);
+}
+
 void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, double alpha, int64_t total,
                      hipStream_t s) {
   if (total == 0) return;
-  int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   if (xprec == Prec::FP64)
-    fold_tab_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(t, (const double*)X, out, alpha, total);
+    fold_launch<double>(t, (const double*)X, out, alpha, total, s);
   else
-    fold_tab_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(t, (const float*)X, out, alpha, total);
+    fold_launch<float>(t, (const float*)X, out, alpha, total, s);
   FNO_HIP(hipGetLastError());
 }
 

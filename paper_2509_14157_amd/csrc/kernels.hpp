@@ -41,6 +41,10 @@ void launch_denominators(const IndexTables& tb, const MatDim& dims, int nh, cons
 void launch_jacobi(double* t, const double* r, const double* d, double* step, int64_t n, hipStream_t s);
 void launch_precond(double* y, const double* x, const double* d, double shift, int64_t n, hipStream_t s);
 int dot_partial_blocks(int64_t n);
+// out[0] = alpha * (x . y) + beta * out[0] over n contiguous elements
+// (partial needs dot_partial_blocks(n) doubles); deterministic.
+void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial, double* out, double alpha,
+                    double beta, hipStream_t s);
 void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64_t n, double* partial, double* out,
                  hipStream_t s);
 void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, int nvec, double alpha, double beta,
@@ -80,6 +84,7 @@ void launch_gemm(const GemmArgs& g, hipStream_t s);
 // Name of the kernel instantiation launch_gemm would use (as tools demangle it).
 std::string gemm_label(const GemmArgs& g);
 int gemm_num_tiles(Prec p);
+int gemm_default_tile(const GemmArgs& g);  // the tile launch_gemm uses for tile = -1
 
 
 // ---- learned guess: MLP building blocks (FP32) and T3 feature / guess kernels

@@ -111,6 +111,22 @@ def test_roots_match_oracle(P, kind, o, v):
     assert np.abs(np.sort(r["omega"]) - w).max() < 1e-8
 
 
+@pytest.mark.parametrize("kind,o,v", [("IP", 3, 6), ("EA", 3, 5), ("DIP", 4, 4), ("DEA", 2, 6)])
+def test_thick_restart_reaches_dense_roots(P, kind, o, v):
+    """A subspace of 2 * nroots vectors restarts at every iteration: the kept
+    Ritz vectors, with their sigma vectors carried by the same combinations,
+    must still converge to the roots of the explicit EOM matrix."""
+    h = make_hamiltonian(o, v, 37)
+    ref = cc.solve_ccsdt(h.fock, h.eri, o, r_tol=1e-10, e_tol=1e-12)
+    w, _, _ = cc.eom_roots_dense(h.fock, h.eri, o, ref["amps"], kind, 2)
+    assert np.abs(w.imag).max() < 1e-10
+    with _ctx(P, h.fock, h.eri, o) as c:
+        c.ccsdt(r_tol=1e-10, e_tol=1e-12)
+        r = c.eom(kind, nroots=2, max_sub=4, max_iter=300, r_tol=1e-8, e_tol=1e-10)
+    assert r["converged"]
+    assert np.abs(np.sort(r["omega"]) - np.sort(w.real)).max() < 1e-8
+
+
 @pytest.mark.parametrize("kind,prec", [("EA", "fp32"), ("EA", "bf16x3"), ("DIP", "fp32"), ("DEA", "fp32"),
                                        ("DEA", "bf16x3")])
 def test_mixed_precision_roots(P, kind, prec):
