@@ -280,19 +280,39 @@ void Context::residual_body(Prec tri) {
     // the amplitudes are fixed during the sweep: their expanded operand
     // matrices are shared between terms (the ring, R1 and the F_ov term of R2
     // use one layout of T3; the T3 pieces of W3_vvvo/W3_ovoo and the G terms
-    // of R2 another).  The triples terms run first so that the largest GEMM
-    // (the ring) fixes the stored orientation.
+    // of R2 another).  The triples terms are issued first so that the largest
+    // GEMM (the ring) fixes the stored orientation.
     CacheScope cache(e, {"T1", "T2", "T3"});
-    // dressing, intermediates and the singles/doubles residual are FP64; the
-    // triples residual contractions (ladders, ring, one-body, drivers) run in
-    // the requested precision and accumulate into the FP64 residual
-    e.terms(kCCInter2, count(kCCInter2));
+    struct Join {  // the side lane is joined on every exit
+      Engine& e;
+      ~Join() {
+        try {
+          e.join_side();
+        } catch (...) {
+        }
+      }
+    } join{e};
+    // two lanes from here: the triples intermediates and residual on the main
+    // stream; the doubles intermediates and the singles/doubles residual on
+    // the side lane, concurrently (they read T and the dressed integrals
+    // only, and write R1, R2 and the W2/F2 blocks).  Dressing, intermediates
+    // and the singles/doubles residual are FP64; the triples residual
+    // contractions run in the requested precision and accumulate into the
+    // FP64 residual.
+    e.fork_mark();
     e.terms(kCCInter3, count(kCCInter3));
     e.prec = tri;
     e.terms(kCCR3, count(kCCR3));
     e.prec = Prec::FP64;
-    e.terms(kCCR1, count(kCCR1));
-    e.terms(kCCR2, count(kCCR2));
+    e.begin_side();
+    e.terms(kCCInter2, count(kCCInter2));
+    // T3 terms last: they use expansions made by the triples terms
+    std::vector<const char*> late;
+    for (const char* t : kCCR1) (std::strstr(t, "T3[") ? late.push_back(t) : e.term(t));
+    for (const char* t : kCCR2) (std::strstr(t, "T3[") ? late.push_back(t) : e.term(t));
+    for (const char* t : late) e.term(t);
+    e.end_side();
+    e.join_side();
   }
   e.prec = tri;
   e.record = false;

@@ -63,17 +63,68 @@ Engine::~Engine() {
   (void)hipDeviceSynchronize();
   for (auto& kv : reg_)
     if (kv.second->owner && kv.second->d) (void)hipFree(kv.second->d);
-  for (int i = 0; i < 7; ++i)
+  for (int i = 0; i < 7; ++i) {
     if (ws_[i]) (void)hipFree(ws_[i]);
+    if (other_ws_[i]) (void)hipFree(other_ws_[i]);
+  }
   for (auto ev : evpool_) (void)hipEventDestroy(ev);
   for (auto& kv : ecache_) {
     if (kv.second.hi) (void)hipFree(kv.second.hi);
     if (kv.second.lo) (void)hipFree(kv.second.lo);
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   }
+  if (fork_ev_) (void)hipEventDestroy(fork_ev_);
+  if (join_ev_) (void)hipEventDestroy(join_ev_);
+  if (side_stream_) (void)hipStreamDestroy(side_stream_);
   if (d_binom_) (void)hipFree(d_binom_);
   for (int g = 0; g <= kMaxGroup; ++g)
     if (d_dec_[g]) (void)hipFree(d_dec_[g]);
   if (own_stream_) (void)hipStreamDestroy(own_stream_);
+}
+
+// ------------------------------------------------------------------ lanes
+void Engine::swap_lanes() {
+  std::swap(stream, other_stream_);
+  for (int i = 0; i < 7; ++i) {
+    std::swap(ws_[i], other_ws_[i]);
+    std::swap(ws_bytes_[i], other_ws_bytes_[i]);
+  }
+  lane_ = 1 - lane_;
+}
+
+void Engine::fork_mark() {
+  FNO_REQUIRE(lane_ == 0 && !side_open_ && !fork_marked_, kEINVAL, "side lane already forked");
+  if (!side_stream_) {
+    FNO_REQUIRE(!rec_, kEINVAL, "side lane created while recording");
+    FNO_HIP(hipStreamCreate(&side_stream_));
+    FNO_HIP(hipEventCreateWithFlags(&fork_ev_, hipEventDisableTiming));
+    FNO_HIP(hipEventCreateWithFlags(&join_ev_, hipEventDisableTiming));
+  }
+  FNO_HIP(hipEventRecord(fork_ev_, stream));
+  fork_marked_ = true;
+}
+
+void Engine::begin_side() {
+  FNO_REQUIRE(lane_ == 0 && !side_open_, kEINVAL, "side lane already open");
+  if (!fork_marked_) fork_mark();
+  FNO_HIP(hipStreamWaitEvent(side_stream_, fork_ev_, 0));
+  other_stream_ = side_stream_;
+  swap_lanes();
+  side_open_ = true;
+}
+
+void Engine::end_side() {
+  FNO_REQUIRE(lane_ == 1, kEINVAL, "not issuing to the side lane");
+  FNO_HIP(hipEventRecord(join_ev_, stream));
+  swap_lanes();
+}
+
+void Engine::join_side() {
+  if (lane_ == 1) end_side();
+  fork_marked_ = false;
+  if (!side_open_) return;
+  side_open_ = false;
+  FNO_HIP(hipStreamWaitEvent(stream, join_ev_, 0));
 }
 
 // ------------------------------------------------------------------ recording
@@ -122,7 +173,7 @@ void Engine::replay(const Program& prog) {
   for (auto& it : prog.items) FNO_HIP(hipGraphLaunch(it.exec, stream));
   if (!prog.timers.empty()) {
     // the event nodes are re-recorded by the next replay: read them now
-    FNO_HIP(hipEventSynchronize(prog.timers.back().b));
+    for (const auto& t : prog.timers) FNO_HIP(hipEventSynchronize(t.b));
     for (const auto& t : prog.timers) {
       float ms = 0;
       FNO_HIP(hipEventElapsedTime(&ms, t.a, t.b));
@@ -165,6 +216,7 @@ void Engine::prof_mark(const std::string& label, const std::string& spec, double
 
 std::string Engine::profile_report() {
   FNO_HIP(hipStreamSynchronize(stream));
+  if (side_stream_) FNO_HIP(hipStreamSynchronize(side_stream_));
   struct Agg {
     int64_t n = 0;
     double ms = 0, flops = 0, bytes = 0;
@@ -1077,8 +1129,12 @@ void Engine::execute(const Plan& p, double scale) {
                     int64_t rows, int64_t cols, bool tab_ok, const ExpandTab& tab, const OperandDesc& od,
                     const MatDim& r, const MatDim& c, const void*& hi, const void*& lo, bool& fast, int64_t& ld) {
     if (!ok || !is_cacheable(t->name)) return false;
+    auto other_lane = [&](const CacheEntry& ce) {
+      if (fork_marked_ && ce.ready_set && ce.lane != lane_) FNO_HIP(hipStreamWaitEvent(stream, ce.ready, 0));
+    };
     auto it = ecache_.find(key);
     if (it != ecache_.end() && it->second.valid) {
+      other_lane(it->second);
       hi = it->second.hi;
       lo = it->second.lo;
       fast = true;
@@ -1088,6 +1144,7 @@ void Engine::execute(const Plan& p, double scale) {
     }
     it = ecache_.find(keyT);
     if (it != ecache_.end() && it->second.valid) {
+      other_lane(it->second);
       hi = it->second.hi;
       lo = it->second.lo;
       fast = false;
@@ -1113,6 +1170,15 @@ void Engine::execute(const Plan& p, double scale) {
     expand_into(t, tab_ok, tab, od, r, c, ce.hi, ce.lo);
     ce.sign = sgn;
     ce.valid = true;
+    ce.lane = lane_;
+    ce.ready_set = fork_marked_;
+    if (fork_marked_) {
+      if (!ce.ready) {
+        FNO_REQUIRE(!rec_, kEINVAL, "cache event created while recording");
+        FNO_HIP(hipEventCreateWithFlags(&ce.ready, hipEventDisableTiming));
+      }
+      FNO_HIP(hipEventRecord(ce.ready, stream));
+    }
     hi = ce.hi;
     lo = ce.lo;
     fast = true;

@@ -158,6 +158,18 @@ class Engine {
   bool record = false;
   std::vector<GemmStats> stats;
 
+  // --- a second lane.  fork_mark() notes the main stream's current point;
+  // terms issued between begin_side() and end_side() run on a side stream
+  // (with its own workspaces) that starts from that point, concurrently with
+  // whatever the main stream runs after it; join_side() makes the main stream
+  // wait for the side lane.  Expansion-cache entries made after the mark are
+  // followed by an event, and a lane using an entry made by the other waits
+  // for it.
+  void fork_mark();
+  void begin_side();
+  void end_side();
+  void join_side();
+
   // --- recording into a Program (stream capture into a hipGraph); nothing
   // executes while recording: replay the program to run it
   void begin_record(Program& prog);
@@ -208,7 +220,19 @@ class Engine {
     size_t bytes = 0;  // per buffer
     int sign = 1;      // stored matrix = sign * canonical matrix
     bool valid = false;
+    int lane = 0;                 // lane that made the current contents
+    hipEvent_t ready = nullptr;   // recorded after that expansion
+    bool ready_set = false;       // made after the fork mark: consumers on the other lane wait
   };
+  // lanes: `stream` and ws_ belong to the lane being issued to; other_* to the
+  // other one (swapped by begin_side / end_side)
+  hipStream_t side_stream_ = nullptr, other_stream_ = nullptr;
+  hipEvent_t fork_ev_ = nullptr, join_ev_ = nullptr;
+  int lane_ = 0;
+  bool side_open_ = false, fork_marked_ = false;
+  void* other_ws_[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  size_t other_ws_bytes_[7] = {0, 0, 0, 0, 0, 0, 0};
+  void swap_lanes();
   std::map<std::string, CacheEntry> ecache_;
   std::vector<std::string> cacheable_;
   bool is_cacheable(const std::string& name) const {
