@@ -293,26 +293,28 @@ void Context::residual_body(Prec tri) {
       }
     } join{e};
     // two lanes from here: the triples intermediates and residual on the main
-    // stream; the doubles intermediates and the singles/doubles residual on
-    // the side lane, concurrently (they read T and the dressed integrals
-    // only, and write R1, R2 and the W2/F2 blocks).  Dressing, intermediates
-    // and the singles/doubles residual are FP64; the triples residual
-    // contractions run in the requested precision and accumulate into the
-    // FP64 residual.
+    // stream; the doubles intermediates and the T2 parts of the singles and
+    // doubles residual on the side lane, concurrently (they read T1, T2 and
+    // the dressed integrals, and write R1, R2 and the W2/F2 blocks).  The T3
+    // feedback into R1 and R2 follows the triples on the main stream: it uses
+    // expansions of T3 made by the triples terms, and the side lane has
+    // finished long before the last triples term (the ring), which therefore
+    // runs alone.  Dressing, intermediates and the singles/doubles residual
+    // are FP64; the triples residual contractions run in the requested
+    // precision and accumulate into the FP64 residual.
     e.fork_mark();
     e.terms(kCCInter3, count(kCCInter3));
     e.prec = tri;
     e.terms(kCCR3, count(kCCR3));
     e.prec = Prec::FP64;
+    std::vector<const char*> late;
     e.begin_side();
     e.terms(kCCInter2, count(kCCInter2));
-    // T3 terms last: they use expansions made by the triples terms
-    std::vector<const char*> late;
     for (const char* t : kCCR1) (std::strstr(t, "T3[") ? late.push_back(t) : e.term(t));
     for (const char* t : kCCR2) (std::strstr(t, "T3[") ? late.push_back(t) : e.term(t));
-    for (const char* t : late) e.term(t);
     e.end_side();
     e.join_side();
+    for (const char* t : late) e.term(t);
   }
   e.prec = tri;
   e.record = false;
