@@ -334,7 +334,7 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   const int64_t small = (int64_t)2 * d->nroots * d->max_sub + 64;
   d->gres = alloc(small);
   d->cm = alloc(small);
-  d->gws_bytes = (size_t)256 * (size_t)d->nroots * (size_t)d->max_sub * sizeof(double);
+  d->gws_bytes = (size_t)kMaxSplit * (size_t)d->nroots * (size_t)d->max_sub * sizeof(double);
   d->gws = alloc((int64_t)(d->gws_bytes / sizeof(double)));
   // guesses: unit vectors on the lowest zeroth-order diagonal entries of the
   // principal block, continued into the other blocks when it is too small

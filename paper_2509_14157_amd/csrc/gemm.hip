@@ -534,6 +534,42 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(const T* __restrict_
   }
 }
 
+// Few outputs with many partials: one wavefront per output, each lane
+// summing a fixed strided subset of the partials, then a fixed shuffle tree.
+template <typename T>
+__global__ void __launch_bounds__(256) splitk_reduce_wave_kernel(const T* __restrict__ P, int split, int64_t M,
+                                                                 int64_t N, T* __restrict__ C, int64_t ldc, T alpha,
+                                                                 T beta) {
+  const int64_t total = M * N;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (i >= total) return;  // uniform per wavefront
+  T acc = 0;
+  for (int z = lane; z < split; z += 64) acc += P[(int64_t)z * total + i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  if (lane == 0) {
+    const int64_t r = i / N, c = i - r * N;
+    T v = alpha * acc;
+    if (beta != (T)0) v += beta * C[r * ldc + c];
+    C[r * ldc + c] = v;
+  }
+}
+
+// C = alpha * sum_z P[z] + beta * C over the split-K partials (deterministic:
+// the order depends on the shape only)
+template <typename T>
+static void launch_splitk_reduce(const T* P, int split, int64_t M, int64_t N, T* C, int64_t ldc, T alpha, T beta,
+                                 hipStream_t s) {
+  const int64_t total = M * N;
+  if (total < 16384 && split >= 64) {
+    splitk_reduce_wave_kernel<T><<<dim3((unsigned)((total + 3) / 4)), 256, 0, s>>>(P, split, M, N, C, ldc, alpha,
+                                                                                   beta);
+  } else {
+    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+    splitk_reduce_kernel<T><<<dim3((unsigned)blocks), 256, 0, s>>>(P, split, M, N, C, ldc, alpha, beta);
+  }
+}
+
 template <typename T, int BM, int BN>
 static void launch_k4(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
@@ -560,11 +596,7 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
     gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
                                                                  be, kchunk, cz, mf);
   if (split > 1) {
-    int64_t total = g.M * g.N;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    splitk_reduce_kernel<T><<<dim3((unsigned)blocks), 256, 0, s>>>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc,
-                                                                   (T)g.alpha, (T)g.beta);
+    launch_splitk_reduce<T>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc, (T)g.alpha, (T)g.beta, s);
   }
 }
 
@@ -594,12 +626,8 @@ static void launch_b3(const GemmArgs& g, hipStream_t s) {
     gemm_bf16x3_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
                                                                  ldc, al, be, kchunk, cz, mf);
   if (split > 1) {
-    int64_t total = g.M * g.N;
-    int64_t blocks = (total + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    splitk_reduce_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>((const float*)g.ws, nz, g.M, g.N,
-                                                                       (float*)g.C, g.ldc, (float)g.alpha,
-                                                                       (float)g.beta);
+    launch_splitk_reduce<float>((const float*)g.ws, nz, g.M, g.N, (float*)g.C, g.ldc, (float)g.alpha,
+                                (float)g.beta, s);
   }
 }
 
@@ -651,10 +679,7 @@ static void launch_db(const GemmArgs& g, hipStream_t s) {
     gemm_db_kernel<T, BM, BN, BK, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc,
                                                                      al, be, kchunk, cz, mf);
   if (split > 1) {
-    const int64_t total = g.M * g.N;
-    const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-    splitk_reduce_kernel<T><<<dim3((unsigned)blocks), 256, 0, s>>>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc,
-                                                                   (T)g.alpha, (T)g.beta);
+    launch_splitk_reduce<T>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc, (T)g.alpha, (T)g.beta, s);
   }
 }
 
@@ -670,13 +695,14 @@ static void dispatch_db(const GemmArgs& g, hipStream_t s) {
 }
 
 int gemm_split_factor(const GemmArgs& g) {
-  // enough workgroups to fill 256 CUs a few times over; chunks of >= 128 k
+  // about 2048 workgroups (eight per CU) for small outputs with a long sum;
+  // chunks of >= 128 k
   const int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
   const int64_t tiles = ((g.M + kTiles[t].bm - 1) / kTiles[t].bm) * ((g.N + kTiles[t].bn - 1) / kTiles[t].bn);
   if (tiles >= 512 || g.K < 512) return 1;
-  int64_t s = (1024 + tiles - 1) / tiles;
+  int64_t s = (2048 + tiles - 1) / tiles;
   s = std::min<int64_t>(s, g.K / 128);
-  s = std::min<int64_t>(s, 256);
+  s = std::min<int64_t>(s, kMaxSplit);
   return s < 2 ? 1 : (int)s;
 }
 

@@ -76,8 +76,9 @@ struct GemmArgs {
   int split = 1;
   void* ws = nullptr;
 };
-// Number of K chunks worth using for this shape (1 = no split) and the
-// workspace bytes it needs.
+// Number of K chunks worth using for this shape (1 = no split, at most
+// kMaxSplit) and the workspace bytes it needs.
+constexpr int kMaxSplit = 1024;
 int gemm_split_factor(const GemmArgs& g);
 size_t gemm_split_bytes(const GemmArgs& g, int split);
 void launch_gemm(const GemmArgs& g, hipStream_t s);
