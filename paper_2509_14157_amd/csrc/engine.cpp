@@ -441,6 +441,7 @@ struct Engine::Plan {
   int64_t ldb = 0;
   OperandDesc bd{};
   bool x_direct = false;
+  bool copy_direct = false;  // single operand expanded straight into the output
   OperandDesc od{};
   MatDim odims{};
   FoldCombos fc{};
@@ -985,6 +986,10 @@ std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
     }
   }
   if (prec == Prec::FP64 && trivial && P->out->full_view() && P->B && same(go, cat(mg, ngp))) P->x_direct = true;
+  // single operand whose gathered rows are the output elements in order: the
+  // expansion accumulates straight into the output (no fold)
+  if (!P->B && trivial && P->fc.ncombo == 1 && P->fc.sign[0] == 1 && P->out->full_view() && same(go, mg))
+    P->copy_direct = true;
   if (!P->a_direct) {
     P->a_kfast = true;
     P->lda = P->K.size;
@@ -1083,6 +1088,15 @@ void Engine::execute(const Plan& p, double scale) {
     const bool tm = timed(p.f_tab_ok ? "fno::copy (expand_tab + fold_tab)" : "fno::copy (expand + fold)") && !rec_;
     hipEvent_t e0 = tm ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
+    if (p.copy_direct && p.a_tab_ok && !p.a_direct) {
+      launch_expand_tab_acc(p.a_tab, p.A->d, p.out->d, p.alpha * scale, stream);
+      if (e0) {
+        hipEvent_t e1 = event();
+        FNO_HIP(hipEventRecord(e1, stream));
+        prof_mark("fno::copy (expand_tab)", p.spec, 0, (double)Msz * 24.0, e0, e1);
+      }
+      return;
+    }
     if (!p.a_direct) {
       void* a = workspace(0, (size_t)Msz * 8);
       if (p.a_tab_ok)

@@ -627,6 +627,33 @@ __global__ void __launch_bounds__(256) expand_tab_flat_kernel(ExpandTab t, const
   }
 }
 
+// out[i] += alpha * (gathered element i), the expansion as an M x 1 matrix
+__global__ void __launch_bounds__(256) expand_tab_acc_kernel(ExpandTab t, const double* __restrict__ src,
+                                                             double* __restrict__ out, double alpha) {
+  const int64_t total = t.rows * t.cols;
+  const int64_t first = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = first; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = t.cols == 1 ? i : i / t.cols;
+    const int64_t c = i - r * t.cols;
+    int64_t o = t.row_off[r] + t.col_off[c];
+    int s = t.row_sign[r] * t.col_sign[c];
+    for (int m = 0; m < t.nmixed; ++m) {
+      const int64_t k = (int64_t)t.row_sub[m][r] * t.ncsub[m] + t.col_sub[m][c];
+      o += t.tab_off[m][k];
+      s *= t.tab_sign[m][k];
+    }
+    if (s) out[i] += alpha * (s * src[o]);
+  }
+}
+
+void launch_expand_tab_acc(const ExpandTab& t, const double* src, double* out, double alpha, hipStream_t s) {
+  const int64_t total = t.rows * t.cols;
+  if (total == 0) return;
+  const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
+  expand_tab_acc_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(t, src, out, alpha);
+  FNO_HIP(hipGetLastError());
+}
+
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
   if (t.rows == 0 || t.cols == 0) return;
   if (t.cols < 128) {

@@ -30,6 +30,8 @@ void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, con
                        const MatDim& xrows, const MatDim& xcols, unsigned xr_mask, unsigned xc_mask,
                        int64_t* rowc, int64_t* colc, hipStream_t s);
 
+// out[i] += alpha * element i of the expansion (an M x 1 gather), FP64
+void launch_expand_tab_acc(const ExpandTab& t, const double* src, double* out, double alpha, hipStream_t s);
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s);
 void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, double alpha, int64_t total,
                      hipStream_t s);
