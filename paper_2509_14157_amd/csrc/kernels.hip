@@ -3,6 +3,8 @@
 // stores coalesce, and the packed sources they gather from are small enough
 // to stay in L2 / the MALL.
 #include <hip/hip_bf16.h>
+#include <cstdio>
+#include <cstdlib>
 
 #include "kernels.hpp"
 
@@ -753,12 +755,20 @@ static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha
     fold_tab_fixed_kernel<XT, NG, NC><<<grid, 256, 0, s>>>(t, X, out, alpha, total);           \
     return;                                                                                    \
   }
+  // every (groups, combos) pair the ground-state and EOM tables produce:
+  // up to three output groups (batch index, hole group, particle group) and
+  // products of the per-group shuffle counts 1, 2, 3, 4, 6
   FNO_FOLD_CASE(1, 1) FNO_FOLD_CASE(1, 2) FNO_FOLD_CASE(1, 3) FNO_FOLD_CASE(1, 4) FNO_FOLD_CASE(1, 6)
   FNO_FOLD_CASE(2, 1) FNO_FOLD_CASE(2, 2) FNO_FOLD_CASE(2, 3) FNO_FOLD_CASE(2, 4) FNO_FOLD_CASE(2, 6)
-  FNO_FOLD_CASE(2, 9) FNO_FOLD_CASE(2, 12) FNO_FOLD_CASE(2, 18)
+  FNO_FOLD_CASE(2, 8) FNO_FOLD_CASE(2, 9) FNO_FOLD_CASE(2, 12) FNO_FOLD_CASE(2, 16) FNO_FOLD_CASE(2, 18)
+  FNO_FOLD_CASE(2, 24) FNO_FOLD_CASE(2, 36)
   FNO_FOLD_CASE(3, 1) FNO_FOLD_CASE(3, 2) FNO_FOLD_CASE(3, 3) FNO_FOLD_CASE(3, 4) FNO_FOLD_CASE(3, 6)
-  FNO_FOLD_CASE(3, 9)
+  FNO_FOLD_CASE(3, 8) FNO_FOLD_CASE(3, 9) FNO_FOLD_CASE(3, 12) FNO_FOLD_CASE(3, 16) FNO_FOLD_CASE(3, 18)
+  FNO_FOLD_CASE(3, 24) FNO_FOLD_CASE(3, 36)
+  FNO_FOLD_CASE(4, 1) FNO_FOLD_CASE(4, 2) FNO_FOLD_CASE(4, 3) FNO_FOLD_CASE(4, 4) FNO_FOLD_CASE(4, 6)
 #undef FNO_FOLD_CASE
+  static bool trace = std::getenv("FNO_TRACE") != nullptr;
+  if (trace) std::fprintf(stderr, "[fno] generic fold: %d groups, %d combos\n", t.ngroups, t.ncombo);
   fold_tab_kernel<XT><<<grid, 256, 0, s>>>(t, X, out, alpha, total);
 }
 
