@@ -715,9 +715,14 @@ __global__ void __launch_bounds__(256) fold_tab_kernel(FoldTab t, const XT* __re
 // chain of dependent ones).  Summation order as in fold_tab_kernel.
 template <typename XT, int NG, int NC>
 __global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT* __restrict__ X,
-                                                             double* __restrict__ out, double alpha, int64_t total) {
-  const int64_t first = xcd_chunk(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  for (int64_t e = first; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+                                                             double* __restrict__ out, double alpha, int64_t total,
+                                                             int64_t chunk) {
+  // each block walks `chunk` consecutive outputs: the matrix lines read by one
+  // 256-output step (for the shuffles whose fastest output index runs along
+  // the rows of X) are read again by the next steps, from this CU's cache
+  const int64_t begin = xcd_chunk(blockIdx.x, gridDim.x) * chunk;
+  const int64_t end = begin + chunk < total ? begin + chunk : total;
+  for (int64_t e = begin + threadIdx.x; e < end; e += blockDim.x) {
     int64_t u[NG];
     int64_t idx = e;
 #pragma unroll
@@ -750,9 +755,12 @@ __global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT
 template <typename XT>
 static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha, int64_t total, hipStream_t s) {
   const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
+  // chunks of 8 steps for the largest outputs (the 4p2h / 4h2p sigma blocks)
+  const int64_t chunk = total >= ((int64_t)16 << 20) ? 2048 : 256;
+  const dim3 cgrid((unsigned)((total + chunk - 1) / chunk));
 #define FNO_FOLD_CASE(NG, NC)                                                                  \
   if (t.ngroups == NG && t.ncombo == NC) {                                                     \
-    fold_tab_fixed_kernel<XT, NG, NC><<<grid, 256, 0, s>>>(t, X, out, alpha, total);           \
+    fold_tab_fixed_kernel<XT, NG, NC><<<cgrid, 256, 0, s>>>(t, X, out, alpha, total, chunk);   \
     return;                                                                                    \
   }
   // every (groups, combos) pair the ground-state and EOM tables produce:
