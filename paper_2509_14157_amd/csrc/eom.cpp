@@ -193,12 +193,7 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
   for (int b = 0; b < t.nblocks; ++b) {
     const int64_t sz = sp.blocks[b].size;
     double* in = e.get(t.in[b])->d;
-    for (int j = 0; j < sp.nb; ++j) {
-      if (j < count)
-        launch_axpby(in + j * sz, r + j * ldr + sp.blocks[b].offset, (double)t.sign[b], 0.0, sz, e.stream);
-      else
-        launch_fill(in + j * sz, 0.0, sz, e.stream);
-    }
+    launch_scale_rows(in, sz, r + sp.blocks[b].offset, ldr, (double)t.sign[b], sz, count, sp.nb, e.stream);
   }
   auto sweep = [&]() {
     for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
@@ -275,8 +270,7 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
   for (int b = 0; b < t.nblocks; ++b) {
     const int64_t sz = sp.blocks[b].size;
     const double* out = e.get(t.out[b])->d;
-    for (int j = 0; j < count; ++j)
-      launch_axpby(sigma + j * lds + sp.blocks[b].offset, out + j * sz, (double)t.sign[b], 0.0, sz, e.stream);
+    launch_scale_rows(sigma + sp.blocks[b].offset, lds, out, sz, (double)t.sign[b], sz, count, count, e.stream);
   }
   c.last_triples_flops += sp.sweep_tri;  // summed over the sweeps of a solve (reset by the caller)
   c.last_all_flops += sp.sweep_all;

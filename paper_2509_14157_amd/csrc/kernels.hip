@@ -185,6 +185,31 @@ void launch_axpby(double* y, const double* x, double a, double b, int64_t n, hip
   FNO_HIP(hipGetLastError());
 }
 
+// y_j = a * x_j for j < count and y_j = 0 for count <= j < rows, each of n
+// elements (y_j = y + j * ldy, x_j = x + j * ldx): a block of vectors in one launch
+__global__ void __launch_bounds__(256) scale_rows_kernel(double* __restrict__ y, int64_t ldy,
+                                                         const double* __restrict__ x, int64_t ldx, double a,
+                                                         int64_t n, int count) {
+  const int j = blockIdx.y;
+  double* yj = y + (int64_t)j * ldy;
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (int64_t)gridDim.x * blockDim.x;
+  if (j < count) {  // uniform per block: rows past count are never read
+    const double* xj = x + (int64_t)j * ldx;
+    for (int64_t i = i0; i < n; i += step) yj[i] = a * xj[i];
+  } else {
+    for (int64_t i = i0; i < n; i += step) yj[i] = 0.0;
+  }
+}
+
+void launch_scale_rows(double* y, int64_t ldy, const double* x, int64_t ldx, double a, int64_t n, int count, int rows,
+                       hipStream_t s) {
+  if (n == 0 || rows == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  scale_rows_kernel<<<dim3((unsigned)blocks, (unsigned)rows), dim3(256), 0, s>>>(y, ldy, x, ldx, a, n, count);
+  FNO_HIP(hipGetLastError());
+}
+
 // Zeroth-order denominators of a packed block: D = sum_holes e_h - sum_particles e_p
 // scaled by hole_sign / particle_sign (both +1 for amplitudes; the EOM diagonal
 // uses D = sum_p e_p - sum_h e_h).  out = D (shift applied: out = shift - D when
