@@ -9,9 +9,10 @@ doubles and triples residuals (pp-ladder, hh-ladder, ring, drivers,
 one-body and T2*T3 terms, T3 -> T2/T1 feedback), the Jacobi update, DIIS and
 the energy.  value = algorithmic triples flops per iteration (packed GEMM
 forms, 2*M*N*K) / measured time per iteration.  The timed iterations replay
-the residual sweep from hipGraphs; the dominant GEMM is timed with HIP events
-on the library's stream in that same region (roofline), the per-kernel
-breakdown comes from the host-launched warm-up iterations.
+the residual sweep from a hipGraph; the dominant GEMM is timed in that same
+region by event-record nodes inside the graph, on the stream it runs on
+(roofline); the per-kernel breakdown comes from the host-launched warm-up
+iterations.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16x3]
 """
@@ -398,7 +399,7 @@ def main():
     dom_name = max(gemms, key=lambda k: k["total_ms"])["name"]
 
     # timed region: graph replay of the residual sweep; only the dominant GEMM
-    # is bracketed by HIP events (it runs between graph segments)
+    # is bracketed by events (event-record nodes inside the graph)
     ctx.set_graphs(not args.no_graphs)
     ctx.profile(True, only=dom_name)
     t0 = time.perf_counter()

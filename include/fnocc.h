@@ -209,9 +209,10 @@ int fno_profile(fno_ctx *ctx, int on);
 int fno_profile_report(fno_ctx *ctx, char *buf, size_t len);
 /*
  * Restrict timing to the kernels whose name contains `substr` (NULL or "" =
- * all kernels).  With a filter set, the residual sweep can still be replayed
- * from hipGraphs: the selected kernels run between graph segments, each
- * bracketed by its own events.  FNO_EINVAL on a null context.
+ * all kernels).  With a filter set, the residual and sigma sweeps are still
+ * replayed from hipGraphs: the selected GEMMs are bracketed by event-record
+ * nodes inside the graph, read after every replay.  FNO_EINVAL on a null
+ * context.
  */
 int fno_profile_filter(fno_ctx *ctx, const char *substr);
 
@@ -219,8 +220,10 @@ int fno_profile_filter(fno_ctx *ctx, const char *substr);
  * Launch mode of the CCSDT residual sweep (the loop of fno_ccsdt, and the
  * ground-state intermediates of fno_eom / fno_eom_sigma / fno_cc_residual).
  * on = 1 (default): once a sweep has run without allocating device memory, the
- * next one is recorded into hipGraphs on the context's stream and later sweeps
- * replay it; any new allocation in the context discards the recording.
+ * next one is recorded into a hipGraph (by stream capture on the context's
+ * stream and, for the concurrent part of the residual, a side stream joined
+ * back into it) and later sweeps replay it; any new allocation in the context
+ * discards the recording.
  * on = 0: every launch is issued from the host.  Results are identical in both
  * modes (same kernels, same order).
  */
