@@ -3,6 +3,7 @@
 
 #include <array>
 #include <cstdio>
+#include <cstdlib>
 
 #include <algorithm>
 #include <cctype>
@@ -1360,6 +1361,12 @@ int Engine::tuned_tile(const GemmArgs& g0) {
   for (int t = 0; t < ntile; ++t)
     if (t_ms[t] < t_ms[best]) best = t;
   if (best != def && t_ms[best] > 0.97f * t_ms[def]) best = def;
+  static const bool trace = std::getenv("FNO_TRACE") != nullptr;
+  if (trace) {
+    std::fprintf(stderr, "[fno] tile times %s (ms):", key);
+    for (int t = 0; t < ntile; ++t) std::fprintf(stderr, " %d:%.4f", t, t_ms[t]);
+    std::fprintf(stderr, " -> %d\n", best);
+  }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   GemmArgs g = g0;

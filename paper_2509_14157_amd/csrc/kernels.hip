@@ -553,75 +553,82 @@ void launch_fold_table(const IndexTables& tb, const DimGroup& og, int nshuf, con
 
 // ---------------------------------------------------------------- hot paths
 // Each thread owns one column c (its table entries stay in registers) and
-// walks a strided set of rows; the row entries are uniform per iteration.
-template <typename Out>
-__global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const double* __restrict__ src,
-                                                         Out* __restrict__ dst) {
-  const int64_t L = xcd_chunk((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
-  const int64_t bx = L % gridDim.x, by = L / gridDim.x;
-  const int64_t c = bx * blockDim.x + threadIdx.x;
-  if (c >= t.cols) return;
-  const int64_t co = t.col_off[c];
-  const int cs = t.col_sign[c];
-  int32_t csub0 = 0, csub1 = 0;
-  if (t.nmixed > 0) csub0 = t.col_sub[0][c];
-  if (t.nmixed > 1) csub1 = t.col_sub[1][c];
-  // a contiguous range of rows per block: neighbouring rows gather from
-  // neighbouring source elements, so the cache lines are reused
-  const int64_t per = (t.rows + gridDim.y - 1) / gridDim.y;
-  const int64_t r_end = (by + 1) * per < t.rows ? (by + 1) * per : t.rows;
-  for (int64_t r = by * per; r < r_end; ++r) {
-    int64_t o = t.row_off[r] + co;
-    int s = t.row_sign[r] * cs;
-    if (t.nmixed > 0) {
-      const int64_t k = (int64_t)t.row_sub[0][r] * t.ncsub[0] + csub0;
-      o += t.tab_off[0][k];
-      s *= t.tab_sign[0][k];
-    }
-    if (t.nmixed > 1) {
-      const int64_t k = (int64_t)t.row_sub[1][r] * t.ncsub[1] + csub1;
-      o += t.tab_off[1][k];
-      s *= t.tab_sign[1][k];
-    }
-    const double v = s ? s * src[o] : 0.0;
-    dst[r * t.cols + c] = (Out)v;
+// walks a contiguous range of rows, kRowStep rows per step.  The row entries
+// are uniform per step (scalar loads); within a step every table gather of
+// the rows is issued before the first is used, then every source gather, so a
+// wavefront keeps kRowStep independent chains in flight instead of one.
+constexpr int kRowStep = 4;
+__device__ const double kExpandZero = 0.0;
+
+template <int MODE>  // 0 = FP64, 1 = FP32, 2 = split-BF16 (hi, lo)
+__device__ __forceinline__ void expand_store(void* dst, void* dst_lo, int64_t i, double v) {
+  if constexpr (MODE == 0) {
+    ((double*)dst)[i] = v;
+  } else if constexpr (MODE == 1) {
+    ((float*)dst)[i] = (float)v;
+  } else {
+    const float x = (float)v;
+    const __hip_bfloat16 h = __float2bfloat16(x);
+    ((__hip_bfloat16*)dst)[i] = h;
+    ((__hip_bfloat16*)dst_lo)[i] = __float2bfloat16(x - __bfloat162float(h));
   }
 }
 
-__global__ void __launch_bounds__(256) expand_tab_bf16_kernel(ExpandTab t, const double* __restrict__ src,
-                                                              __hip_bfloat16* __restrict__ hi,
-                                                              __hip_bfloat16* __restrict__ lo) {
+template <int MODE, int NM, int R>
+__device__ __forceinline__ void expand_rows(const ExpandTab& t, const double* __restrict__ src, void* dst,
+                                            void* dst_lo, int64_t r, int64_t c, int64_t co, int cs,
+                                            const int32_t (&csub)[kMaxMixed]) {
+  int64_t o[R];
+  int sg[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    o[q] = t.row_off[r + q] + co;
+    sg[q] = t.row_sign[r + q] * cs;
+  }
+#pragma unroll
+  for (int m = 0; m < NM; ++m) {
+    int64_t to[R];
+    int ts[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int64_t k = (int64_t)t.row_sub[m][r + q] * t.ncsub[m] + csub[m];
+      to[q] = t.tab_off[m][k];
+      ts[q] = t.tab_sign[m][k];
+    }
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      o[q] += to[q];
+      sg[q] *= ts[q];
+    }
+  }
+  // lanes with a repeated index read a zero from a fixed address: the loads
+  // stay unconditional (no branch, so no wait) and never touch an empty source
+  double v[R];
+#pragma unroll
+  for (int q = 0; q < R; ++q) v[q] = *(sg[q] ? src + o[q] : &kExpandZero);
+#pragma unroll
+  for (int q = 0; q < R; ++q) expand_store<MODE>(dst, dst_lo, (r + q) * t.cols + c, sg[q] * v[q]);
+}
+
+template <int MODE, int NM>
+__global__ void __launch_bounds__(256) expand_tab_kernel(ExpandTab t, const double* __restrict__ src, void* dst,
+                                                         void* dst_lo) {
   const int64_t L = xcd_chunk((int64_t)blockIdx.y * gridDim.x + blockIdx.x, (int64_t)gridDim.x * gridDim.y);
   const int64_t bx = L % gridDim.x, by = L / gridDim.x;
   const int64_t c = bx * blockDim.x + threadIdx.x;
   if (c >= t.cols) return;
   const int64_t co = t.col_off[c];
   const int cs = t.col_sign[c];
-  int32_t csub0 = 0, csub1 = 0;
-  if (t.nmixed > 0) csub0 = t.col_sub[0][c];
-  if (t.nmixed > 1) csub1 = t.col_sub[1][c];
+  int32_t csub[kMaxMixed] = {0, 0};
+#pragma unroll
+  for (int m = 0; m < NM; ++m) csub[m] = t.col_sub[m][c];
   // a contiguous range of rows per block: neighbouring rows gather from
   // neighbouring source elements, so the cache lines are reused
   const int64_t per = (t.rows + gridDim.y - 1) / gridDim.y;
   const int64_t r_end = (by + 1) * per < t.rows ? (by + 1) * per : t.rows;
-  for (int64_t r = by * per; r < r_end; ++r) {
-    int64_t o = t.row_off[r] + co;
-    int s = t.row_sign[r] * cs;
-    if (t.nmixed > 0) {
-      const int64_t k = (int64_t)t.row_sub[0][r] * t.ncsub[0] + csub0;
-      o += t.tab_off[0][k];
-      s *= t.tab_sign[0][k];
-    }
-    if (t.nmixed > 1) {
-      const int64_t k = (int64_t)t.row_sub[1][r] * t.ncsub[1] + csub1;
-      o += t.tab_off[1][k];
-      s *= t.tab_sign[1][k];
-    }
-    const float x = s ? (float)(s * src[o]) : 0.0f;
-    const __hip_bfloat16 h = __float2bfloat16(x);
-    hi[r * t.cols + c] = h;
-    lo[r * t.cols + c] = __float2bfloat16(x - __bfloat162float(h));
-  }
+  int64_t r = by * per;
+  for (; r + kRowStep <= r_end; r += kRowStep) expand_rows<MODE, NM, kRowStep>(t, src, dst, dst_lo, r, c, co, cs, csub);
+  for (; r < r_end; ++r) expand_rows<MODE, NM, 1>(t, src, dst, dst_lo, r, c, co, cs, csub);
 }
 
 // Narrow matrices (few columns): one thread per element over the flat index.
@@ -681,6 +688,28 @@ void launch_expand_tab_acc(const ExpandTab& t, const double* src, double* out, d
   FNO_HIP(hipGetLastError());
 }
 
+template <int MODE>
+static void launch_expand_rows_m(int nm, dim3 grid, const ExpandTab& t, const double* src, void* dst, void* dst_lo,
+                                 hipStream_t s) {
+  if (nm == 0)
+    expand_tab_kernel<MODE, 0><<<grid, 256, 0, s>>>(t, src, dst, dst_lo);
+  else if (nm == 1)
+    expand_tab_kernel<MODE, 1><<<grid, 256, 0, s>>>(t, src, dst, dst_lo);
+  else
+    expand_tab_kernel<MODE, 2><<<grid, 256, 0, s>>>(t, src, dst, dst_lo);
+}
+
+static void launch_expand_rows(int mode, int nm, dim3 grid, const ExpandTab& t, const double* src, void* dst,
+                               void* dst_lo, hipStream_t s) {
+  FNO_REQUIRE(nm >= 0 && nm <= kMaxMixed, kEINVAL, "expansion table with too many straddling groups");
+  if (mode == 0)
+    launch_expand_rows_m<0>(nm, grid, t, src, dst, dst_lo, s);
+  else if (mode == 1)
+    launch_expand_rows_m<1>(nm, grid, t, src, dst, dst_lo, s);
+  else
+    launch_expand_rows_m<2>(nm, grid, t, src, dst, dst_lo, s);
+}
+
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
   if (t.rows == 0 || t.cols == 0) return;
   if (t.cols < 128) {
@@ -700,12 +729,8 @@ void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* d
   int64_t gy = std::max<int64_t>(1, std::min<int64_t>(t.rows, (8192 + gx - 1) / gx));
   gy = std::min<int64_t>(gy, 65535);
   dim3 grid(gx, (unsigned)gy);
-  if (prec == Prec::FP64)
-    expand_tab_kernel<double><<<grid, 256, 0, s>>>(t, src, (double*)dst);
-  else if (prec == Prec::FP32)
-    expand_tab_kernel<float><<<grid, 256, 0, s>>>(t, src, (float*)dst);
-  else
-    expand_tab_bf16_kernel<<<grid, 256, 0, s>>>(t, src, (__hip_bfloat16*)dst, (__hip_bfloat16*)dst_lo);
+  const int mode = prec == Prec::FP64 ? 0 : prec == Prec::FP32 ? 1 : 2;
+  launch_expand_rows(mode, t.nmixed, grid, t, src, dst, dst_lo, s);
   FNO_HIP(hipGetLastError());
 }
 
