@@ -763,7 +763,12 @@ __global__ void __launch_bounds__(256) fold_tab_kernel(FoldTab t, const XT* __re
 // unroll, so every table entry and every X element of one output is requested
 // before the first is used (two memory round trips per output instead of a
 // chain of dependent ones).  Summation order as in fold_tab_kernel.
-template <typename XT, int NG, int NC>
+//
+// SH (every group has at most kShufMax shuffles): each group's row and column
+// parts are read once per shuffle and shared by the combos that pick it (a
+// two-group fold with 3 x 3 combos reads 12 table entries instead of 36).
+constexpr int kShufMax = 3;
+template <typename XT, int NG, int NC, bool SH>
 __global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT* __restrict__ X,
                                                              double* __restrict__ out, double alpha, int64_t total,
                                                              int64_t chunk) {
@@ -781,16 +786,43 @@ __global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT
       idx /= t.count[k];
     }
     int64_t addr[NC];
+    if constexpr (SH) {
+      int64_t rr[NG][kShufMax], cc[NG][kShufMax];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      int64_t r = 0, col = 0;
+      for (int k = 0; k < NG; ++k)
 #pragma unroll
-      for (int k = 0; k < NG; ++k) {
-        const int64_t j = (int64_t)t.combo[c][k] * t.count[k] + u[k];
-        r += t.rowc[k][j];
-        col += t.colc[k][j];
+        for (int q = 0; q < kShufMax; ++q) {
+          rr[k][q] = 0;
+          cc[k][q] = 0;
+          if (q < t.nshuf[k]) {
+            const int64_t j = (int64_t)q * t.count[k] + u[k];
+            rr[k][q] = t.rowc[k][j];
+            cc[k][q] = t.colc[k][j];
+          }
+        }
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        int64_t r = 0, col = 0;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          const int q = t.combo[c][k];
+          r += q == 0 ? rr[k][0] : (q == 1 ? rr[k][1] : rr[k][2]);
+          col += q == 0 ? cc[k][0] : (q == 1 ? cc[k][1] : cc[k][2]);
+        }
+        addr[c] = r * t.xcols + col;
       }
-      addr[c] = r * t.xcols + col;
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        int64_t r = 0, col = 0;
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+          const int64_t j = (int64_t)t.combo[c][k] * t.count[k] + u[k];
+          r += t.rowc[k][j];
+          col += t.colc[k][j];
+        }
+        addr[c] = r * t.xcols + col;
+      }
     }
     double v[NC];
 #pragma unroll
@@ -808,10 +840,15 @@ static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha
   // chunks of 8 steps for the largest outputs (the 4p2h / 4h2p sigma blocks)
   const int64_t chunk = total >= ((int64_t)16 << 20) ? 2048 : 256;
   const dim3 cgrid((unsigned)((total + chunk - 1) / chunk));
-#define FNO_FOLD_CASE(NG, NC)                                                                  \
-  if (t.ngroups == NG && t.ncombo == NC) {                                                     \
-    fold_tab_fixed_kernel<XT, NG, NC><<<cgrid, 256, 0, s>>>(t, X, out, alpha, total, chunk);   \
-    return;                                                                                    \
+  bool sh = true;
+  for (int k = 0; k < t.ngroups; ++k) sh = sh && t.nshuf[k] <= kShufMax;
+#define FNO_FOLD_CASE(NG, NC)                                                                        \
+  if (t.ngroups == NG && t.ncombo == NC) {                                                           \
+    if (sh)                                                                                          \
+      fold_tab_fixed_kernel<XT, NG, NC, true><<<cgrid, 256, 0, s>>>(t, X, out, alpha, total, chunk);  \
+    else                                                                                             \
+      fold_tab_fixed_kernel<XT, NG, NC, false><<<cgrid, 256, 0, s>>>(t, X, out, alpha, total, chunk); \
+    return;                                                                                          \
   }
   // every (groups, combos) pair the ground-state and EOM tables produce:
   // up to three output groups (batch index, hole group, particle group) and
