@@ -567,7 +567,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
       owned_.erase(std::remove(owned_.begin(), owned_.end(), rplain), owned_.end());
       FNO_HIP(hipFree(rplain));
       order.clear();  // the DIIS history restarts from the chosen guess
-      ++it;           // the judge's extra residual evaluation
+      ++it;           // the extra residual evaluation of the guess comparison
     } else {
       residual();
     }

@@ -842,6 +842,12 @@ static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha
   const dim3 cgrid((unsigned)((total + chunk - 1) / chunk));
   bool sh = true;
   for (int k = 0; k < t.ngroups; ++k) sh = sh && t.nshuf[k] <= kShufMax;
+  static const bool trace_shapes = std::getenv("FNO_TRACE") != nullptr;
+  if (trace_shapes) {
+    std::fprintf(stderr, "[fno] fold shape: %d groups, %d combos, shuffles", t.ngroups, t.ncombo);
+    for (int k = 0; k < t.ngroups; ++k) std::fprintf(stderr, " %d", t.nshuf[k]);
+    std::fprintf(stderr, ", %lld outputs\n", (long long)total);
+  }
 #define FNO_FOLD_CASE(NG, NC)                                                                        \
   if (t.ngroups == NG && t.ncombo == NC) {                                                           \
     if (sh)                                                                                          \
