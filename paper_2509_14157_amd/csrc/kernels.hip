@@ -834,12 +834,82 @@ __global__ void __launch_bounds__(256) fold_tab_fixed_kernel(FoldTab t, const XT
   }
 }
 
+// Three output groups whose first has a single shuffle (the root or instance
+// index), the shuffle counts NS1 and NS2 of the other two fixed at compile
+// time.  The host builds the combos as a mixed-radix product, so combo
+// c = p1 + NS1 * p2 takes shuffle p1 of group 1 and p2 of group 2: every table
+// entry of an output is read once and addressed at compile time, and the sum
+// runs over c in the same order as the other fold kernels.
+template <typename XT, int NS1, int NS2>
+__global__ void __launch_bounds__(256) fold_tab_prod3_kernel(FoldTab t, const XT* __restrict__ X,
+                                                             double* __restrict__ out, double alpha, int64_t total,
+                                                             int64_t chunk) {
+  constexpr int NC = NS1 * NS2;
+  const int64_t begin = xcd_chunk(blockIdx.x, gridDim.x) * chunk;
+  const int64_t end = begin + chunk < total ? begin + chunk : total;
+  for (int64_t e = begin + threadIdx.x; e < end; e += blockDim.x) {
+    int64_t idx = e;
+    const int64_t u2 = idx % t.count[2];
+    idx /= t.count[2];
+    const int64_t u1 = idx % t.count[1];
+    idx /= t.count[1];
+    const int64_t u0 = idx % t.count[0];
+    const int64_t r0 = t.rowc[0][u0], c0 = t.colc[0][u0];
+    int64_t r1[NS1], c1[NS1], r2[NS2], c2[NS2];
+#pragma unroll
+    for (int q = 0; q < NS1; ++q) {
+      r1[q] = t.rowc[1][(int64_t)q * t.count[1] + u1];
+      c1[q] = t.colc[1][(int64_t)q * t.count[1] + u1];
+    }
+#pragma unroll
+    for (int q = 0; q < NS2; ++q) {
+      r2[q] = t.rowc[2][(int64_t)q * t.count[2] + u2];
+      c2[q] = t.colc[2][(int64_t)q * t.count[2] + u2];
+    }
+    double v[NC];
+#pragma unroll
+    for (int p2 = 0; p2 < NS2; ++p2)
+#pragma unroll
+      for (int p1 = 0; p1 < NS1; ++p1)
+        v[p1 + NS1 * p2] = (double)X[(r0 + r1[p1] + r2[p2]) * t.xcols + c0 + c1[p1] + c2[p2]];
+    double acc = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc += t.csign[c] * v[c];
+    out[e] += alpha * acc;
+  }
+}
+
+// True when the combo table is the mixed-radix product the product kernels assume.
+static bool fold_is_product(const FoldTab& t) {
+  if (t.nshuf[1] * t.nshuf[2] != t.ncombo || t.ncombo > kMaxCombos) return false;
+  int c = 0;
+  for (int p2 = 0; p2 < t.nshuf[2]; ++p2)
+    for (int p1 = 0; p1 < t.nshuf[1]; ++p1, ++c)
+      if (t.combo[c][0] != 0 || t.combo[c][1] != p1 || t.combo[c][2] != p2) return false;
+  return c == t.ncombo;
+}
+
 template <typename XT>
 static void fold_launch(const FoldTab& t, const XT* X, double* out, double alpha, int64_t total, hipStream_t s) {
   const dim3 grid((unsigned)std::min<int64_t>((total + 255) / 256, 65536));
   // chunks of 8 steps for the largest outputs (the 4p2h / 4h2p sigma blocks)
   const int64_t chunk = total >= ((int64_t)16 << 20) ? 2048 : 256;
   const dim3 cgrid((unsigned)((total + chunk - 1) / chunk));
+  if (t.ngroups == 3 && t.nshuf[0] == 1 && fold_is_product(t)) {
+#define FNO_FOLD_PROD(A, B)                                                                    \
+  if (t.nshuf[1] == A && t.nshuf[2] == B) {                                                    \
+    fold_tab_prod3_kernel<XT, A, B><<<cgrid, 256, 0, s>>>(t, X, out, alpha, total, chunk);     \
+    return;                                                                                    \
+  }
+    // every pair the EOM tables produce: hole and particle groups of up to four
+    // letters, whose antisymmetrizers have 1, 2, 3, 4, 6 or 12 shuffles
+    FNO_FOLD_PROD(1, 1) FNO_FOLD_PROD(1, 2) FNO_FOLD_PROD(2, 1) FNO_FOLD_PROD(2, 2)
+    FNO_FOLD_PROD(1, 3) FNO_FOLD_PROD(3, 1) FNO_FOLD_PROD(2, 3) FNO_FOLD_PROD(3, 2) FNO_FOLD_PROD(3, 3)
+    FNO_FOLD_PROD(1, 4) FNO_FOLD_PROD(4, 1) FNO_FOLD_PROD(2, 4) FNO_FOLD_PROD(4, 2)
+    FNO_FOLD_PROD(1, 6) FNO_FOLD_PROD(6, 1) FNO_FOLD_PROD(2, 6) FNO_FOLD_PROD(6, 2)
+    FNO_FOLD_PROD(1, 12) FNO_FOLD_PROD(12, 1) FNO_FOLD_PROD(2, 12) FNO_FOLD_PROD(12, 2)
+#undef FNO_FOLD_PROD
+  }
   bool sh = true;
   for (int k = 0; k < t.ngroups; ++k) sh = sh && t.nshuf[k] <= kShufMax;
   static const bool trace_shapes = std::getenv("FNO_TRACE") != nullptr;
