@@ -206,6 +206,24 @@ void Context::dress() {
   e.term("Fd[pq] += 1 * Gd_nono[piqj] * Iocc[ij]");
 }
 
+double* Context::pinned() {
+  if (!host_pin_) FNO_HIP(hipHostMalloc((void**)&host_pin_, kPinned * sizeof(double), hipHostMallocDefault));
+  return host_pin_;
+}
+
+void Context::energy_async() {
+  Engine& e = *eng;
+  Prec keep = e.prec;
+  e.prec = Prec::FP64;  // energies are always FP64
+  e.zero(e.get("E"));
+  e.zero(e.get("Ie"));
+  e.terms(kCCEnergy, count(kCCEnergy));
+  e.prec = keep;
+  FNO_HIP(hipMemcpyAsync(pinned(), e.get("E")->d, sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  if (!e_ready_) FNO_HIP(hipEventCreateWithFlags(&e_ready_, hipEventDisableTiming));
+  FNO_HIP(hipEventRecord(e_ready_, e.stream));
+}
+
 double Context::energy() {
   Engine& e = *eng;
   Prec keep = e.prec;
@@ -224,7 +242,7 @@ double Context::energy() {
 // an eager sweep has run without allocating anything, the next one is
 // recorded into hipGraph segments and later sweeps replay them (host launch
 // overhead removed).  Any allocation in the engine invalidates the recording.
-void Context::residual() {
+void Context::residual(bool defer_timers) {
   Engine& e = *eng;
   const Prec tri = e.prec;  // precision of the triples-residual contractions
   auto matches = [&]() {
@@ -232,10 +250,11 @@ void Context::residual() {
            cc_prog_.profiled == e.profile && cc_prog_.filter == e.profile_filter;
   };
   if (use_graphs && matches()) {
-    e.replay(cc_prog_);
+    e.replay(cc_prog_, defer_timers);
     e.prec = tri;
     return;
   }
+  e.flush_timers(cc_prog_);
   cc_prog_.clear();
   if (use_graphs && cc_stable_ && cc_stable_epoch_ == e.epoch && cc_stable_prec_ == (int)tri &&
       cc_stable_profiled_ == e.profile && cc_stable_filter_ == e.profile_filter) {
@@ -253,7 +272,7 @@ void Context::residual() {
       cc_stable_ = false;
     }
     if (recorded && cc_prog_.valid()) {
-      e.replay(cc_prog_);
+      e.replay(cc_prog_, defer_timers);
       return;
     }
   }
@@ -540,8 +559,15 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
       }
     xg = dkeep = nullptr;
   };
+  // the next iteration's residual is enqueued before the host waits for this
+  // iteration's energy, so the graph submission overlaps the tail of the work
+  // instead of leaving the device idle (when the loop stops there, that
+  // residual is left unused: amplitudes and reported norms are unaffected)
+  bool ahead = false;
   for (it = 1; it <= opt.max_iter; ++it) {
-    if (opt.guess == 1 && it == 3 && b3.size > 0 && it + 1 <= opt.max_iter) {
+    if (ahead) {
+      ahead = false;
+    } else if (opt.guess == 1 && it == 3 && b3.size > 0 && it + 1 <= opt.max_iter) {
       // residual at the plain guess, kept aside
       residual();
       double* rplain = alloc(nt_);
@@ -587,6 +613,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     double hv[2 + 16];
     FNO_HIP(hipMemcpyAsync(hv, dres, (2 + (m > 0 ? mm : 0)) * sizeof(double), hipMemcpyDeviceToHost, e.stream));
     FNO_HIP(hipStreamSynchronize(e.stream));
+    e.flush_timers(cc_prog_);  // a sweep launched ahead has finished: read its timers
     rnorm = std::sqrt(hv[0]);
     if (!std::isfinite(rnorm)) {
       e.prec = Prec::FP64;
@@ -610,18 +637,28 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
       rhs[k] = -1.0;
       if (solve(k + 1, A, rhs)) {
         // combine in slot order: coefficients c[slot]
-        std::vector<double> c(std::max(m, 1), 0.0);
+        // coefficients in slot order, staged in pinned memory: the copy runs
+        // after the host has moved on, and the buffer is next written only
+        // after the following iteration's synchronization
+        double* c = pinned() + 1;
+        const int nc = std::max(m, 1);
+        for (int a = 0; a < nc; ++a) c[a] = 0.0;
         for (int a = 0; a < k; ++a) c[order[a]] = rhs[a];
-        FNO_HIP(hipMemcpyAsync(dcoef, c.data(), c.size() * sizeof(double), hipMemcpyHostToDevice, e.stream));
-        launch_combine(amp_, ht[0], nt_, dcoef, (int)c.size(), 1.0, 0.0, nt_, e.stream);
-        FNO_HIP(hipStreamSynchronize(e.stream));  // c is a host temporary
+        FNO_HIP(hipMemcpyAsync(dcoef, c, nc * sizeof(double), hipMemcpyHostToDevice, e.stream));
+        launch_combine(amp_, ht[0], nt_, dcoef, nc, 1.0, 0.0, nt_, e.stream);
       } else {
         launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
       }
     } else {
       launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
     }
-    double E = energy();
+    energy_async();
+    if (it < opt.max_iter && !(opt.guess == 1 && it + 1 == 3)) {
+      residual(true);
+      ahead = true;
+    }
+    FNO_HIP(hipEventSynchronize(e_ready_));
+    const double E = host_pin_[0];
     de = E - e_old;
     e_old = E;
     if (rnorm < opt.r_tol && std::fabs(de) < opt.e_tol) {
@@ -634,6 +671,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   release_guess();
   // release the DIIS history
   FNO_HIP(hipStreamSynchronize(e.stream));
+  e.flush_timers(cc_prog_);
   owned_.erase(std::remove(owned_.begin(), owned_.end(), hist), owned_.end());
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dcoef), owned_.end());
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dres), owned_.end());

@@ -42,6 +42,8 @@ Context::~Context() {
   (void)hipSetDevice(device);
   (void)hipDeviceSynchronize();
   for (double* p : owned_) (void)hipFree(p);
+  if (host_pin_) (void)hipHostFree(host_pin_);
+  if (e_ready_) (void)hipEventDestroy(e_ready_);
   eng.reset();
 }
 

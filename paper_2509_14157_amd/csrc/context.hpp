@@ -99,7 +99,14 @@ class Context {
   void setup_cc();
   void dress();
   double energy();
-  void residual();
+  // energy terms and the copy of E into host_pin_[0], followed by e_ready_
+  void energy_async();
+  double* pinned();  // host_pin_ (kPinned doubles of pinned host memory), allocated on first use
+  static constexpr int kPinned = 64;
+  double* host_pin_ = nullptr;
+  hipEvent_t e_ready_ = nullptr;
+  // defer_timers: a replayed sweep's in-graph timers are read later
+  void residual(bool defer_timers = false);
   void residual_body(Prec tri);
   void plain_guess();
   double t3_rms(const double* x);

@@ -170,16 +170,24 @@ void Engine::abort_record() {
   prog->clear();
 }
 
-void Engine::replay(const Program& prog) {
+void Engine::flush_timers(const Program& prog) {
+  if (!prog.pending) return;
+  for (const auto& t : prog.timers) FNO_HIP(hipEventSynchronize(t.b));
+  for (const auto& t : prog.timers) {
+    float ms = 0;
+    FNO_HIP(hipEventElapsedTime(&ms, t.a, t.b));
+    prof_.push_back({t.label, t.spec, t.flops, t.bytes, nullptr, nullptr, ms});
+  }
+  prog.pending = false;
+}
+
+void Engine::replay(const Program& prog, bool defer) {
+  // the event nodes are re-recorded by this replay: read the last one's first
+  flush_timers(prog);
   for (auto& it : prog.items) FNO_HIP(hipGraphLaunch(it.exec, stream));
   if (!prog.timers.empty()) {
-    // the event nodes are re-recorded by the next replay: read them now
-    for (const auto& t : prog.timers) FNO_HIP(hipEventSynchronize(t.b));
-    for (const auto& t : prog.timers) {
-      float ms = 0;
-      FNO_HIP(hipEventElapsedTime(&ms, t.a, t.b));
-      prof_.push_back({t.label, t.spec, t.flops, t.bytes, nullptr, nullptr, ms});
-    }
+    prog.pending = true;
+    if (!defer) flush_timers(prog);
   }
 }
 

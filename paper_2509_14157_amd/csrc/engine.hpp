@@ -97,6 +97,8 @@ struct Program {
     hipEvent_t a, b;
   };
   std::vector<Timer> timers;
+  // the last replay's timers have not been read yet (deferred replay)
+  mutable bool pending = false;
   uint64_t epoch = 0;  // engine epoch the recording is valid for
   int prec = -1;
   bool profiled = false;
@@ -106,6 +108,9 @@ struct Program {
     for (auto& it : items)
       if (it.exec) (void)hipGraphExecDestroy(it.exec);
     items.clear();
+    if (pending)
+      for (auto& t : timers) (void)hipEventSynchronize(t.b);
+    pending = false;
     for (auto& t : timers) {
       (void)hipEventDestroy(t.a);
       (void)hipEventDestroy(t.b);
@@ -175,7 +180,10 @@ class Engine {
   void begin_record(Program& prog);
   void end_record(Program& prog);
   void abort_record();  // after an error while recording: discard the capture
-  void replay(const Program& prog);
+  // Launches a recorded program.  Its timers are read after the launch, or,
+  // with defer, at the next replay or flush_timers (the host does not wait).
+  void replay(const Program& prog, bool defer = false);
+  void flush_timers(const Program& prog);
   bool recording() const { return rec_ != nullptr; }
   hipStream_t own_stream() const { return own_stream_; }
 
