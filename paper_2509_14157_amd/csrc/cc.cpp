@@ -288,10 +288,11 @@ void Context::residual(bool defer_timers) {
 void Context::residual_body(Prec tri) {
   Engine& e = *eng;
   e.prec = Prec::FP64;
-  launch_fill(res_, 0.0, nt_, e.stream);
+  std::vector<Tensor*> cleared;
   for (const char* nm : {"F2_vv", "F2_oo", "W2_oooo", "W2_vvvv", "W2_ovvo", "F3_vv", "F3_oo", "W3_oooo", "W3_vvvv",
                          "W3_ovvo", "W3_vvvo", "W3_ovoo"})
-    e.zero(e.get(nm));
+    cleared.push_back(e.get(nm));
+  e.zero_many(cleared, res_, nt_);
   dress();
   e.stats.clear();
   e.record = true;

@@ -437,6 +437,21 @@ void Engine::zero(Tensor* t) {
   launch_fill(t->d, 0.0, t->elems, stream);
 }
 
+void Engine::zero_many(const std::vector<Tensor*>& ts, double* extra, int64_t extra_n) {
+  std::vector<double*> p;
+  std::vector<int64_t> n;
+  if (extra) {
+    p.push_back(extra);
+    n.push_back(extra_n);
+  }
+  for (Tensor* t : ts) {
+    FNO_REQUIRE(t->full_view(), kEINVAL, "zero() needs a whole tensor");
+    p.push_back(t->d);
+    n.push_back(t->elems);
+  }
+  launch_zero_many(p.data(), n.data(), (int)p.size(), stream);
+}
+
 // ------------------------------------------------------------------ planning
 struct Engine::Plan {
   std::string spec;

@@ -146,6 +146,8 @@ class Engine {
   bool has(const std::string& name) const { return reg_.count(name) != 0; }
   void drop(const std::string& name);
   void zero(Tensor* t);
+  // zero(t) for every tensor, plus extra[0 .. extra_n) when given, in one launch
+  void zero_many(const std::vector<Tensor*>& ts, double* extra = nullptr, int64_t extra_n = 0);
 
   // --- terms
   void term(const std::string& spec, double scale = 1.0);

@@ -196,7 +196,9 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
     launch_scale_rows(in, sz, r + sp.blocks[b].offset, ldr, (double)t.sign[b], sz, count, sp.nb, e.stream);
   }
   auto sweep = [&]() {
-    for (int i = 0; i < t.nzero; ++i) e.zero(e.get(t.zero[i]));
+    std::vector<Tensor*> cleared;
+    for (int i = 0; i < t.nzero; ++i) cleared.push_back(e.get(t.zero[i]));
+    e.zero_many(cleared);
     e.stats.clear();
     e.record = true;
     // the R blocks are fixed during one sigma: share their expansions

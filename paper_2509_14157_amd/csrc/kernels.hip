@@ -170,6 +170,39 @@ void launch_fill(double* x, double v, int64_t n, hipStream_t s) {
   FNO_HIP(hipGetLastError());
 }
 
+// Several arrays cleared by one launch: blockIdx.y picks the array.
+constexpr int kZeroMax = 16;
+struct ZeroList {
+  double* p[kZeroMax];
+  int64_t n[kZeroMax];
+};
+__global__ void __launch_bounds__(256) zero_many_kernel(ZeroList z) {
+  double* p = z.p[blockIdx.y];
+  const int64_t n = z.n[blockIdx.y];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
+void launch_zero_many(double* const* ptrs, const int64_t* ns, int count, hipStream_t s) {
+  int i = 0;
+  while (i < count) {
+    ZeroList z{};
+    int k = 0;
+    int64_t nmax = 0;
+    for (; i < count && k < kZeroMax; ++i) {
+      if (ns[i] <= 0) continue;
+      z.p[k] = ptrs[i];
+      z.n[k] = ns[i];
+      nmax = std::max(nmax, ns[i]);
+      ++k;
+    }
+    if (k == 0) continue;
+    const int64_t blocks = std::min<int64_t>((nmax + 255) / 256, 4096);
+    zero_many_kernel<<<dim3((unsigned)blocks, (unsigned)k), dim3(256), 0, s>>>(z);
+    FNO_HIP(hipGetLastError());
+  }
+}
+
 __global__ void __launch_bounds__(256) axpby_kernel(double* __restrict__ y, const double* __restrict__ x, double a,
                                                     double b, int64_t n) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

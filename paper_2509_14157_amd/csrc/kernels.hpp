@@ -13,6 +13,8 @@ void launch_fold(const IndexTables& tb, const OperandDesc& outd, const MatDim& o
                  const MatDim& xcols, const FoldCombos& fc, const void* X, Prec xprec, double* out, double alpha,
                  hipStream_t s);
 void launch_fill(double* x, double v, int64_t n, hipStream_t s);
+// ptrs[i][0 .. ns[i]) = 0 for every i, in as few launches as possible
+void launch_zero_many(double* const* ptrs, const int64_t* ns, int count, hipStream_t s);
 
 // table construction (run once per plan)
 // off[i], sign[i] for i < dims.size: contribution of the operand groups set in
