@@ -142,6 +142,7 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
         h = make_hamiltonian(o, full_virtuals_for(v), seed)
         c = P.Context(0)
         c.set_graphs(not args.no_graphs)
+        c.set_autotune(not args.no_autotune)  # tiles chosen in each shape's first host-launched sweep
         c.load_hamiltonian(h.fock, h.eri, o)
         kept, _, _ = c.truncate(1.0, v)
         assert kept == v
@@ -202,6 +203,7 @@ def bench_eom(args, nroots=8):
     out = {}
     with P.Context(0) as c:
         c.set_graphs(not args.no_graphs)
+        c.set_autotune(not args.no_autotune)  # tiles chosen in each shape's first host-launched sweep
         c.load_hamiltonian(h.fock, h.eri, o)
         c.truncate(1.0, kv)
         t0 = time.perf_counter()

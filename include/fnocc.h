@@ -235,7 +235,9 @@ int fno_set_graphs(fno_ctx *ctx, int on);
  * MFMA tile configuration on a scratch output and keeps the fastest for that
  * shape in this context; fno_profile_report lists the choices under "tuned".
  * Tiles change the tiling and split-K slicing, not the k order within a
- * slice, so results agree with the untuned run to rounding.
+ * slice, so results agree with the untuned run to rounding.  The setting
+ * survives fno_load_hamiltonian and fno_truncate; the tuned choices do not
+ * (they belong to the problem's shapes).
  */
 int fno_set_autotune(fno_ctx *ctx, int on);
 

@@ -345,7 +345,8 @@ int fno_profile_filter(fno_ctx* ctx, const char* substr) {
 
 int fno_set_autotune(fno_ctx* ctx, int on) {
   return guard(ctx, [&](fno::Context& c) {
-    c.eng->autotune = on != 0;
+    c.autotune = on != 0;
+    c.eng->autotune = c.autotune;
     return FNO_OK;
   });
 }

@@ -36,6 +36,7 @@ void Context::reset_engine(std::unique_ptr<Engine> e) {
   eom_.reset();
   eng = std::move(e);
   if (user_stream) eng->stream = user_stream;
+  eng->autotune = autotune;
 }
 
 Context::~Context() {

@@ -88,6 +88,7 @@ class Context {
   // launch mode: replay the residual sweep from a recorded hipGraph program
   bool use_graphs = true;
   hipStream_t user_stream = nullptr;  // caller's stream (fno_set_stream), kept across engine rebuilds
+  bool autotune = false;              // GEMM tile autotuner (fno_set_autotune), kept across engine rebuilds
   void set_stream(hipStream_t s);
   void reset_engine(std::unique_ptr<Engine> e);
   struct EomSpace;  // per-variant layout and tensors (eom_space.hpp)
