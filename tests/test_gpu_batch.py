@@ -80,3 +80,18 @@ def test_autotuned_tiles_give_the_same_energy(P):
         c.profile(False)
     assert abs(e1 - e0) < 1e-10
     assert len(rep["tuned"]) > 0
+
+
+def test_autotune_setting_survives_truncation(P):
+    print("autotune after truncation", flush=True)
+    h = make_hamiltonian(4, 12, 47)
+    with P.Context(0) as c:
+        c.set_autotune(True)  # before the engine is rebuilt by the truncation
+        c.load_hamiltonian(h.fock, h.eri, 4)
+        kept, _, _ = c.truncate(1.0, 9)
+        assert kept == 9
+        c.profile(True)
+        c.ccsdt(max_iter=1, allow_noconv=True)
+        rep = c.profile_report()
+        c.profile(False)
+    assert len(rep["tuned"]) > 0
