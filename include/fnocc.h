@@ -211,8 +211,9 @@ int fno_profile_report(fno_ctx *ctx, char *buf, size_t len);
  * Restrict timing to the kernels whose name contains `substr` (NULL or "" =
  * all kernels).  With a filter set, the residual and sigma sweeps are still
  * replayed from hipGraphs: the selected GEMMs are bracketed by event-record
- * nodes inside the graph, read after every replay.  FNO_EINVAL on a null
- * context.
+ * nodes inside the graph, read after every replay (in fno_ccsdt, where the
+ * next sweep is enqueued before the host waits for the energy, after the
+ * following synchronization).  FNO_EINVAL on a null context.
  */
 int fno_profile_filter(fno_ctx *ctx, const char *substr);
 
@@ -225,7 +226,9 @@ int fno_profile_filter(fno_ctx *ctx, const char *substr);
  * back into it) and later sweeps replay it; any new allocation in the context
  * discards the recording.
  * on = 0: every launch is issued from the host.  Results are identical in both
- * modes (same kernels, same order).
+ * modes (same kernels, same order).  In either mode fno_ccsdt enqueues the next
+ * iteration's sweep before it waits for the current energy; when the loop
+ * stops before max_iter, that last sweep's residual is not used.
  */
 int fno_set_graphs(fno_ctx *ctx, int on);
 
