@@ -158,3 +158,16 @@ def test_graph_replay_matches_host_launches(P, prec):
         c.set_graphs(True)
         e1 = c.ccsdt(r_tol=1e-9, e_tol=1e-11, prec=prec, allow_noconv=True)
         assert e0["iters"] == e1["iters"] and e0["e_tot"] == e1["e_tot"]
+
+
+def test_sweep_enqueued_ahead_leaves_no_state(P):
+    """fno_ccsdt enqueues the next sweep before it checks convergence; a solve that
+    stops early leaves that sweep unused, and the next solve starts clean."""
+    print("sweep ahead", flush=True)
+    h = make_hamiltonian(4, 12, 2)
+    with _ctx(P, h) as c:
+        c.ccsdt(r_tol=1e-9, e_tol=1e-11)  # converges before max_iter: one sweep left unused
+        a = c.ccsdt(max_iter=3, allow_noconv=True)
+    with _ctx(P, h) as c:
+        b = c.ccsdt(max_iter=3, allow_noconv=True)
+    assert a["e_tot"] == b["e_tot"] and a["res_norm"] == b["res_norm"] and a["iters"] == b["iters"] == 3
