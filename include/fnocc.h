@@ -206,8 +206,8 @@ int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops)
  * NUL-terminated, FNO_EINVAL if too small) and clears the records.
  */
 /*
- * Diagnostics: with the environment variable FNO_TRACE set (read once per
- * process), the library prints to stderr each Davidson iteration's Ritz
+ * Diagnostics: with the environment variable FNO_TRACE set, the library
+ * prints to stderr each Davidson iteration's Ritz
  * values and residual norms, the autotuner's time for every tile of every
  * shape it tunes, and the shape (groups, combos, shuffles, outputs) of every
  * fold it launches.
