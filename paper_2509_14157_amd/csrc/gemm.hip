@@ -61,13 +61,13 @@ __device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, in
 }
 
 // ---------------------------------------------------------------------------
-// 16x16x4 path (FP64 / FP32).  BK = 16 (4 MFMA k-steps per staged tile).
-template <typename T, int BM, int BN, bool AK, bool BN_FAST>
-__global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
-                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
-                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta,
-                                                      int64_t kchunk, int64_t cz, int m_fast) {
-  constexpr int BK = 16;
+// 16x16x4 path (FP64 / FP32).  BK k values staged per tile (BK / 4 MFMA k-steps
+// per pair of barriers): 16, or 32 for the FP32 tiles, whose MFMA steps take
+// half as long, so the barriers and loads weigh twice as much per flop.
+template <typename T, int BM, int BN, bool AK, bool BN_FAST, int BK>
+__device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
+                                             const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
+                                             T alpha, T beta, int64_t kchunk, int64_t cz, int m_fast) {
   {  // split-K: this z-slice owns K range [z*kchunk, z*kchunk + kchunk)
     const int64_t k0 = (int64_t)blockIdx.z * kchunk;
     A += AK ? k0 : k0 * lda;
@@ -204,6 +204,23 @@ __global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, i
 }
 
 // ---------------------------------------------------------------------------
+
+template <typename T, int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                      int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                      T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                      int64_t kchunk, int64_t cz, int m_fast) {
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+}
+
+template <typename T, int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256, 2) gemm_k32_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                       int64_t kchunk, int64_t cz, int m_fast) {
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+}
+
 // Double-buffered 16x16x4 path (FP64 / FP32): two LDS stages, one barrier per
 // k-tile.  While the MFMAs of stage s run, the next k-tile is already in
 // flight from global memory into registers; it is written into the other LDS
@@ -494,11 +511,14 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
 // Tile table used by the planner and the autotuner.
 struct TileCfg {
   int bm, bn;
-  int bk;  // double-buffered k-tile depth (FP64 / FP32); 0 = single-buffered BK = 16
+  int bk;  // double-buffered k-tile depth (FP64 / FP32); 0 = single-buffered
+  int kd;  // single-buffered k depth: 16 or 32
 };
-static const TileCfg kTiles[] = {{64, 64, 0},    {128, 64, 0},   {64, 128, 0},   {128, 128, 0}, {32, 64, 0},
-                                 {64, 32, 0},    {128, 128, 16}, {128, 128, 32}, {128, 64, 32}, {64, 128, 32},
-                                 {64, 64, 32},   {256, 64, 0},   {64, 256, 0}};
+static const TileCfg kTiles[] = {{64, 64, 0, 16},   {128, 64, 0, 16},  {64, 128, 0, 16},  {128, 128, 0, 16},
+                                 {32, 64, 0, 16},   {64, 32, 0, 16},   {128, 128, 16, 0}, {128, 128, 32, 0},
+                                 {128, 64, 32, 0},  {64, 128, 32, 0},  {64, 64, 32, 0},   {256, 64, 0, 16},
+                                 {64, 256, 0, 16},  {128, 128, 0, 32}, {128, 64, 0, 32},  {256, 128, 0, 16},
+                                 {128, 256, 0, 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
 int gemm_num_tiles(Prec) { return kNumTiles; }
@@ -570,10 +590,21 @@ static void launch_splitk_reduce(const T* P, int split, int64_t M, int64_t N, T*
   }
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, bool AK, bool BF, int KD>
+static void k4_launch(dim3 grid, hipStream_t s, const GemmArgs& g, const T* A, const T* B, T* C, int64_t ldc, T al,
+                      T be, int64_t kchunk, int64_t cz, int mf) {
+  if constexpr (KD == 32)
+    gemm_k32_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be, kchunk,
+                                                           cz, mf);
+  else
+    gemm_k4_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be, kchunk,
+                                                          cz, mf);
+}
+
+template <typename T, int BM, int BN, int KD = 16>
 static void launch_k4(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
-  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 15) / 16) * 16 : (g.K > 0 ? g.K : 1);
+  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + KD - 1) / KD) * KD : (g.K > 0 ? g.K : 1);
   const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
   dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), 1u, (unsigned)nz);
   const int mf = m_fast_order(g);
@@ -584,17 +615,13 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
   const int64_t cz = split > 1 ? g.M * g.N : 0;
   T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
   if (g.a_kfast && g.b_nfast)
-    gemm_k4_kernel<T, BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                               kchunk, cz, mf);
+    k4_launch<T, BM, BN, true, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
   else if (g.a_kfast)
-    gemm_k4_kernel<T, BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                                kchunk, cz, mf);
+    k4_launch<T, BM, BN, true, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
   else if (g.b_nfast)
-    gemm_k4_kernel<T, BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
-                                                                kchunk, cz, mf);
+    k4_launch<T, BM, BN, false, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
   else
-    gemm_k4_kernel<T, BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al,
-                                                                 be, kchunk, cz, mf);
+    k4_launch<T, BM, BN, false, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
   if (split > 1) {
     launch_splitk_reduce<T>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc, (T)g.alpha, (T)g.beta, s);
   }
@@ -637,6 +664,29 @@ static void dispatch_tile(const GemmArgs& g, hipStream_t s) {
     launch_k4<double, BM, BN>(g, s);
   else if (g.prec == Prec::FP32)
     launch_k4<float, BM, BN>(g, s);
+  else
+    launch_b3<BM, BN>(g, s);
+}
+
+// FP32-only tiles: a 128 x 64 (or 64 x 128) block per wavefront, the register
+// budget of the FP64 128 x 128 tile; FP64 and split-BF16 run them as 128 x 128.
+template <int BM, int BN>
+static void dispatch_f32(const GemmArgs& g, hipStream_t s) {
+  if (g.prec == Prec::FP32)
+    launch_k4<float, BM, BN>(g, s);
+  else if (g.prec == Prec::FP64)
+    launch_k4<double, 128, 128>(g, s);
+  else
+    launch_b3<128, 128>(g, s);
+}
+
+// BK = 32 single-buffered tiles (FP64 / FP32); split-BF16 runs its own kernel.
+template <int BM, int BN>
+static void dispatch_k32(const GemmArgs& g, hipStream_t s) {
+  if (g.prec == Prec::FP64)
+    launch_k4<double, BM, BN, 32>(g, s);
+  else if (g.prec == Prec::FP32)
+    launch_k4<float, BM, BN, 32>(g, s);
   else
     launch_b3<BM, BN>(g, s);
 }
@@ -714,6 +764,7 @@ int gemm_default_tile(const GemmArgs& g) { return default_tile(g); }
 
 std::string gemm_label(const GemmArgs& g) {
   int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
+  if (t >= 15 && g.prec != Prec::FP32) t = 3;  // FP32-only tiles run as 128 x 128
   std::string bm = std::to_string(kTiles[t].bm), bn = std::to_string(kTiles[t].bn);
   std::string lay = std::string(g.a_kfast ? "true" : "false") + ", " + (g.b_nfast ? "true" : "false");
   if (g.prec == Prec::BF16X3) {
@@ -723,8 +774,8 @@ std::string gemm_label(const GemmArgs& g) {
   if (kTiles[t].bk > 0)
     return std::string("fno::gemm_db_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " +
            bn + ", " + std::to_string(kTiles[t].bk) + ", " + lay + ">";
-  return std::string("fno::gemm_k4_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " + bn +
-         ", " + lay + ">";
+  const char* name = kTiles[t].kd == 32 ? "fno::gemm_k32_kernel<" : "fno::gemm_k4_kernel<";
+  return std::string(name) + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " + bn + ", " + lay + ">";
 }
 
 void launch_gemm(const GemmArgs& g, hipStream_t s) {
@@ -743,7 +794,11 @@ void launch_gemm(const GemmArgs& g, hipStream_t s) {
     case 9: dispatch_db<64, 128, 32>(g, s); break;
     case 10: dispatch_db<64, 64, 32>(g, s); break;
     case 11: dispatch_tall<256, 64>(g, s); break;
-    default: dispatch_tall<64, 256>(g, s); break;
+    case 12: dispatch_tall<64, 256>(g, s); break;
+    case 13: dispatch_k32<128, 128>(g, s); break;
+    case 14: dispatch_k32<128, 64>(g, s); break;
+    case 15: dispatch_f32<256, 128>(g, s); break;
+    default: dispatch_f32<128, 256>(g, s); break;
   }
   FNO_HIP(hipGetLastError());
 }

@@ -25,7 +25,7 @@ def ctx():
 def test_gemm_all_tiles_and_layouts(ctx, prec):
     rng = np.random.default_rng(1)
     bad = []
-    for tile in range(13):  # every tile configuration (6 single-, 5 double-buffered, 256x64, 64x256)
+    for tile in range(17):  # every tile: 6 single-, 5 double-buffered, 256x64, 64x256, two with k depth 32, two FP32-only
         for (M, N, K) in ((37, 53, 29), (130, 70, 45), (16, 16, 4), (1, 70, 33), (257, 129, 3),
                           (3, 5, 5000), (1, 1, 70001)):
             for ak in (True, False):
