@@ -521,7 +521,8 @@ static const TileCfg kTiles[] = {{64, 64, 0, 16},   {128, 64, 0, 16},  {64, 128,
                                  {128, 256, 0, 16}};
 constexpr int kNumTiles = sizeof(kTiles) / sizeof(kTiles[0]);
 
-int gemm_num_tiles(Prec) { return kNumTiles; }
+// the last two tiles are FP32-only (the other precisions would run them as tile 3)
+int gemm_num_tiles(Prec p) { return p == Prec::FP32 ? kNumTiles : kNumTiles - 2; }
 
 static int default_tile(const GemmArgs& g) {
   // Prefer big tiles when the grid still fills the 256 CUs several times.
