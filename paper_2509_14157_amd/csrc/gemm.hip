@@ -64,7 +64,7 @@ __device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, in
 // 16x16x4 path (FP64 / FP32).  BK k values staged per tile (BK / 4 MFMA k-steps
 // per pair of barriers): 16, or 32 for the FP32 tiles, whose MFMA steps take
 // half as long, so the barriers and loads weigh twice as much per flop.
-template <typename T, int BM, int BN, bool AK, bool BN_FAST, int BK>
+template <typename T, int BM, int BN, bool AK, bool BN_FAST, int BK, int VW>
 __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
                                              const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
                                              T alpha, T beta, int64_t kchunk, int64_t cz, int m_fast) {
@@ -77,8 +77,13 @@ __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, co
   }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_PER = BM * BK / 256;  // elements each thread stages
-  constexpr int B_PER = BN * BK / 256;
+  // staged per thread: VW consecutive elements along the operand's fastest
+  // index per global load (VW = 1: one element per load)
+  constexpr int A_PER = BM * BK / VW / 256;
+  constexpr int B_PER = BN * BK / VW / 256;
+  static_assert(A_PER * VW * 256 == BM * BK && B_PER * VW * 256 == BN * BK, "tile shape");
+  constexpr int AF = AK ? BK / VW : BM / VW;       // vectors along A's fast index
+  constexpr int BF = BN_FAST ? BN / VW : BK / VW;  // vectors along B's fast index
   constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
   __shared__ T As[BK][BM + PAD];
   __shared__ T Bs[BK][BN + PAD];
@@ -96,67 +101,108 @@ __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, co
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = (typename Acc<T>::type){0, 0, 0, 0};
 
-  T ra[A_PER], rb[B_PER];
+  typedef T Vec __attribute__((ext_vector_type(VW)));  // 16 bytes when VW > 1: one dwordx4 load
+  Vec ra[A_PER], rb[B_PER];
+  // a run of VW elements from p: one 16-byte load when all are in range (the
+  // host only selects VW > 1 when every run starts 16-byte aligned), else
+  // one guarded load per element
+  auto load_run = [&](const T* p, int64_t fast, int64_t fast_end, bool slow_ok) {
+    Vec v;
+    if constexpr (VW > 1) {
+      if (slow_ok && fast + VW <= fast_end) {
+        v = *(const Vec*)p;
+        return v;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < VW; ++i) v[i] = (slow_ok && fast + i < fast_end) ? p[i] : (T)0;
+    return v;
+  };
   auto load_tiles = [&](int64_t k0) {
+    if constexpr (VW == 1) {
+#pragma unroll
+      for (int p = 0; p < A_PER; ++p) {
+        int e = tid + p * 256;
+        int mm, kk;
+        if (AK) {  // k fastest in memory: consecutive threads walk k
+          kk = e % BK;
+          mm = e / BK;
+        } else {
+          mm = e % BM;
+          kk = e / BM;
+        }
+        int64_t gm = m0 + mm, gk = k0 + kk;
+        T v = 0;
+        if (gm < M && gk < K) v = AK ? A[gm * lda + gk] : A[gk * lda + gm];
+        ra[p][0] = v;
+      }
+#pragma unroll
+      for (int p = 0; p < B_PER; ++p) {
+        int e = tid + p * 256;
+        int nn, kk;
+        if (BN_FAST) {
+          nn = e % BN;
+          kk = e / BN;
+        } else {
+          kk = e % BK;
+          nn = e / BK;
+        }
+        int64_t gn = n0 + nn, gk = k0 + kk;
+        T v = 0;
+        if (gn < N && gk < K) v = BN_FAST ? B[gk * ldb + gn] : B[gn * ldb + gk];
+        rb[p][0] = v;
+      }
+      return;
+    }
 #pragma unroll
     for (int p = 0; p < A_PER; ++p) {
-      int e = tid + p * 256;
-      int mm, kk;
+      const int e = tid + p * 256;
+      const int f = (e % AF) * VW, sl = e / AF;  // fast and slow offsets in the tile
       if (AK) {  // k fastest in memory: consecutive threads walk k
-        kk = e % BK;
-        mm = e / BK;
+        const int64_t gm = m0 + sl, gk = k0 + f;
+        ra[p] = load_run(A + (gm < M ? gm : 0) * lda + gk, gk, K, gm < M);
       } else {
-        mm = e % BM;
-        kk = e / BM;
+        const int64_t gm = m0 + f, gk = k0 + sl;
+        ra[p] = load_run(A + (gk < K ? gk : 0) * lda + gm, gm, M, gk < K);
       }
-      int64_t gm = m0 + mm, gk = k0 + kk;
-      T v = 0;
-      if (gm < M && gk < K) v = AK ? A[gm * lda + gk] : A[gk * lda + gm];
-      ra[p] = v;
     }
 #pragma unroll
     for (int p = 0; p < B_PER; ++p) {
-      int e = tid + p * 256;
-      int nn, kk;
+      const int e = tid + p * 256;
+      const int f = (e % BF) * VW, sl = e / BF;
       if (BN_FAST) {
-        nn = e % BN;
-        kk = e / BN;
+        const int64_t gn = n0 + f, gk = k0 + sl;
+        rb[p] = load_run(B + (gk < K ? gk : 0) * ldb + gn, gn, N, gk < K);
       } else {
-        kk = e % BK;
-        nn = e / BK;
+        const int64_t gn = n0 + sl, gk = k0 + f;
+        rb[p] = load_run(B + (gn < N ? gn : 0) * ldb + gk, gk, K, gn < N);
       }
-      int64_t gn = n0 + nn, gk = k0 + kk;
-      T v = 0;
-      if (gn < N && gk < K) v = BN_FAST ? B[gk * ldb + gn] : B[gn * ldb + gk];
-      rb[p] = v;
     }
   };
   auto store_tiles = [&]() {
 #pragma unroll
     for (int p = 0; p < A_PER; ++p) {
-      int e = tid + p * 256;
-      int mm, kk;
-      if (AK) {
-        kk = e % BK;
-        mm = e / BK;
-      } else {
-        mm = e % BM;
-        kk = e / BM;
+      const int e = tid + p * 256;
+      const int f = (e % AF) * VW, sl = e / AF;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        if (AK)
+          As[f + i][sl] = ra[p][i];
+        else
+          As[sl][f + i] = ra[p][i];
       }
-      As[kk][mm] = ra[p];
     }
 #pragma unroll
     for (int p = 0; p < B_PER; ++p) {
-      int e = tid + p * 256;
-      int nn, kk;
-      if (BN_FAST) {
-        nn = e % BN;
-        kk = e / BN;
-      } else {
-        kk = e % BK;
-        nn = e / BK;
+      const int e = tid + p * 256;
+      const int f = (e % BF) * VW, sl = e / BF;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        if (BN_FAST)
+          Bs[sl][f + i] = rb[p][i];
+        else
+          Bs[f + i][sl] = rb[p][i];
       }
-      Bs[kk][nn] = rb[p];
     }
   };
 
@@ -210,7 +256,18 @@ __global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, i
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                       int64_t kchunk, int64_t cz, int m_fast) {
-  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+}
+
+// Same tile with 16-byte global loads (4 floats or 2 doubles per load); the
+// host launches it only when both operands' rows start 16-byte aligned.
+template <typename T, int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256, 2) gemm_k4v_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                       int64_t kchunk, int64_t cz, int m_fast) {
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, 16 / sizeof(T)>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz,
+                                                           m_fast);
 }
 
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
@@ -218,7 +275,16 @@ __global__ void __launch_bounds__(256, 2) gemm_k32_kernel(int64_t M, int64_t N, 
                                                        int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                        T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                        int64_t kchunk, int64_t cz, int m_fast) {
-  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+}
+
+template <typename T, int BM, int BN, bool AK, bool BN_FAST>
+__global__ void __launch_bounds__(256, 2) gemm_k32v_kernel(int64_t M, int64_t N, int64_t K, const T* __restrict__ A,
+                                                        int64_t lda, const T* __restrict__ B, int64_t ldb,
+                                                        T* __restrict__ C, int64_t ldc, T alpha, T beta,
+                                                        int64_t kchunk, int64_t cz, int m_fast) {
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32, 16 / sizeof(T)>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz,
+                                                           m_fast);
 }
 
 // Double-buffered 16x16x4 path (FP64 / FP32): two LDS stages, one barrier per
@@ -591,15 +657,41 @@ static void launch_splitk_reduce(const T* P, int split, int64_t M, int64_t N, T*
   }
 }
 
+// Tiles whose staged elements split into whole 16-byte vectors per thread.
+template <typename T, int BM, int BN, int KD>
+constexpr bool k4_vectorizable() {
+  constexpr int vw = 16 / sizeof(T);
+  return (BM * KD) % (vw * 256) == 0 && (BN * KD) % (vw * 256) == 0;
+}
+
 template <typename T, int BM, int BN, bool AK, bool BF, int KD>
 static void k4_launch(dim3 grid, hipStream_t s, const GemmArgs& g, const T* A, const T* B, T* C, int64_t ldc, T al,
-                      T be, int64_t kchunk, int64_t cz, int mf) {
+                      T be, int64_t kchunk, int64_t cz, int mf, bool vec) {
+  if constexpr (k4_vectorizable<T, BM, BN, KD>()) {
+    if (vec) {
+      if constexpr (KD == 32)
+        gemm_k32v_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
+                                                                kchunk, cz, mf);
+      else
+        gemm_k4v_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be,
+                                                               kchunk, cz, mf);
+      return;
+    }
+  }
   if constexpr (KD == 32)
     gemm_k32_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be, kchunk,
                                                            cz, mf);
   else
     gemm_k4_kernel<T, BM, BN, AK, BF><<<grid, 256, 0, s>>>(g.M, g.N, g.K, A, g.lda, B, g.ldb, C, ldc, al, be, kchunk,
                                                           cz, mf);
+}
+
+// Both operands' rows (and split-K slices, cut at multiples of 16 k) start
+// 16-byte aligned: the vector-load tiles apply.
+static bool gemm_rows_aligned(const GemmArgs& g) {
+  const int64_t vw = g.prec == Prec::FP64 ? 2 : 4;
+  return g.prec != Prec::BF16X3 && ((uintptr_t)g.A % 16) == 0 && ((uintptr_t)g.B % 16) == 0 && g.lda % vw == 0 &&
+         g.ldb % vw == 0;
 }
 
 template <typename T, int BM, int BN, int KD = 16>
@@ -615,14 +707,15 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
   const int64_t ldc = split > 1 ? g.N : g.ldc;
   const int64_t cz = split > 1 ? g.M * g.N : 0;
   T al = split > 1 ? (T)1 : (T)g.alpha, be = split > 1 ? (T)0 : (T)g.beta;
+  const bool vec = gemm_rows_aligned(g);
   if (g.a_kfast && g.b_nfast)
-    k4_launch<T, BM, BN, true, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
+    k4_launch<T, BM, BN, true, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf, vec);
   else if (g.a_kfast)
-    k4_launch<T, BM, BN, true, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
+    k4_launch<T, BM, BN, true, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf, vec);
   else if (g.b_nfast)
-    k4_launch<T, BM, BN, false, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
+    k4_launch<T, BM, BN, false, true, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf, vec);
   else
-    k4_launch<T, BM, BN, false, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf);
+    k4_launch<T, BM, BN, false, false, KD>(grid, s, g, A, B, C, ldc, al, be, kchunk, cz, mf, vec);
   if (split > 1) {
     launch_splitk_reduce<T>((const T*)g.ws, nz, g.M, g.N, (T*)g.C, g.ldc, (T)g.alpha, (T)g.beta, s);
   }
@@ -775,7 +868,10 @@ std::string gemm_label(const GemmArgs& g) {
   if (kTiles[t].bk > 0)
     return std::string("fno::gemm_db_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " +
            bn + ", " + std::to_string(kTiles[t].bk) + ", " + lay + ">";
-  const char* name = kTiles[t].kd == 32 ? "fno::gemm_k32_kernel<" : "fno::gemm_k4_kernel<";
+  const int vw = g.prec == Prec::FP64 ? 2 : 4, kd = kTiles[t].kd;
+  const bool vec = gemm_rows_aligned(g) && (kTiles[t].bm * kd) % (vw * 256) == 0 && (kTiles[t].bn * kd) % (vw * 256) == 0;
+  const char* name = kd == 32 ? (vec ? "fno::gemm_k32v_kernel<" : "fno::gemm_k32_kernel<")
+                              : (vec ? "fno::gemm_k4v_kernel<" : "fno::gemm_k4_kernel<");
   return std::string(name) + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " + bn + ", " + lay + ">";
 }
 

@@ -2,7 +2,8 @@
 
 Long-K shapes with a tiny output take the deterministic split-K path.
 
-Ragged shapes exercise the bounds of every tile.  Errors are measured
+Ragged shapes exercise the bounds of every tile; shapes whose leading dimensions are
+multiples of 4 run the 16-byte vector-load kernels.  Errors are measured
 against sum_k |alpha a_ik b_kj| + |beta c_ij| (the scale of the rounding
 bound of each dot product): FP64 1e-13, FP32 1e-5, split-BF16 1e-4.
 """
@@ -26,8 +27,10 @@ def test_gemm_all_tiles_and_layouts(ctx, prec):
     rng = np.random.default_rng(1)
     bad = []
     for tile in range(17):  # every tile: 6 single-, 5 double-buffered, 256x64, 64x256, two with k depth 32, two FP32-only
+        # (16, 16, 4), (132, 68, 40) and (260, 196, 36) have every leading dimension a
+        # multiple of 4: they take the 16-byte vector loads, with ragged M, N and K edges
         for (M, N, K) in ((37, 53, 29), (130, 70, 45), (16, 16, 4), (1, 70, 33), (257, 129, 3),
-                          (3, 5, 5000), (1, 1, 70001)):
+                          (3, 5, 5000), (1, 1, 70001), (132, 68, 40), (260, 196, 36)):
             for ak in (True, False):
                 for bn in (True, False):
                     A = rng.normal(size=(M, K))
