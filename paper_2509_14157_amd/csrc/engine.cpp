@@ -526,6 +526,7 @@ bool build_expand_tab(const IndexTables& tb, const OperandDesc& od, const std::v
   t = ExpandTab{};
   t.rows = rows.size;
   t.cols = cols.size;
+  t.ld = cols.size;
   int64_t* ro = (int64_t*)dalloc(rows.size * 8);
   int8_t* rs = (int8_t*)dalloc(rows.size);
   int64_t* co = (int64_t*)dalloc(cols.size * 8);
@@ -1146,14 +1147,19 @@ void Engine::execute(const Plan& p, double scale) {
   double factor = 1.0;
   bool a_kfast = p.a_kfast, b_nfast = p.b_nfast;
   int64_t lda = p.lda, ldb = p.ldb;
+  // rows of an expanded operand start on 16-element boundaries when the row
+  // kernel writes them (16-byte aligned rows let the GEMM use vector loads)
+  auto padded = [](bool tab_ok, int64_t cols) { return (tab_ok && cols >= 128) ? (cols + 15) / 16 * 16 : cols; };
   auto expand_into = [&](const Tensor* t, bool tab_ok, const ExpandTab& tab, const OperandDesc& od, const MatDim& r,
-                         const MatDim& c, void* hi, void* lo) {
+                         const MatDim& c, void* hi, void* lo, int64_t ld) {
     const bool tm = timed(tab_ok ? "fno::expand_tab" : "fno::expand_kernel") && !rec_;
     hipEvent_t e0 = tm ? event() : nullptr;
     if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    if (tab_ok)
-      launch_expand_tab(tab, t->d, hi, lo, prec, stream);
-    else
+    if (tab_ok) {
+      ExpandTab tl = tab;
+      tl.ld = ld;
+      launch_expand_tab(tl, t->d, hi, lo, prec, stream);
+    } else
       launch_expand(tables, od, r, c, t->d, hi, lo, prec, true, stream);
     if (e0) {
       hipEvent_t e1 = event();
@@ -1176,7 +1182,7 @@ void Engine::execute(const Plan& p, double scale) {
       hi = it->second.hi;
       lo = it->second.lo;
       fast = true;
-      ld = cols;
+      ld = it->second.ld;
       factor *= sgn * it->second.sign;
       return true;
     }
@@ -1186,12 +1192,13 @@ void Engine::execute(const Plan& p, double scale) {
       hi = it->second.hi;
       lo = it->second.lo;
       fast = false;
-      ld = rows;
+      ld = it->second.ld;  // stored as this use's transpose: its row stride
       factor *= sgnT * it->second.sign;
       return true;
     }
     CacheEntry& ce = ecache_[key];
-    const size_t need = (size_t)(rows * cols) * esz;
+    const int64_t ldp = padded(tab_ok, cols);
+    const size_t need = (size_t)(rows * ldp) * esz;
     if (ce.bytes < need) {
       FNO_REQUIRE(!rec_, kEINVAL, "expansion cache growth while recording");
       ++epoch;
@@ -1205,7 +1212,8 @@ void Engine::execute(const Plan& p, double scale) {
       ce.bytes = need;
     }
     ce.tensor = t->name;
-    expand_into(t, tab_ok, tab, od, r, c, ce.hi, ce.lo);
+    ce.ld = ldp;
+    expand_into(t, tab_ok, tab, od, r, c, ce.hi, ce.lo, ldp);
     ce.sign = sgn;
     ce.valid = true;
     ce.lane = lane_;
@@ -1220,28 +1228,32 @@ void Engine::execute(const Plan& p, double scale) {
     hi = ce.hi;
     lo = ce.lo;
     fast = true;
-    ld = cols;
+    ld = ldp;
     return true;
   };
   if (p.a_direct) {
     A = p.A->d + p.A->base;
   } else if (!cached(p.A, p.a_cache, p.a_key, p.a_keyT, p.a_sign, p.a_signT, Msz, Ksz, p.a_tab_ok, p.a_tab, p.ad,
                      p.M, p.K, A, Alo, a_kfast, lda)) {
-    void* a = workspace(0, (size_t)(Msz * Ksz) * esz);
-    void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * Ksz) * esz) : nullptr;
-    expand_into(p.A, p.a_tab_ok, p.a_tab, p.ad, p.M, p.K, a, alo);
+    const int64_t ldp = padded(p.a_tab_ok, Ksz);
+    void* a = workspace(0, (size_t)(Msz * ldp) * esz);
+    void* alo = prec == Prec::BF16X3 ? workspace(3, (size_t)(Msz * ldp) * esz) : nullptr;
+    expand_into(p.A, p.a_tab_ok, p.a_tab, p.ad, p.M, p.K, a, alo, ldp);
     A = a;
     Alo = alo;
+    lda = ldp;
   }
   if (p.b_direct) {
     B = p.B->d + p.B->base;
   } else if (!cached(p.B, p.b_cache, p.b_key, p.b_keyT, p.b_sign, p.b_signT, Ksz, Nsz, p.b_tab_ok, p.b_tab, p.bd,
                      p.K, p.N, B, Blo, b_nfast, ldb)) {
-    void* b = workspace(1, (size_t)(Ksz * Nsz) * esz);
-    void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * Nsz) * esz) : nullptr;
-    expand_into(p.B, p.b_tab_ok, p.b_tab, p.bd, p.K, p.N, b, blo);
+    const int64_t ldp = padded(p.b_tab_ok, Nsz);
+    void* b = workspace(1, (size_t)(Ksz * ldp) * esz);
+    void* blo = prec == Prec::BF16X3 ? workspace(4, (size_t)(Ksz * ldp) * esz) : nullptr;
+    expand_into(p.B, p.b_tab_ok, p.b_tab, p.bd, p.K, p.N, b, blo, ldp);
     B = b;
     Blo = blo;
+    ldb = ldp;
   }
   if (prec == Prec::BF16X3)
     FNO_REQUIRE(Alo != nullptr && Blo != nullptr, kEINVAL, "split-BF16 GEMM needs expanded operands: " + p.spec);

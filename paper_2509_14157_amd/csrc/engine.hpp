@@ -228,6 +228,7 @@ class Engine {
     void* hi = nullptr;
     void* lo = nullptr;
     size_t bytes = 0;  // per buffer
+    int64_t ld = 0;    // row stride of the stored matrix (elements)
     int sign = 1;      // stored matrix = sign * canonical matrix
     bool valid = false;
     int lane = 0;                 // lane that made the current contents

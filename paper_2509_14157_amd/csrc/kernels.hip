@@ -640,7 +640,7 @@ __device__ __forceinline__ void expand_rows(const ExpandTab& t, const double* __
 #pragma unroll
   for (int q = 0; q < R; ++q) v[q] = *(sg[q] ? src + o[q] : &kExpandZero);
 #pragma unroll
-  for (int q = 0; q < R; ++q) expand_store<MODE>(dst, dst_lo, (r + q) * t.cols + c, sg[q] * v[q]);
+  for (int q = 0; q < R; ++q) expand_store<MODE>(dst, dst_lo, (r + q) * t.ld + c, sg[q] * v[q]);
 }
 
 template <int MODE, int NM>
@@ -745,6 +745,7 @@ static void launch_expand_rows(int mode, int nm, dim3 grid, const ExpandTab& t, 
 
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
   if (t.rows == 0 || t.cols == 0) return;
+  FNO_REQUIRE(t.ld == t.cols || t.cols >= 128, kEINVAL, "padded rows need the row kernel");
   if (t.cols < 128) {
     const int64_t total = t.rows * t.cols;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);

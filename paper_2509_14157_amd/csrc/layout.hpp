@@ -65,6 +65,7 @@ struct FoldCombos {
 constexpr int kMaxMixed = 2;
 struct ExpandTab {
   int64_t rows, cols;
+  int64_t ld;  // destination row stride (elements, >= cols) of the row kernel
   const int64_t* row_off;
   const int8_t* row_sign;
   const int64_t* col_off;
