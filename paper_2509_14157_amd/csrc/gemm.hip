@@ -15,6 +15,7 @@
 #include <hip/hip_bf16.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -206,13 +207,9 @@ __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, co
     }
   };
 
-  const int64_t nk = (K + BK - 1) / BK;
-  if (nk > 0) load_tiles(0);
-  for (int64_t kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    store_tiles();
-    __syncthreads();
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+  // the MFMA steps of one staged k tile for the first `live` row blocks (a
+  // compile-time count: each variant is a branch-free loop)
+  auto mma_tile = [&](auto live) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -223,8 +220,60 @@ __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, co
       for (int j = 0; j < TN; ++j) bfr[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
+        if (i < (int)live) {
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(af[i], bfr[j], acc[i][j]);
+          for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(af[i], bfr[j], acc[i][j]);
+        }
+    }
+  };
+
+  const int64_t nk = (K + BK - 1) / BK;
+  auto k_loop = [&](auto live) {
+    if (nk > 0) load_tiles(0);
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      __syncthreads();
+      store_tiles();
+      __syncthreads();
+      if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+      mma_tile(live);
+    }
+  };
+  if constexpr (VW > 1 && sizeof(T) == 8) {
+    // In a partial last M tile a wavefront whose sub-tile holds at most one
+    // 16-row block of C (the ring's 590 rows leave 78 in the last 128-row
+    // tile) runs the one-block loop: a second copy of the loop, kept to the
+    // FP64 vector tiles, where it costs no spills.  Other partial sub-tiles
+    // run every block; their extra rows hold zeros and are not stored.
+    const int wrow_first = __builtin_amdgcn_readfirstlane(wm * WM);  // uniform per wavefront
+    const int64_t live_rows = M - (m0 + wrow_first);
+    if (live_rows <= 16) {
+      k_loop(std::integral_constant<int, 1>{});
+    } else {
+      k_loop(std::integral_constant<int, TM>{});
+    }
+  } else {
+    // the same loop written out: built through the lambdas above, the FP32
+    // 128 x 256 and 256 x 128 tiles get a different register allocation
+    // with 24-44 spilled registers
+    if (nk > 0) load_tiles(0);
+    for (int64_t kt = 0; kt < nk; ++kt) {
+      __syncthreads();
+      store_tiles();
+      __syncthreads();
+      if (kt + 1 < nk) load_tiles((kt + 1) * BK);
+#pragma unroll
+      for (int ks = 0; ks < BK; ks += 4) {
+        const int kr = ks + (lane >> 4);
+        T af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = As[kr][wm * WM + i * 16 + (lane & 15)];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = Bs[kr][wn * WN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j) acc[i][j] = mfma4(af[i], bfr[j], acc[i][j]);
+      }
     }
   }
 
