@@ -50,3 +50,20 @@ def test_gemm_empty_k_scales_c(ctx):
     C = np.arange(12.0).reshape(3, 4)
     got = ctx.debug_gemm(np.zeros((3, 0)), np.zeros((0, 4)), C, alpha=1.0, beta=2.0)
     assert np.array_equal(got, 2 * C)
+
+
+@pytest.mark.parametrize("M", [192, 193, 207, 208, 209, 590])
+def test_gemm_fp64_partial_last_m_tile(ctx, M):
+    """FP64 128 x 128 vector tile on a partial last M tile: a wavefront whose sub-tile
+    holds at most 16 rows of C runs the one-block loop (M = 192, 193, 207, 208, and 590:
+    the ring's 78-row fifth tile), one with 17 runs every block (M = 209)."""
+    rng = np.random.default_rng(M)
+    N, K = 136, 40
+    for bn in (True, False):
+        A = rng.normal(size=(M, K))
+        B = rng.normal(size=(K, N))
+        C = rng.normal(size=(M, N))
+        ref = 1.3 * A @ B - 0.5 * C
+        got = ctx.debug_gemm(A, B, C, alpha=1.3, beta=-0.5, prec="fp64", tile=3, a_kfast=True, b_nfast=bn)
+        scale = (1.3 * np.abs(A) @ np.abs(B) + 0.5 * np.abs(C)).max()
+        assert np.abs(got - ref).max() / scale < TOL["fp64"], (M, bn)
