@@ -203,7 +203,10 @@ int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops)
  * starts recording every expansion, GEMM and fold launch; fno_profile_report
  * writes a JSON text (per kernel name: launches, total_ms, algorithmic GEMM
  * flops, operand bytes; per term: the same for the GEMM) into buf (len bytes,
- * NUL-terminated, FNO_EINVAL if too small) and clears the records.
+ * NUL-terminated, FNO_EINVAL if too small) and clears the records.  A GEMM's
+ * name is its kernel followed by its shape, e.g.
+ * "fno::gemm_k4v_kernel<double, 128, 128, true, true> [590x76995x590]" (M x N x K),
+ * so terms that share an instantiation are reported apart.
  */
 /*
  * Diagnostics: with the environment variable FNO_TRACE set, the library
@@ -215,8 +218,8 @@ int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops)
 int fno_profile(fno_ctx *ctx, int on);
 int fno_profile_report(fno_ctx *ctx, char *buf, size_t len);
 /*
- * Restrict timing to the kernels whose name contains `substr` (NULL or "" =
- * all kernels).  With a filter set, the residual and sigma sweeps are still
+ * Restrict timing to the kernels whose name (with a GEMM's shape, as in
+ * fno_profile_report) contains `substr` (NULL or "" = all kernels).  With a filter set, the residual and sigma sweeps are still
  * replayed from hipGraphs: the selected GEMMs are bracketed by event-record
  * nodes inside the graph, read after every replay (in fno_ccsdt, where the
  * next sweep is enqueued before the host waits for the energy, after the

@@ -1147,9 +1147,13 @@ void Engine::execute(const Plan& p, double scale) {
   double factor = 1.0;
   bool a_kfast = p.a_kfast, b_nfast = p.b_nfast;
   int64_t lda = p.lda, ldb = p.ldb;
-  // rows of an expanded operand start on 16-element boundaries when the row
-  // kernel writes them (16-byte aligned rows let the GEMM use vector loads)
-  auto padded = [](bool tab_ok, int64_t cols) { return (tab_ok && cols >= 128) ? (cols + 15) / 16 * 16 : cols; };
+  // rows of a table-expanded operand start 16-byte aligned, so the GEMM can
+  // use vector loads: 16-element boundaries for wide rows, 4-element ones
+  // for rows of 16..127 (at most 19% padding); narrower rows stay packed
+  auto padded = [](bool tab_ok, int64_t cols) {
+    if (!tab_ok || cols < 16) return cols;
+    return cols >= 128 ? (cols + 15) / 16 * 16 : (cols + 3) / 4 * 4;
+  };
   auto expand_into = [&](const Tensor* t, bool tab_ok, const ExpandTab& tab, const OperandDesc& od, const MatDim& r,
                          const MatDim& c, void* hi, void* lo, int64_t ld) {
     const bool tm = timed(tab_ok ? "fno::expand_tab" : "fno::expand_kernel") && !rec_;
@@ -1288,7 +1292,10 @@ void Engine::execute(const Plan& p, double scale) {
       g.split = gemm_split_factor(g);
       if (g.split > 1) g.ws = workspace(5, gemm_split_bytes(g, g.split));
     }
-    const std::string label = gemm_label(g);
+    // the kernel and the GEMM's shape: launches of one instantiation on
+    // different terms are timed and reported apart
+    const std::string label = gemm_label(g) + " [" + std::to_string(Msz) + "x" + std::to_string(Nsz) + "x" +
+                              std::to_string(Ksz) + "]";
     const double b = (double)esz * (double)(Msz * Ksz + Ksz * Nsz) * (prec == Prec::BF16X3 ? 2 : 1) +
                      (prec == Prec::FP64 ? 8.0 : 4.0) * (double)(Msz * Nsz);
     if (!timed(label)) {

@@ -681,15 +681,16 @@ __global__ void __launch_bounds__(256) expand_tab_flat_kernel(ExpandTab t, const
       s *= t.tab_sign[m][k];
     }
     const double v = s ? s * src[o] : 0.0;
+    const int64_t d = r * t.ld + c;  // rows may be padded (t.ld >= t.cols)
     if (MODE == 0) {
-      ((double*)dst)[i] = v;
+      ((double*)dst)[d] = v;
     } else if (MODE == 1) {
-      ((float*)dst)[i] = (float)v;
+      ((float*)dst)[d] = (float)v;
     } else {
       const float x = (float)v;
       const __hip_bfloat16 h = __float2bfloat16(x);
-      ((__hip_bfloat16*)dst)[i] = h;
-      ((__hip_bfloat16*)dst_lo)[i] = __float2bfloat16(x - __bfloat162float(h));
+      ((__hip_bfloat16*)dst)[d] = h;
+      ((__hip_bfloat16*)dst_lo)[d] = __float2bfloat16(x - __bfloat162float(h));
     }
   }
 }
@@ -745,7 +746,7 @@ static void launch_expand_rows(int mode, int nm, dim3 grid, const ExpandTab& t, 
 
 void launch_expand_tab(const ExpandTab& t, const double* src, void* dst, void* dst_lo, Prec prec, hipStream_t s) {
   if (t.rows == 0 || t.cols == 0) return;
-  FNO_REQUIRE(t.ld == t.cols || t.cols >= 128, kEINVAL, "padded rows need the row kernel");
+  FNO_REQUIRE(t.ld >= t.cols, kEINVAL, "expansion row stride shorter than its rows");
   if (t.cols < 128) {
     const int64_t total = t.rows * t.cols;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
