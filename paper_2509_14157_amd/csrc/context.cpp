@@ -26,7 +26,9 @@ void Context::set_stream(hipStream_t s) {
   FNO_HIP(hipDeviceSynchronize());
   user_stream = s;
   eng->stream = s ? s : eng->own_stream();
+  // recordings remember the stream they were last launched on
   cc_prog_.clear();
+  if (eom_) eom_->prog.clear();
 }
 
 void Context::reset_engine(std::unique_ptr<Engine> e) {

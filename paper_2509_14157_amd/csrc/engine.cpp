@@ -184,6 +184,7 @@ void Engine::flush_timers(const Program& prog) {
 void Engine::replay(const Program& prog, bool defer) {
   // the event nodes are re-recorded by this replay: read the last one's first
   flush_timers(prog);
+  prog.launched = stream;
   for (auto& it : prog.items) FNO_HIP(hipGraphLaunch(it.exec, stream));
   if (!prog.timers.empty()) {
     prog.pending = true;

@@ -103,8 +103,15 @@ struct Program {
   int prec = -1;
   bool profiled = false;
   std::string filter;
+  // stream of the last replay: a replay may still run when the recording is
+  // dropped (the solvers launch the next sweep before they wait), and neither
+  // its executable graph nor the events its nodes record may be destroyed
+  // before it has finished
+  mutable hipStream_t launched = nullptr;
   bool valid() const { return !items.empty(); }
   void clear() {
+    if (launched && (!items.empty() || !timers.empty())) (void)hipStreamSynchronize(launched);
+    launched = nullptr;
     for (auto& it : items)
       if (it.exec) (void)hipGraphExecDestroy(it.exec);
     items.clear();
@@ -117,6 +124,9 @@ struct Program {
     }
     timers.clear();
   }
+  Program() = default;
+  Program(const Program&) = delete;
+  Program& operator=(const Program&) = delete;
   ~Program() { clear(); }
 };
 

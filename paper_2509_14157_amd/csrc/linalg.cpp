@@ -2,7 +2,8 @@
 //
 // * symmetric eigenproblem: cyclic Jacobi rotations (Golub & Van Loan, 8.5)
 // * nonsymmetric eigenvalues: Householder reduction to upper Hessenberg form
-//   followed by the Francis implicit double-shift QR iteration (GVL 7.5)
+//   (GVL Algorithm 7.4.2) followed by the Francis implicit double-shift QR
+//   iteration (GVL Algorithms 7.5.1 and 7.5.2)
 // * eigenvectors of selected eigenvalues: inverse iteration (real or complex shift)
 // * linear systems: Gaussian elimination with partial pivoting
 #include "linalg.hpp"
@@ -121,136 +122,175 @@ static void hessenberg(int n, std::vector<double>& a) {
   }
 }
 
-bool nonsym_eigvals(int n, std::vector<double> a, std::vector<double>& wr, std::vector<double>& wi) {
+// Eigenvalues of the 2 x 2 block [[a, b], [c, d]].
+static void eig2x2(double a, double b, double c, double d, double& r1, double& i1, double& r2, double& i2) {
+  const double mean = 0.5 * (a + d), half = 0.5 * (a - d);
+  const double disc = half * half + b * c;
+  if (disc >= 0) {
+    // the root of larger magnitude first, the other from the determinant
+    // (no cancellation between mean and the square root)
+    const double root = std::sqrt(disc);
+    const double big = mean + (mean >= 0 ? root : -root);
+    const double det = a * d - b * c;
+    r1 = big;
+    r2 = big != 0 ? det / big : mean - root;
+    i1 = i2 = 0;
+  } else {
+    r1 = r2 = mean;
+    i1 = std::sqrt(-disc);
+    i2 = -i1;
+  }
+}
+
+// Householder reflector P = I - beta v v^T with v[0] = 1 that maps x (length
+// 2 or 3) onto a multiple of e1; returns beta (0 when x is already e1-aligned).
+static double house(int len, const double* xin, double* v) {
+  // P does not depend on the scale of x: work with x / max|x_i|
+  double amax = 0, x[3];
+  for (int i = 0; i < len; ++i) amax = std::max(amax, std::fabs(xin[i]));
+  v[0] = 1;
+  for (int i = 1; i < len; ++i) v[i] = 0;
+  if (amax == 0) return 0;
+  for (int i = 0; i < len; ++i) x[i] = xin[i] / amax;
+  double sigma = 0;
+  for (int i = 1; i < len; ++i) sigma += x[i] * x[i];
+  for (int i = 1; i < len; ++i) v[i] = x[i];
+  if (sigma == 0) return 0;
+  const double mu = std::sqrt(x[0] * x[0] + sigma);
+  // v0 = x0 - mu, written without cancellation for x0 > 0
+  const double v0 = x[0] <= 0 ? x[0] - mu : -sigma / (x[0] + mu);
+  const double beta = 2 * v0 * v0 / (sigma + v0 * v0);
+  for (int i = 1; i < len; ++i) v[i] /= v0;
+  return beta;
+}
+
+// One Francis double-shift QR step (GVL Algorithm 7.5.1) on the unreduced
+// Hessenberg window lo..hi, with the shifts given by their sum s and product t.
+// Only the window is updated: eigenvalues need nothing outside it.
+static void francis_step(int n, std::vector<double>& a, int lo, int hi, double s, double t) {
+  auto H = [&](int i, int j) -> double& { return a[(size_t)i * n + j]; };
+  // first column of (H - s1 I)(H - s2 I) = H^2 - s H + t I, three entries
+  double x[3] = {H(lo, lo) * H(lo, lo) + H(lo, lo + 1) * H(lo + 1, lo) - s * H(lo, lo) + t,
+                 H(lo + 1, lo) * (H(lo, lo) + H(lo + 1, lo + 1) - s), H(lo + 1, lo) * H(lo + 2, lo + 1)};
+  double v[3];
+  for (int k = lo; k <= hi - 2; ++k) {
+    // chase the bulge: reflect rows/columns k..k+2
+    const double beta = house(3, x, v);
+    if (beta != 0) {
+      const int c0 = std::max(lo, k - 1);
+      for (int j = c0; j <= hi; ++j) {
+        const double w = beta * (H(k, j) + v[1] * H(k + 1, j) + v[2] * H(k + 2, j));
+        H(k, j) -= w;
+        H(k + 1, j) -= w * v[1];
+        H(k + 2, j) -= w * v[2];
+      }
+      const int r1 = std::min(k + 3, hi);
+      for (int i = lo; i <= r1; ++i) {
+        const double w = beta * (H(i, k) + v[1] * H(i, k + 1) + v[2] * H(i, k + 2));
+        H(i, k) -= w;
+        H(i, k + 1) -= w * v[1];
+        H(i, k + 2) -= w * v[2];
+      }
+    }
+    x[0] = H(k + 1, k);
+    x[1] = H(k + 2, k);
+    x[2] = k + 3 <= hi ? H(k + 3, k) : 0.0;
+  }
+  // the last reflector acts on two rows/columns
+  const double beta = house(2, x, v);
+  if (beta != 0) {
+    for (int j = hi - 2; j <= hi; ++j) {
+      if (j < lo) continue;
+      const double w = beta * (H(hi - 1, j) + v[1] * H(hi, j));
+      H(hi - 1, j) -= w;
+      H(hi, j) -= w * v[1];
+    }
+    for (int i = lo; i <= hi; ++i) {
+      const double w = beta * (H(i, hi - 1) + v[1] * H(i, hi));
+      H(i, hi - 1) -= w;
+      H(i, hi) -= w * v[1];
+    }
+  }
+  // the bulge chase leaves round-off below the subdiagonal: clear it
+  for (int i = lo + 2; i <= hi; ++i)
+    for (int j = lo; j < i - 1; ++j) H(i, j) = 0;
+}
+
+// Practical QR (GVL Algorithm 7.5.2): deflate at negligible subdiagonal
+// entries, read eigenvalues off 1 x 1 and 2 x 2 diagonal blocks, and apply
+// Francis steps to the trailing unreduced window.  Shifts are the eigenvalues
+// of the window's trailing 2 x 2 block; every tenth step without a split uses
+// a complex pair of modulus |h_nn| + |h_(n,n-1)| instead (a different angle
+// each time), which breaks the cycles the standard shifts can fall into
+// (e.g. on cyclic permutation matrices, where they are exactly zero).
+static bool nonsym_eigvals_unit(int n, std::vector<double>& a, std::vector<double>& wr, std::vector<double>& wi) {
   hessenberg(n, a);
   auto H = [&](int i, int j) -> double& { return a[(size_t)i * n + j]; };
   wr.assign(n, 0.0);
   wi.assign(n, 0.0);
-  double norm = 0;
-  for (int i = 0; i < n; ++i)
-    for (int j = std::max(i - 1, 0); j < n; ++j) norm += std::fabs(H(i, j));
-  int nn = n - 1;
-  double t = 0;
-  int total_its = 0;
-  while (nn >= 0) {
-    int its = 0, l;
-    do {
-      // look for a small subdiagonal element
-      for (l = nn; l >= 1; --l) {
-        double s = std::fabs(H(l - 1, l - 1)) + std::fabs(H(l, l));
-        if (s == 0) s = norm;
-        if (std::fabs(H(l, l - 1)) <= std::numeric_limits<double>::epsilon() * s) {
-          H(l, l - 1) = 0;
-          break;
-        }
+  const double eps = std::numeric_limits<double>::epsilon();
+  double anorm = 0;
+  for (double x : a) anorm = std::max(anorm, std::fabs(x));
+  int hi = n - 1, stuck = 0, steps = 0;
+  while (hi >= 0) {
+    // lo: start of the unreduced window that ends at hi
+    int lo = hi;
+    while (lo > 0) {
+      double scale = std::fabs(H(lo - 1, lo - 1)) + std::fabs(H(lo, lo));
+      if (scale == 0) scale = anorm;
+      if (std::fabs(H(lo, lo - 1)) <= eps * scale) {
+        H(lo, lo - 1) = 0;
+        break;
       }
-      double x = H(nn, nn);
-      if (l == nn) {  // one root
-        wr[nn] = x + t;
-        wi[nn] = 0;
-        --nn;
-      } else {
-        double y = H(nn - 1, nn - 1);
-        double w = H(nn, nn - 1) * H(nn - 1, nn);
-        if (l == nn - 1) {  // two roots
-          double p = 0.5 * (y - x);
-          double q = p * p + w;
-          double z = std::sqrt(std::fabs(q));
-          x += t;
-          if (q >= 0) {
-            z = p + (p >= 0 ? std::fabs(z) : -std::fabs(z));
-            wr[nn - 1] = wr[nn] = x + z;
-            if (z != 0) wr[nn] = x - w / z;
-            wi[nn - 1] = wi[nn] = 0;
-          } else {
-            wr[nn - 1] = wr[nn] = x + p;
-            wi[nn - 1] = -(wi[nn] = z);
-          }
-          nn -= 2;
-        } else {  // double-shift QR step on the active block l..nn
-          if (its == 60 || ++total_its > 100000) return false;
-          if (its == 10 || its == 20) {  // exceptional shift
-            t += x;
-            for (int i = 0; i <= nn; ++i) H(i, i) -= x;
-            double s = std::fabs(H(nn, nn - 1)) + std::fabs(H(nn - 1, nn - 2));
-            y = x = 0.75 * s;
-            w = -0.4375 * s * s;
-          }
-          ++its;
-          int m;
-          double p = 0, q = 0, r = 0, z;
-          for (m = nn - 2; m >= l; --m) {
-            z = H(m, m);
-            r = x - z;
-            double s = y - z;
-            p = (r * s - w) / H(m + 1, m) + H(m, m + 1);
-            q = H(m + 1, m + 1) - z - r - s;
-            r = H(m + 2, m + 1);
-            s = std::fabs(p) + std::fabs(q) + std::fabs(r);
-            p /= s;
-            q /= s;
-            r /= s;
-            if (m == l) break;
-            double u = std::fabs(H(m, m - 1)) * (std::fabs(q) + std::fabs(r));
-            double v = std::fabs(p) * (std::fabs(H(m - 1, m - 1)) + std::fabs(z) + std::fabs(H(m + 1, m + 1)));
-            if (u <= std::numeric_limits<double>::epsilon() * v) break;
-          }
-          for (int i = m; i < nn - 1; ++i) {
-            H(i + 2, i) = 0;
-            if (i != m) H(i + 2, i - 1) = 0;
-          }
-          for (int k = m; k < nn; ++k) {
-            if (k != m) {
-              p = H(k, k - 1);
-              q = H(k + 1, k - 1);
-              r = 0;
-              if (k != nn - 1) r = H(k + 2, k - 1);
-              if ((x = std::fabs(p) + std::fabs(q) + std::fabs(r)) != 0) {
-                p /= x;
-                q /= x;
-                r /= x;
-              }
-            }
-            double s = std::sqrt(p * p + q * q + r * r);
-            if (p < 0) s = -s;
-            if (s != 0) {
-              if (k == m) {
-                if (l != m) H(k, k - 1) = -H(k, k - 1);
-              } else {
-                H(k, k - 1) = -s * x;
-              }
-              p += s;
-              x = p / s;
-              y = q / s;
-              z = r / s;
-              q /= p;
-              r /= p;
-              for (int j = k; j <= nn; ++j) {
-                p = H(k, j) + q * H(k + 1, j);
-                if (k != nn - 1) {
-                  p += r * H(k + 2, j);
-                  H(k + 2, j) -= p * z;
-                }
-                H(k + 1, j) -= p * y;
-                H(k, j) -= p * x;
-              }
-              int mmin = nn < k + 3 ? nn : k + 3;
-              for (int i = l; i <= mmin; ++i) {
-                p = x * H(i, k) + y * H(i, k + 1);
-                if (k != nn - 1) {
-                  p += z * H(i, k + 2);
-                  H(i, k + 2) -= p * r;
-                }
-                H(i, k + 1) -= p * q;
-                H(i, k) -= p;
-              }
-            }
-          }
-        }
-      }
-    } while (l < nn - 1);
+      --lo;
+    }
+    if (lo == hi) {  // a 1 x 1 block
+      wr[hi] = H(hi, hi);
+      wi[hi] = 0;
+      hi -= 1;
+      stuck = 0;
+      continue;
+    }
+    if (lo == hi - 1) {  // a 2 x 2 block
+      eig2x2(H(hi - 1, hi - 1), H(hi - 1, hi), H(hi, hi - 1), H(hi, hi), wr[hi - 1], wi[hi - 1], wr[hi], wi[hi]);
+      hi -= 2;
+      stuck = 0;
+      continue;
+    }
+    if (++steps > 100 * n + 1000) return false;
+    ++stuck;
+    double s, t;
+    if (stuck % 10 == 0) {
+      // a complex pair of modulus |h_nn| + |h_(n,n-1)| at an angle that
+      // changes with every exceptional step
+      const double rho = std::fabs(H(hi, hi)) + std::fabs(H(hi, hi - 1));
+      const double angle = 1.1 + 0.37 * (stuck / 10);
+      s = 2 * rho * std::cos(angle);
+      t = rho * rho;
+    } else {
+      const double p = H(hi - 1, hi - 1), q = H(hi - 1, hi), r = H(hi, hi - 1), u = H(hi, hi);
+      s = p + u;
+      t = p * u - q * r;
+    }
+    francis_step(n, a, lo, hi, s, t);
   }
   return true;
+}
+
+bool nonsym_eigvals(int n, std::vector<double> a, std::vector<double>& wr, std::vector<double>& wi) {
+  // eigenvalues scale with the matrix: work at unit scale (no under- or
+  // overflow in the squares of the shift polynomial) and scale back
+  double amax = 0;
+  for (double x : a) amax = std::max(amax, std::fabs(x));
+  if (!std::isfinite(amax)) return false;
+  const double unit = amax > 0 ? amax : 1.0;
+  for (double& x : a) x /= unit;
+  const bool ok = nonsym_eigvals_unit(n, a, wr, wi);
+  for (int i = 0; i < (int)wr.size(); ++i) {
+    wr[i] *= unit;
+    wi[i] *= unit;
+  }
+  return ok;
 }
 
 void inverse_iteration(int n, const std::vector<double>& a, double lambda, std::vector<double>& x) {
