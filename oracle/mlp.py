@@ -127,9 +127,10 @@ def dressed_hamiltonian(fock, eri, nocc, t1):
 def dressed_diagonal(fock, eri, nocc, amps):
     """fo_i = f^_ii + 1/2 sum_{n,e,f} g^[i n e f] t_in^ef,
     fv_a = f^_aa - 1/2 sum_{m,n,f} g^[m n a f] t_mn^af (the one-body diagonal
-    of the triples equations at the given amplitudes).  The T2 terms are a
-    training target of the learned guess, not a quantity of the paper: parity
-    unpinned beyond the T1 part (pinned against determinants in the tests)."""
+    of the triples equations at the given amplitudes).  These are the diagonals
+    of the one-hole block (-fo) and the one-particle block (fv) of
+    e^{-T} H e^{T} - E_CC, pinned against the determinant model with T1 and T2
+    (and T3, which does not reach those blocks) in the tests."""
     o = nocc
     f, g = dressed_hamiltonian(fock, eri, o, amps[1])
     t2 = amps[2]
