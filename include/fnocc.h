@@ -243,6 +243,21 @@ int fno_profile_filter(fno_ctx *ctx, const char *substr);
 int fno_set_graphs(fno_ctx *ctx, int on);
 
 /*
+ * Ground-state triples residual path (on by default).  With on = 1 every term
+ * of the CCSDT triples projection (eq 5 on the triples; the pp-ladder, the
+ * hh-ladder, the ring, the one-body and the two T2 driver terms) runs through
+ * one fused pass per sweep: each occupied triple's products with the three
+ * occupied placements concatenated along K, computed by one MFMA GEMM whose
+ * operand tiles are gathered from packed T3/T2 into LDS, followed by one
+ * P(a/bc) fold into R3 and one occupied-only operator applied to packed T3.
+ * Used when 3 <= nvir <= 64 (after truncation) and nocc >= 3.  With on = 0,
+ * or outside those sizes, every term runs as its own expand / GEMM / fold
+ * sequence.  Both paths compute the same residual (to rounding); the EOM
+ * sigma vectors always use the per-term path.  Returns FNO_OK.
+ */
+int fno_set_fused(fno_ctx *ctx, int on);
+
+/*
  * GEMM tile autotuner (off by default).  With on = 1, the first host-launched
  * contraction GEMM of every (precision, M, N, K, operand layout) times each
  * MFMA tile configuration on a scratch output and keeps the fastest for that

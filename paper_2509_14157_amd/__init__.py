@@ -23,7 +23,7 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_profile_filter",
-           "fno_set_graphs", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
+           "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
            "fno_set_guess_model", "fno_last_guess_accepted", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
@@ -85,6 +85,7 @@ def library() -> C.CDLL:
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_set_graphs.argtypes = [C.c_void_p, C.c_int]
+        lib.fno_set_fused.argtypes = [C.c_void_p, C.c_int]
         lib.fno_set_autotune.argtypes = [C.c_void_p, C.c_int]
         fp = C.POINTER(C.c_float)
         lib.fno_mlp_num_params.argtypes = []
@@ -238,6 +239,10 @@ class Context:
     def set_autotune(self, on: bool = True) -> None:
         """Pick GEMM tiles per shape by timing every configuration on first use."""
         self._check(self._lib.fno_set_autotune(self._h, int(bool(on))))
+
+    def set_fused(self, on: bool = True) -> None:
+        """Ground-state triples residual through the fused per-triple pass (default) or per term."""
+        self._check(self._lib.fno_set_fused(self._h, int(bool(on))))
 
     def set_graphs(self, on: bool = True) -> None:
         """Replay the residual sweep from recorded hipGraphs (default) or launch eagerly."""

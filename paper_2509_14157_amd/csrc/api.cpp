@@ -351,6 +351,13 @@ int fno_set_autotune(fno_ctx* ctx, int on) {
   });
 }
 
+int fno_set_fused(fno_ctx* ctx, int on) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.fused_r3 = on != 0;
+    return FNO_OK;
+  });
+}
+
 int fno_set_graphs(fno_ctx* ctx, int on) {
   return guard(ctx, [&](fno::Context& c) {
     c.use_graphs = on != 0;

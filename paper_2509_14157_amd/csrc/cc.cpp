@@ -4,6 +4,7 @@
 #include <cstring>
 
 #include "context.hpp"
+#include "triples.hpp"
 #include "mlp.hpp"
 #include "linalg.hpp"
 
@@ -108,6 +109,13 @@ void Context::setup_cc() {
     FNO_HIP(hipMemcpy(e.get("Iocc")->d, Io.data(), Io.size() * sizeof(double), hipMemcpyHostToDevice));
   }
   make_views(e, kCCViews, count(kCCViews), o, v);
+  // fused triples residual: its buffers, and the packed-GEMM flops of the
+  // terms it replaces (the algorithmic count both paths report)
+  if (o >= 3 && v >= 3 && v <= 64) {
+    r3_y_ = alloc(r3_fused_y_elems(o, v));
+    r3_c_ = alloc((int64_t)binom_host(o, 3) * (int64_t)binom_host(o, 3));
+    r3_aring_ = alloc((int64_t)o * v * o * v);
+  }
   e.view("Xt_vo", e.get("Xt"), {{o, v}, {0, o}});
   e.view("Yt_vo", e.get("Yt"), {{o, v}, {0, o}});
   e.view("Gd_nono", Gd, {{0, n}, {0, o}, {0, n}, {0, o}});
@@ -133,6 +141,13 @@ void Context::setup_cc() {
     for (int s = 0; s < np; ++s) md.grp[1].letter[s] = (int8_t)(nh + s);
     md.size = md.grp[0].count * md.grp[1].count;
     launch_denominators(e.tables, md, nh, d_eo, d_ev, den_ + tblocks_[k].offset, e.stream);
+  }
+  r3_stats_.clear();
+  if (r3_y_) {
+    const Prec keep = e.prec;
+    e.prec = Prec::FP64;
+    for (const char* t : kCCR3) r3_stats_.push_back(e.term_shape(t));
+    e.prec = keep;
   }
   cc_ready = true;
 }
@@ -325,7 +340,10 @@ void Context::residual_body(Prec tri) {
     e.fork_mark();
     e.terms(kCCInter3, count(kCCInter3));
     e.prec = tri;
-    e.terms(kCCR3, count(kCCR3));
+    if (fused_r3_ok())
+      r3_fused(tri);
+    else
+      e.terms(kCCR3, count(kCCR3));
     e.prec = Prec::FP64;
     std::vector<const char*> late;
     e.begin_side();
@@ -339,6 +357,75 @@ void Context::residual_body(Prec tri) {
   e.prec = tri;
   e.record = false;
   tally_flops();
+}
+
+bool Context::fused_r3_ok() const {
+  return fused_r3 && nocc >= 3 && nvir >= 3 && nvir <= 64 && nocc <= eng->tables.dec_max_n[3] && r3_y_ != nullptr;
+}
+
+// The triples residual of kCCR3 in one pass (triples.hpp): the occupied-only
+// operator C from W3_oooo and F3_oo, the per-triple products Y_t of every
+// other term in one fused GEMM, the P(a/bc) fold of Y into R3, and
+// R3 += C T3.  The packed-GEMM flops of the replaced terms are recorded as
+// the per-term path would record them.
+void Context::r3_fused(Prec tri) {
+  Engine& e = *eng;
+  const int o = nocc, v = nvir;
+  const int nt = (int)binom_host(o, 3), nv3 = (int)binom_host(v, 3);
+  double* T3 = amp_ + tblocks_[2].offset;
+  double* R3 = res_ + tblocks_[2].offset;
+  const double bytes_t3 = 8.0 * (double)tblocks_[2].size;
+  e.timed_launch("fno::r3_ring_operand_kernel", "R3 fused: W3_ovvo rearranged", 0, 16.0 * o * v * o * v,
+                 [&]() { launch_r3_ring_operand(e.get("W3_ovvo")->d, o, v, r3_aring_, e.stream); });
+  e.timed_launch("fno::r3_occ_operator_kernel", "R3 fused: occupied operator", 0, 8.0 * nt * nt,
+                 [&]() { launch_r3_occ_operator(e.tables, o, e.get("W3_oooo")->d, e.get("F3_oo")->d, r3_c_,
+                                                e.stream); });
+  R3FusedArgs a;
+  a.o = o;
+  a.v = v;
+  a.T3 = T3;
+  a.T2 = amp_ + tblocks_[1].offset;
+  a.Wvvvv = e.get("W3_vvvv")->d;
+  a.Fvv = e.get("F3_vv")->d;
+  a.Aring = r3_aring_;
+  a.Wvvvo = e.get("W3_vvvo")->d;
+  a.Wovoo = e.get("W3_ovoo")->d;
+  a.Y = r3_y_;
+  a.ldy = r3_fused_ldy(v);
+  double fl = 0;
+  for (auto& st : r3_stats_)
+    if (st.term.find("W3_oooo") == std::string::npos && st.term.find("F3_oo") == std::string::npos) fl += st.flops;
+  const double ybytes = (tri == Prec::FP64 ? 8.0 : 4.0) * (double)r3_fused_y_elems(o, v);
+  e.timed_launch(tri == Prec::FP64 ? "fno::r3_fused_kernel<double>" : "fno::r3_fused_kernel<float>",
+                 "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, bytes_t3 + ybytes,
+                 [&]() { launch_r3_fused(e.tables, a, tri, e.stream); });
+  e.timed_launch("fno::r3_fold_kernel", "R3 fused: P(a/bc) fold", 0, 3.0 * ybytes / v + 2.0 * bytes_t3,
+                 [&]() { launch_r3_fold(e.tables, o, v, r3_y_, a.ldy, tri, R3, e.stream); });
+  // R3 += C T3 (FP64: a small GEMM on the packed rows)
+  GemmArgs g{};
+  g.prec = Prec::FP64;
+  g.M = nt;
+  g.N = nv3;
+  g.K = nt;
+  g.A = r3_c_;
+  g.lda = nt;
+  g.a_kfast = true;
+  g.B = T3;
+  g.ldb = nv3;
+  g.b_nfast = true;
+  g.C = R3;
+  g.ldc = nv3;
+  g.alpha = 1.0;
+  g.beta = 1.0;
+  g.tile = -1;
+  g.split = 1;
+  double flo = 0;
+  for (auto& st : r3_stats_)
+    if (st.term.find("W3_oooo") != std::string::npos || st.term.find("F3_oo") != std::string::npos) flo += st.flops;
+  e.timed_launch(gemm_label(g) + " [R3 += C T3]", "R3 fused: hh-ladder, F_oo", flo, 3.0 * bytes_t3,
+                 [&]() { launch_gemm(g, e.stream); });
+  if (e.record)
+    for (auto& st : r3_stats_) e.stats.push_back(st);
 }
 
 void Context::tally_flops() {

@@ -87,6 +87,9 @@ class Context {
 
   // launch mode: replay the residual sweep from a recorded hipGraph program
   bool use_graphs = true;
+  // ground-state triples residual through the fused per-triple kernel
+  // (triples.hpp); off: one expand / GEMM / fold sequence per term
+  bool fused_r3 = true;
   hipStream_t user_stream = nullptr;  // caller's stream (fno_set_stream), kept across engine rebuilds
   bool autotune = false;              // GEMM tile autotuner (fno_set_autotune), kept across engine rebuilds
   void set_stream(hipStream_t s);
@@ -109,6 +112,12 @@ class Context {
   // defer_timers: a replayed sweep's in-graph timers are read later
   void residual(bool defer_timers = false);
   void residual_body(Prec tri);
+  bool fused_r3_ok() const;
+  void r3_fused(Prec tri);
+  double* r3_y_ = nullptr;      // per-triple products Y_t (FP64-sized; FP32 modes use half)
+  double* r3_c_ = nullptr;      // occupied-only operator, C(o,3) x C(o,3)
+  double* r3_aring_ = nullptr;  // W3_ovvo rearranged for the ring segments
+  std::vector<GemmStats> r3_stats_;  // packed-GEMM flops of the replaced terms
   void plain_guess();
   double t3_rms(const double* x);
   void learned_t3(const double* x, double sx, double* t3, double* den3);

@@ -224,6 +224,33 @@ void Engine::prof_mark(const std::string& label, const std::string& spec, double
   prof_.push_back({label, spec, flops, bytes, a, b});
 }
 
+void Engine::timed_launch(const std::string& label, const std::string& spec, double flops, double bytes,
+                          const std::function<void()>& launch) {
+  if (!timed(label)) {
+    launch();
+    return;
+  }
+  if (rec_) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    FNO_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      throw Error(kEDEVICE, "hipEventCreate failed");
+    }
+    rec_->timers.push_back({label, spec, flops, bytes, e0, e1});
+    FNO_HIP(hipEventRecordWithFlags(e0, stream, hipEventRecordExternal));
+    launch();
+    FNO_HIP(hipEventRecordWithFlags(e1, stream, hipEventRecordExternal));
+    return;
+  }
+  hipEvent_t e0 = event();
+  FNO_HIP(hipEventRecord(e0, stream));
+  launch();
+  hipEvent_t e1 = event();
+  FNO_HIP(hipEventRecord(e1, stream));
+  prof_mark(label, spec, flops, bytes, e0, e1);
+}
+
 std::string Engine::profile_report() {
   FNO_HIP(hipStreamSynchronize(stream));
   if (side_stream_) FNO_HIP(hipStreamSynchronize(side_stream_));
@@ -775,6 +802,11 @@ CanonKey canon_key(const Tensor* t, const std::vector<int>& ids, const MatDim& r
 }
 
 }  // namespace
+
+GemmStats Engine::term_shape(const std::string& spec) {
+  auto p = plan(spec);
+  return {spec, p->M.size, p->N.size, p->K.size, p->flops};
+}
 
 std::shared_ptr<Engine::Plan> Engine::plan(const std::string& spec) {
   // zero-copy decisions depend on the precision: plans are cached per precision

@@ -161,6 +161,8 @@ class Engine {
 
   // --- terms
   void term(const std::string& spec, double scale = 1.0);
+  // the packed-GEMM shape and flops the term would run with (plans it, launches nothing)
+  GemmStats term_shape(const std::string& spec);
   void terms(const char* const* specs, int n, double scale = 1.0);
 
   // --- expansion cache
@@ -217,6 +219,10 @@ class Engine {
                  hipEvent_t b);
   hipEvent_t event();
   std::string profile_report();  // JSON aggregate per kernel label; clears the records
+  // Runs `launch` (kernels on `stream`), timed under `label` when profiling
+  // selects it: HIP events around it, or event-record nodes while recording.
+  void timed_launch(const std::string& label, const std::string& spec, double flops, double bytes,
+                    const std::function<void()>& launch);
 
   // workspace sizes (bytes) currently held
   size_t workspace_bytes() const {

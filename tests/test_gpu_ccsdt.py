@@ -50,6 +50,55 @@ def test_residual_matches_oracle(P, o, v, seed):
     assert abs(ec - cc.cc_energy(h.fock, h.eri, o, amps)) < 1e-12
 
 
+@pytest.mark.parametrize("o,v,seed", [(3, 3, 5), (4, 12, 1), (7, 24, 9), (8, 30, 6)])
+def test_fused_triples_residual_matches_oracle(P, o, v, seed):
+    """The fused triples pass (one per-triple GEMM with the occupied placements
+    along K, one P(a/bc) fold, one occupied-only operator) against the oracle,
+    elementwise, and against the per-term path.  (7, 24) and (8, 30) take
+    several column tiles with a ragged last one and ragged k tiles in every
+    K segment; (3, 3) is the smallest shape (one triple, three pairs)."""
+    print(f"fused R3 parity o={o} v={v} seed={seed}", flush=True)
+    h = make_hamiltonian(o, v, seed)
+    amps = random_amps(np.random.default_rng(seed), o, v)
+    with _ctx(P, h) as c:
+        _set(c, amps)
+        c.set_fused(True)
+        fused = c.cc_residual("fp64")
+        fused32 = c.cc_residual("fp32")
+        c.set_fused(False)
+        per_term = c.cc_residual("fp64")
+    R = cc.cc_residual(h.fock, h.eri, o, amps)
+    refs = (R[1].ravel(), pack(R[2], 2, 2), pack(R[3], 3, 3))
+    for got, alt, ref in zip(fused[:3], per_term[:3], refs):
+        scale = max(1.0, np.abs(ref).max())
+        assert np.abs(got - ref).max() < 1e-11 * scale
+        assert np.abs(got - alt).max() < 1e-12 * scale
+    # FP32 triples products (FP32 MFMA, FP32 accumulation over K <= 1000 here)
+    scale3 = max(1.0, np.abs(refs[2]).max())
+    assert np.abs(fused32[2] - refs[2]).max() < 2e-5 * scale3
+    assert abs(fused[3] - per_term[3]) < 1e-12
+
+
+@pytest.mark.parametrize("o,v", [(5, 64), (11, 20)])
+def test_fused_triples_residual_extremes(P, o, v):
+    """Largest virtual space the fused pass takes (v = 64: every row of the
+    64-row tile live, 16 column tiles) and a larger occupied space (165
+    triples), against the per-term path."""
+    print(f"fused R3 extremes o={o} v={v}", flush=True)
+    h = make_hamiltonian(o, v, 12)
+    rng = np.random.default_rng(2)
+    with _ctx(P, h) as c:
+        sizes = [math.comb(o, k) * math.comb(v, k) for k in (1, 2, 3)]
+        for k, n, sc in zip((1, 2, 3), sizes, (0.05, 0.02, 0.01)):
+            c.set_amplitudes(k, rng.normal(0, sc, n))
+        c.set_fused(True)
+        fused = c.cc_residual("fp64")
+        c.set_fused(False)
+        per_term = c.cc_residual("fp64")
+    for got, alt in zip(fused[:3], per_term[:3]):
+        assert np.abs(got - alt).max() < 1e-12 * max(1.0, np.abs(alt).max())
+
+
 def test_ccsdt_exact_for_three_electrons(P):
     h = make_hamiltonian(3, 5, 21)
     with _ctx(P, h) as c:
