@@ -397,7 +397,7 @@ def main():
     wrep = ctx.profile_report()
     ctx.profile(False)
     _log(f"[bench] warmup {warm} iterations done (host-launched, all kernels timed)")
-    gemms = [k for k in wrep["kernels"] if "gemm" in k["name"]]
+    gemms = [k for k in wrep["kernels"] if "gemm" in k["name"] or "r3_fused_kernel" in k["name"]]
     dom_name = max(gemms, key=lambda k: k["total_ms"])["name"]
 
     # timed region: graph replay of the residual sweep; only the dominant GEMM

@@ -114,7 +114,10 @@ void Context::setup_cc() {
   if (o >= 3 && v >= 3 && v <= 64) {
     r3_y_ = alloc(r3_fused_y_elems(o, v));
     r3_c_ = alloc((int64_t)binom_host(o, 3) * (int64_t)binom_host(o, 3));
-    r3_aring_ = alloc((int64_t)o * v * o * v);
+    r3_aring_ = alloc(r3_ring_operand_elems(o, v));
+    r3_t3v_ = alloc(r3_fused_t3v_elems(o, v));
+    r3_wt_ = alloc(r3_fused_wt_elems(v));
+    r3_fvvp_ = alloc(r3_fvv_padded_elems(v));
   }
   e.view("Xt_vo", e.get("Xt"), {{o, v}, {0, o}});
   e.view("Yt_vo", e.get("Yt"), {{o, v}, {0, o}});
@@ -375,8 +378,16 @@ void Context::r3_fused(Prec tri) {
   double* T3 = amp_ + tblocks_[2].offset;
   double* R3 = res_ + tblocks_[2].offset;
   const double bytes_t3 = 8.0 * (double)tblocks_[2].size;
+  const double esz = tri == Prec::FP64 ? 8.0 : 4.0;
+  e.timed_launch("fno::r3_t3v_kernel + r3_wt_kernel", "R3 fused: T3v and W3_vvvv^T", 0,
+                 bytes_t3 + esz * (double)(r3_fused_y_elems(o, v) + r3_fused_wt_elems(v)) +
+                     8.0 * (double)r3_fused_wt_elems(v),
+                 [&]() { launch_r3_operands(e.tables, o, v, T3, e.get("W3_vvvv")->d, r3_t3v_, r3_wt_, tri, e.stream); });
   e.timed_launch("fno::r3_ring_operand_kernel", "R3 fused: W3_ovvo rearranged", 0, 16.0 * o * v * o * v,
-                 [&]() { launch_r3_ring_operand(e.get("W3_ovvo")->d, o, v, r3_aring_, e.stream); });
+                 [&]() {
+                   launch_r3_ring_operand(e.get("W3_ovvo")->d, e.get("F3_vv")->d, o, v, r3_aring_, r3_fvvp_,
+                                          e.stream);
+                 });
   e.timed_launch("fno::r3_occ_operator_kernel", "R3 fused: occupied operator", 0, 8.0 * nt * nt,
                  [&]() { launch_r3_occ_operator(e.tables, o, e.get("W3_oooo")->d, e.get("F3_oo")->d, r3_c_,
                                                 e.stream); });
@@ -384,9 +395,11 @@ void Context::r3_fused(Prec tri) {
   a.o = o;
   a.v = v;
   a.T3 = T3;
+  a.T3v = r3_t3v_;
+  a.WT = r3_wt_;
   a.T2 = amp_ + tblocks_[1].offset;
   a.Wvvvv = e.get("W3_vvvv")->d;
-  a.Fvv = e.get("F3_vv")->d;
+  a.Fvvp = r3_fvvp_;
   a.Aring = r3_aring_;
   a.Wvvvo = e.get("W3_vvvo")->d;
   a.Wovoo = e.get("W3_ovoo")->d;
@@ -397,7 +410,7 @@ void Context::r3_fused(Prec tri) {
     if (st.term.find("W3_oooo") == std::string::npos && st.term.find("F3_oo") == std::string::npos) fl += st.flops;
   const double ybytes = (tri == Prec::FP64 ? 8.0 : 4.0) * (double)r3_fused_y_elems(o, v);
   e.timed_launch(tri == Prec::FP64 ? "fno::r3_fused_kernel<double>" : "fno::r3_fused_kernel<float>",
-                 "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, bytes_t3 + ybytes,
+                 "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, 2.0 * ybytes,
                  [&]() { launch_r3_fused(e.tables, a, tri, e.stream); });
   e.timed_launch("fno::r3_fold_kernel", "R3 fused: P(a/bc) fold", 0, 3.0 * ybytes / v + 2.0 * bytes_t3,
                  [&]() { launch_r3_fold(e.tables, o, v, r3_y_, a.ldy, tri, R3, e.stream); });

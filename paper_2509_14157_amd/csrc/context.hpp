@@ -117,6 +117,9 @@ class Context {
   double* r3_y_ = nullptr;      // per-triple products Y_t (FP64-sized; FP32 modes use half)
   double* r3_c_ = nullptr;      // occupied-only operator, C(o,3) x C(o,3)
   double* r3_aring_ = nullptr;  // W3_ovvo rearranged for the ring segments
+  double* r3_t3v_ = nullptr;    // T3 with one virtual letter unpacked (FP64-sized)
+  double* r3_wt_ = nullptr;     // W3_vvvv transposed (FP64-sized)
+  double* r3_fvvp_ = nullptr;   // F3_vv padded
   std::vector<GemmStats> r3_stats_;  // packed-GEMM flops of the replaced terms
   void plain_guess();
   double t3_rms(const double* x);

@@ -14,6 +14,7 @@
 #include "triples.hpp"
 
 #include <algorithm>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -68,39 +69,46 @@ struct Params {
   int nv2, nv3, no2, nt, ntn;  // C(v,2), C(v,3), C(o,2), C(o,3), N tiles per triple
   int kt_begin[kSegs + 1];     // first k tile of each segment
   int seg_k[kSegs];            // K of each segment
+  int ep;                      // padded e range of the ring segments (multiple of 16)
 };
 
+// Element mappings of the staged tiles (uniform per k tile):
+//   A: 0 = rows of 16-byte vectors along k (pp-ladder, rows of T3v),
+//      1 = one element per lane with k fastest, 2 = one element per lane with
+//      the row fastest (k uniform per wavefront)
+//   B: 0 = rows of 16-byte vectors along the columns (k uniform per vector
+//      row: W3_vvvv^T, T3v), 1 = one element per lane, column fastest
 template <typename T>
 __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
-  constexpr int PAD = (sizeof(T) == 8) ? 1 : 2;
-  __shared__ T As[2][kBK][kBM + PAD];
-  __shared__ T Bs[2][kBK][kBN + PAD];
+  constexpr int VW = 16 / sizeof(T);          // elements per 16-byte vector
+  constexpr int AV = kBM * kBK / VW / kThreads;  // A vectors per thread
+  constexpr int BV = kBK * kBN / VW / kThreads;  // B vectors per thread
+  constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;  // keeps B rows 16-byte aligned
+  typedef T Vec __attribute__((ext_vector_type(VW)));
+  static_assert(AV * VW == 4 && BV * VW == 8, "slot counts");
+  __shared__ T As[2][kBK][kBM + 1];
+  __shared__ __attribute__((aligned(16))) T Bs[2][kBK][kBN + PAD];
   const R3FusedArgs& g = P.a;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // tiles: triple fast within an XCD's contiguous range, so consecutive
-  // tiles of one XCD share the column strip of W3_vvvv in its L2
+  // tiles: the column tiles of one triple are consecutive within an XCD's
+  // contiguous range; they run together and walk K in near lockstep, so the
+  // triple's T3v rows, the k slab of W3_vvvv^T and the ring's T3v rows are
+  // shared through the XCD's L2
   int64_t L;
   {
     const int64_t n = gridDim.x, b = blockIdx.x, q = n / 8, r = n % 8, x = b % 8, k = b / 8;
     L = x * q + (x < r ? x : r) + k;
   }
-  const int t = (int)(L % P.nt);
-  const int n0 = (int)(L / P.nt) * kBN;
-  const int v = g.v, o = g.o, nv2 = P.nv2, nv3 = P.nv3;
+  const int t = (int)(L / P.ntn);
+  const int n0 = (int)(L % P.ntn) * kBN;
+  const int v = g.v, o = g.o, nv2 = P.nv2;
+  const int64_t ldy = g.ldy;
   const uint8_t* d3 = P.tb.dec[3] + 3 * t;
   const int tt[3] = {d3[0], d3[1], d3[2]};
-  const double* T3t = g.T3 + (int64_t)t * nv3;
-
-  // this thread's column for the column-fast B tiles: its (b, c) stay in registers
-  const int ncol = tid & (kBN - 1);
-  const int col = n0 + ncol;
-  const bool col_ok = col < nv2;
-  int cb = 0, cc = 1;
-  if (col_ok) {
-    cb = P.tb.dec[2][2 * col];
-    cc = P.tb.dec[2][2 * col + 1];
-  }
+  const T* T3v = (const T*)g.T3v;
+  const T* T3vt = T3v + (int64_t)t * v * ldy;
+  const T* WT = (const T*)g.WT;
 
   typename AccT<T>::type acc[2][4];
 #pragma unroll
@@ -108,8 +116,11 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = (typename AccT<T>::type){0, 0, 0, 0};
 
-  T ra[4], rb[8];
-  bool a_kfast = false, b_kfast = false;  // element mapping of the tile in registers
+  // a staged k tile in registers and the element mappings it was loaded with
+  struct Regs {
+    T a[4], b[8];
+    int amode, bmode;
+  };
 
   // placement p of the triple: x = t_p, pair (q0 < q1) = the other two
   auto placement = [&](int p, int& x, int& q0, int& q1) {
@@ -117,92 +128,75 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
     q0 = tt[p == 0 ? 1 : 0];
     q1 = tt[p == 2 ? 1 : 2];
   };
+  // Unguarded row loads for the hot segments: every buffer they read is
+  // padded so that rows a >= v, rows e >= v, columns >= C(v,2) and k beyond
+  // the segment stay inside the allocation.  Those elements meet zeros in
+  // the other operand (k) or land in accumulator rows / columns that are
+  // never stored (a, bc).
+  // A[a][kk] = scale * abase[a * lda + kk] (16 values per row)
+  auto load_a_rows = [&](Regs& R, const auto* abase, int64_t lda, T scale) {
+    typedef std::remove_cv_t<std::remove_pointer_t<decltype(abase)>> S;
+    constexpr int SW = 16 / sizeof(S);
+    typedef S SVec __attribute__((ext_vector_type(SW)));
+    R.amode = 0;
+#pragma unroll
+    for (int i = 0; i < AV; ++i) {
+      const int q = tid + kThreads * i;
+      const int a = q / (kBK / VW), kv = (q % (kBK / VW)) * VW;
+      const SVec* src = (const SVec*)(abase + a * lda + kv);
+#pragma unroll
+      for (int h = 0; h < VW / SW; ++h) {
+        const SVec y = src[h];
+#pragma unroll
+        for (int j = 0; j < SW; ++j) R.a[i * VW + h * SW + j] = scale * (T)y[j];
+      }
+    }
+  };
+  // B[kk][n] = scale * bbase[kk * ldb + n]  (bbase already at column n0)
+  auto load_b_rows = [&](Regs& R, const T* bbase, int64_t ldb, T scale) {
+    R.bmode = 0;
+#pragma unroll
+    for (int i = 0; i < BV; ++i) {
+      const int q = tid + kThreads * i;
+      const int kk = q / (kBN / VW), nv = (q % (kBN / VW)) * VW;
+      const Vec y = *(const Vec*)(bbase + kk * ldb + nv);
+#pragma unroll
+      for (int j = 0; j < VW; ++j) R.b[i * VW + j] = scale * y[j];
+    }
+  };
 
-  auto load_tile = [&](int kt) {
+  auto load_tile = [&](int kt, Regs& R) {
     int s = 0;
 #pragma unroll
     for (int q = 1; q < kSegs; ++q) s += (kt >= P.kt_begin[q]) ? 1 : 0;
     const int k0 = (kt - P.kt_begin[s]) * kBK;
     const int K = P.seg_k[s];
     if (s == 0) {
-      // pp-ladder: A[a, ef] = T3[t, a e f], lanes over a, k uniform per wave
-      a_kfast = false;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int kk = wave + 4 * i, a = lane, k = k0 + kk;
-        double val = 0;
-        if (k < K && a < v) {
-          const int e = P.tb.dec[2][2 * k], f = P.tb.dec[2][2 * k + 1];
-          int sg;
-          const int r = tri_rank(a, e, f, sg);
-          if (sg) val = sg * T3t[r];
-        }
-        ra[i] = (T)val;
-      }
-      // B[ef, bc] = W3_vvvv[bc][ef]: k fastest in memory, 16-element runs
-      b_kfast = true;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int kk = tid & 15, nn = (tid >> 4) + 16 * i, k = k0 + kk, c = n0 + nn;
-        rb[i] = (T)((k < K && c < nv2) ? g.Wvvvv[(int64_t)c * nv2 + k] : 0.0);
-      }
+      // pp-ladder: A[a, ef] = T3v[t][a][ef], B[ef, bc] = W3_vvvv^T[ef][bc]
+      load_a_rows(R, T3vt + k0, ldy, (T)1);
+      load_b_rows(R, WT + (int64_t)k0 * ldy + n0, ldy, (T)1);
     } else if (s == 1) {
-      // one-body: A[a, e] = F3_vv[a][e], B[e, bc] = T3[t, e b c]
-      a_kfast = true;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int kk = tid & 15, a = (tid >> 4) + 16 * i, k = k0 + kk;
-        ra[i] = (T)((k < K && a < v) ? g.Fvv[a * v + k] : 0.0);
-      }
-      b_kfast = false;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i;
-        double val = 0;
-        if (k < K && col_ok) {
-          int sg;
-          const int r = tri_rank(k, cb, cc, sg);
-          if (sg) val = sg * T3t[r];
-        }
-        rb[i] = (T)val;
-      }
+      // one-body: A[a, e] = F3_vv[a][e] (rows padded to ep), B[e, bc] = T3v[t][e][bc]
+      load_a_rows(R, g.Fvvp + k0, P.ep, (T)1);
+      load_b_rows(R, T3vt + (int64_t)k0 * ldy + n0, ldy, (T)1);
     } else if (s <= 4) {
-      // ring, placement p: k = m' v + e over the o - 2 occupied m outside the pair
+      // ring, placement p: the k tiles walk m' (the o - 2 occupied m outside
+      // the pair) and, for each, e in steps of 16 over the padded range ep;
+      // A[a, e] = (-1)^p W3_ovvo[m][a][e][x], B[e, bc] = +-T3[m pair, e b c]
       const int p = s - 2;
       int x, q0, q1;
       placement(p, x, q0, q1);
-      const double sp = (p & 1) ? -1.0 : 1.0;
-      a_kfast = true;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int kk = tid & 15, a = (tid >> 4) + 16 * i, k = k0 + kk;
-        double val = 0;
-        if (k < K && a < v) {
-          int m = k / v;
-          const int e = k - m * v;
-          m += (m >= q0) ? 1 : 0;
-          m += (m >= q1) ? 1 : 0;
-          val = sp * g.Aring[(((int64_t)x * v + a) * o + m) * v + e];
-        }
-        ra[i] = (T)val;
-      }
-      b_kfast = false;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i;  // uniform per wavefront
-        double val = 0;
-        if (k < K && col_ok) {
-          int m = k / v;
-          const int e = k - m * v;
-          m += (m >= q0) ? 1 : 0;
-          m += (m >= q1) ? 1 : 0;
-          int so, sv;
-          const int ro = tri_rank(m, q0, q1, so);
-          const int rv = tri_rank(e, cb, cc, sv);
-          if (sv) val = (so * sv) * g.T3[(int64_t)ro * nv3 + rv];
-        }
-        rb[i] = (T)val;
-      }
+      const int ltile = kt - P.kt_begin[s], per_m = P.ep / kBK;
+      int m = ltile / per_m;
+      const int e0 = (ltile - m * per_m) * kBK;
+      m += (m >= q0) ? 1 : 0;
+      m += (m >= q1) ? 1 : 0;
+      int so;
+      const int ro = tri_rank(m, q0, q1, so);
+      const T sg = (T)(((p & 1) ? -1 : 1) * so);
+      load_a_rows(R, g.Aring + ((int64_t)x * v * o + m) * P.ep + e0, (int64_t)o * P.ep, sg);
+      load_b_rows(R, T3v + ((int64_t)ro * v + e0) * ldy + n0, ldy, (T)1);
+      (void)K;
     } else if (s <= 7) {
       // driver: A[a, e] = (-1)^p T2[pair, a e], B[e, bc] = W3_vvvo[x][e][bc]
       const int p = s - 5;
@@ -210,21 +204,19 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       placement(p, x, q0, q1);
       const double sp = (p & 1) ? -1.0 : 1.0;
       const double* t2row = g.T2 + (int64_t)(q0 + cb2(q1)) * nv2;
-      a_kfast = false;
+      R.amode = 2;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int kk = wave + 4 * i, a = lane, k = k0 + kk;
         double val = 0;
-        if (k < K && a < v && a != k) {
-          val = a < k ? sp * t2row[a + cb2(k)] : -sp * t2row[k + cb2(a)];
-        }
-        ra[i] = (T)val;
+        if (k < K && a < v && a != k) val = a < k ? sp * t2row[a + cb2(k)] : -sp * t2row[k + cb2(a)];
+        R.a[i] = (T)val;
       }
-      b_kfast = false;
+      R.bmode = 1;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i;
-        rb[i] = (T)((k < K && col_ok) ? g.Wvvvo[((int64_t)x * v + k) * nv2 + col] : 0.0);
+        const int k = k0 + (tid >> 7) + 2 * i, c = n0 + (tid & (kBN - 1));
+        R.b[i] = (T)((k < K && c < nv2) ? g.Wvvvo[((int64_t)x * v + k) * nv2 + c] : 0.0);
       }
     } else {
       // driver: A[a, m] = -(-1)^p W3_ovoo[m][a][pair], B[m, bc] = T2[x m, bc]
@@ -233,52 +225,61 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       placement(p, x, q0, q1);
       const double sp = (p & 1) ? 1.0 : -1.0;
       const int pr = q0 + cb2(q1);
-      a_kfast = false;
+      R.amode = 2;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int kk = wave + 4 * i, a = lane, k = k0 + kk;
-        ra[i] = (T)((k < K && a < v) ? sp * g.Wovoo[((int64_t)k * v + a) * P.no2 + pr] : 0.0);
+        R.a[i] = (T)((k < K && a < v) ? sp * g.Wovoo[((int64_t)k * v + a) * P.no2 + pr] : 0.0);
       }
-      b_kfast = false;
+      R.bmode = 1;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i;
+        const int k = k0 + (tid >> 7) + 2 * i, c = n0 + (tid & (kBN - 1));
         double val = 0;
-        if (k < K && col_ok && k != x) {
+        if (k < K && c < nv2 && k != x) {
           const int lo = k < x ? k : x, hi = k < x ? x : k;
           const double sg = k < x ? -1.0 : 1.0;  // (x, m) sorted
-          val = sg * g.T2[(int64_t)(lo + cb2(hi)) * nv2 + col];
+          val = sg * g.T2[(int64_t)(lo + cb2(hi)) * nv2 + c];
         }
-        rb[i] = (T)val;
+        R.b[i] = (T)val;
       }
     }
   };
 
-  auto store_tile = [&](int st) {
+  auto store_tile = [&](int st, const Regs& R) {
+    if (R.amode == 0) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      if (a_kfast)
-        As[st][tid & 15][(tid >> 4) + 16 * i] = ra[i];
-      else
-        As[st][wave + 4 * i][lane] = ra[i];
+      for (int i = 0; i < AV; ++i) {
+        const int q = tid + kThreads * i;
+        const int a = q / (kBK / VW), kv = (q % (kBK / VW)) * VW;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) As[st][kv + j][a] = R.a[i * VW + j];
+      }
+    } else if (R.amode == 1) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) As[st][tid & 15][(tid >> 4) + 16 * i] = R.a[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) As[st][wave + 4 * i][lane] = R.a[i];
     }
+    if (R.bmode == 0) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      if (b_kfast)
-        Bs[st][tid & 15][(tid >> 4) + 16 * i] = rb[i];
-      else
-        Bs[st][(tid >> 7) + 2 * i][tid & (kBN - 1)] = rb[i];
+      for (int i = 0; i < BV; ++i) {
+        const int q = tid + kThreads * i;
+        const int kk = q / (kBN / VW), nv = (q % (kBN / VW)) * VW;
+        Vec x;
+#pragma unroll
+        for (int j = 0; j < VW; ++j) x[j] = R.b[i * VW + j];
+        *(Vec*)&Bs[st][kk][nv] = x;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[st][(tid >> 7) + 2 * i][tid & (kBN - 1)] = R.b[i];
     }
   };
 
   const int nk = P.kt_begin[kSegs];
-  load_tile(0);
-  store_tile(0);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) load_tile(kt + 1);
+  auto mma_stage = [&](int cur) {
 #pragma unroll
     for (int ks = 0; ks < kBK; ks += 4) {
       const int kr = ks + (lane >> 4);
@@ -292,13 +293,25 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[i], bf[j], acc[i][j]);
     }
-    if (more) store_tile(cur ^ 1);
+  };
+  // one k tile in flight: the loads of tile kt + 1 are issued before the
+  // MFMAs of tile kt and stored to the other LDS stage after them
+  Regs R;
+  load_tile(0, R);
+  store_tile(0, R);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) load_tile(kt + 1, R);
+    mma_stage(cur);
+    if (more) store_tile(cur ^ 1, R);
     __syncthreads();
   }
 
   // C/D layout of the 16x16 block: lane l holds column l % 16; FP64 rows
   // l / 16 + 4 r, FP32 rows 4 (l / 16) + r
-  T* Y = (T*)g.Y + (int64_t)t * v * g.ldy;
+  T* Y = (T*)g.Y + (int64_t)t * v * ldy;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -308,9 +321,50 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       for (int r = 0; r < 4; ++r) {
         const int rr = (sizeof(T) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
         const int a = wm * 32 + i * 16 + rr;
-        if (a < v && c < nv2) Y[(int64_t)a * g.ldy + c] = acc[i][j][r];
+        if (a < v && c < nv2) Y[(int64_t)a * ldy + c] = acc[i][j][r];
       }
     }
+}
+
+// T3v[t][x][p] = T3[t, x, p0, p1] (p = pair p0 < p1; zero for x in the pair
+// and for p >= C(v,2)): a thread per element, pairs fastest
+template <typename T>
+__global__ void __launch_bounds__(256) r3_t3v_kernel(IndexTables tb, int v, int nv2, int nv3, int64_t ldy,
+                                                     int64_t rows, int64_t rows_all, const double* __restrict__ T3,
+                                                     T* __restrict__ T3v) {
+  const int64_t blk_per_row = (ldy + 255) / 256;
+  const int64_t row = blockIdx.x / blk_per_row;  // (t, x); rows >= `rows` are padding
+  const int64_t p = (blockIdx.x % blk_per_row) * 256 + threadIdx.x;
+  if (row >= rows_all || p >= ldy) return;
+  const int t = (int)(row / v), x = (int)(row % v);
+  double val = 0;
+  if (row < rows && p < nv2) {
+    const int p0 = tb.dec[2][2 * p], p1 = tb.dec[2][2 * p + 1];
+    int sg;
+    const int r = tri_rank(x, p0, p1, sg);
+    if (sg) val = sg * T3[(int64_t)t * nv3 + r];
+  }
+  T3v[row * ldy + p] = (T)val;
+}
+
+// WT[ef][bc] = W[bc][ef] (square C(v,2) matrix, rows of WT padded to ldy with
+// zeros), through 32 x 32 LDS tiles
+template <typename T>
+__global__ void __launch_bounds__(256) r3_wt_kernel(int n, int64_t ldy, int64_t rows_all, const double* __restrict__ W,
+                                                    T* __restrict__ WT) {
+  __shared__ double tile[32][33];
+  const int tiles = (int)((ldy + 31) / 32);
+  const int bi = blockIdx.x / tiles, bj = blockIdx.x % tiles;  // WT rows bi (ef), columns bj (bc)
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int bc = bj * 32 + r, ef = bi * 32 + tx;
+    tile[r][tx] = (bc < n && ef < n) ? W[(int64_t)bc * n + ef] : 0.0;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t ef = bi * 32 + r, bc = bj * 32 + tx;
+    if (ef < rows_all && bc < ldy) WT[ef * ldy + bc] = (T)tile[tx][r];
+  }
 }
 
 // R3[t, abc] += Y_t[a, bc] - Y_t[b, ac] + Y_t[c, ab]; a thread per output,
@@ -334,19 +388,22 @@ __global__ void __launch_bounds__(256) r3_fold_kernel(IndexTables tb, int v, int
   R3[(int64_t)t * nv3 + u] += z;
 }
 
-__global__ void __launch_bounds__(256) r3_ring_operand_kernel(const double* __restrict__ W, int o, int v,
+__global__ void __launch_bounds__(256) r3_ring_operand_kernel(const double* __restrict__ W, int o, int v, int ep,
                                                               double* __restrict__ A) {
-  // A[x][a][m][e] = W[m][a][e][x]; a thread per element of A
-  const int64_t n = (int64_t)o * v * o * v;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const int e = (int)(i % v);
-    int64_t r = i / v;
-    const int m = (int)(r % o);
-    r /= o;
-    const int a = (int)(r % v);
-    const int x = (int)(r / v);
-    A[i] = W[(((int64_t)m * v + a) * v + e) * o + x];
+  // A[x][a][m][e] = W[m][a][e][x] (e < v; zero for v <= e < ep): a block
+  // per (x, a), a thread per (m, e)
+  const int x = blockIdx.x / v, a = blockIdx.x % v;
+  double* dst = A + ((int64_t)x * v + a) * o * ep;
+  for (int q = threadIdx.x; q < o * ep; q += blockDim.x) {
+    const int m = q / ep, e = q % ep;
+    dst[q] = e < v ? W[(((int64_t)m * v + a) * v + e) * o + x] : 0.0;
   }
+}
+
+// Fvvp[a][e] = F3_vv[a][e] for a, e < v, zero elsewhere (kBM rows of ep)
+__global__ void r3_fvv_pad_kernel(const double* __restrict__ F, int v, int ep, double* __restrict__ Fp) {
+  const int a = blockIdx.x;
+  for (int e = threadIdx.x; e < ep; e += blockDim.x) Fp[a * ep + e] = (a < v && e < v) ? F[a * v + e] : 0.0;
 }
 
 // C[t][t'] = sum_p (-1)^p [ W3_oooo[(t' \ x_p)][pair_p] s1 - F3_oo[t' \ pair_p][x_p] s2 ]
@@ -402,7 +459,8 @@ Params make_params(const IndexTables& tb, const R3FusedArgs& a) {
   P.no2 = (int)binom_host(o, 2);
   P.nt = (int)binom_host(o, 3);
   P.ntn = ceil_div(P.nv2, kBN);
-  const int ks[kSegs] = {P.nv2, v, (o - 2) * v, (o - 2) * v, (o - 2) * v, v, v, v, o, o, o};
+  P.ep = (v + kBK - 1) / kBK * kBK;
+  const int ks[kSegs] = {P.nv2, v, (o - 2) * P.ep, (o - 2) * P.ep, (o - 2) * P.ep, v, v, v, o, o, o};
   int kt = 0;
   for (int s = 0; s < kSegs; ++s) {
     P.seg_k[s] = ks[s];
@@ -417,10 +475,23 @@ Params make_params(const IndexTables& tb, const R3FusedArgs& a) {
 
 int64_t r3_fused_ldy(int v) {
   const int64_t nv2 = (int64_t)binom_host(v, 2);
-  return (nv2 + 3) / 4 * 4;
+  return (nv2 + kBK - 1) / kBK * kBK;
 }
 
+// the fused kernel reads past the last triple's rows (rows a or e up to 63)
+// and past the last row's end (columns up to the last 128-column tile):
+// whole padding rows after the data, all written (zeros) by the operand
+// kernels in the compute type, so that they hold finite values whatever
+// precision last used the buffer
+static int64_t pad_rows(int v) { return kBM + (2 * kBN + r3_fused_ldy(v) - 1) / r3_fused_ldy(v); }
+
+int64_t r3_fused_t3v_elems(int o, int v) { return r3_fused_y_elems(o, v) + pad_rows(v) * r3_fused_ldy(v); }
+
 int64_t r3_fused_y_elems(int o, int v) { return (int64_t)binom_host(o, 3) * v * r3_fused_ldy(v); }
+
+int64_t r3_fused_wt_elems(int v) { return (r3_fused_ldy(v) + pad_rows(v)) * r3_fused_ldy(v); }
+
+int64_t r3_fvv_padded_elems(int v) { return (int64_t)kBM * ((v + kBK - 1) / kBK * kBK); }
 
 double r3_fused_executed_flops(int o, int v) {
   IndexTables tb{};
@@ -435,7 +506,8 @@ void launch_r3_fused(const IndexTables& tb, const R3FusedArgs& a, Prec prec, hip
   FNO_REQUIRE(a.o >= 3 && a.v >= 3 && a.v <= kBM, kEINVAL, "fused triples residual needs 3 <= o, 3 <= v <= 64");
   FNO_REQUIRE(a.o <= tb.dec_max_n[3] && a.v <= tb.dec_max_n[3] && a.v <= tb.dec_max_n[2], kEINVAL,
               "index tables too small for the fused triples residual");
-  FNO_REQUIRE(a.ldy >= (int64_t)binom_host(a.v, 2), kEINVAL, "bad Y leading dimension");
+  FNO_REQUIRE(a.ldy == r3_fused_ldy(a.v), kEINVAL, "bad Y leading dimension");
+  FNO_REQUIRE(a.T3v && a.WT && a.Y, kEINVAL, "fused triples residual: missing buffers");
   const Params P = make_params(tb, a);
   const int64_t tiles = (int64_t)P.nt * P.ntn;
   FNO_REQUIRE(tiles < (1ll << 31), kEINVAL, "too many tiles");
@@ -459,10 +531,35 @@ void launch_r3_fold(const IndexTables& tb, int o, int v, const void* Y, int64_t 
   FNO_HIP(hipGetLastError());
 }
 
-void launch_r3_ring_operand(const double* Wovvo, int o, int v, double* Aring, hipStream_t s) {
-  const int64_t n = (int64_t)o * v * o * v;
-  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
-  r3_ring_operand_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(Wovvo, o, v, Aring);
+int64_t r3_ring_operand_elems(int o, int v) {
+  const int64_t ep = (v + kBK - 1) / kBK * kBK;
+  return ((int64_t)o * v + kBM) * o * ep;
+}
+
+void launch_r3_ring_operand(const double* Wovvo, const double* Fvv, int o, int v, double* Aring, double* Fvvp,
+                            hipStream_t s) {
+  const int ep = (v + kBK - 1) / kBK * kBK;
+  r3_ring_operand_kernel<<<dim3((unsigned)(o * v)), 256, 0, s>>>(Wovvo, o, v, ep, Aring);
+  r3_fvv_pad_kernel<<<dim3(kBM), 64, 0, s>>>(Fvv, v, ep, Fvvp);
+  FNO_HIP(hipGetLastError());
+}
+
+void launch_r3_operands(const IndexTables& tb, int o, int v, const double* T3, const double* Wvvvv, void* T3v,
+                        void* WT, Prec prec, hipStream_t s) {
+  const int nv2 = (int)binom_host(v, 2), nv3 = (int)binom_host(v, 3);
+  const int64_t ldy = r3_fused_ldy(v), rows = (int64_t)binom_host(o, 3) * v;
+  const int64_t rows_all = r3_fused_t3v_elems(o, v) / ldy, wrows_all = r3_fused_wt_elems(v) / ldy;
+  const int64_t blocks = rows_all * ((ldy + 255) / 256);
+  const int64_t tiles = (ldy + 31) / 32, wblocks = ((wrows_all + 31) / 32) * tiles;
+  if (prec == Prec::FP64) {
+    r3_t3v_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
+                                                                 (double*)T3v);
+    r3_wt_kernel<double><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (double*)WT);
+  } else {
+    r3_t3v_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
+                                                                (float*)T3v);
+    r3_wt_kernel<float><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (float*)WT);
+  }
   FNO_HIP(hipGetLastError());
 }
 
