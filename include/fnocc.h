@@ -99,6 +99,12 @@ void fno_cc_opts_default(fno_cc_opts *o);
  * Ground-state CCSDT (eqs 5-7) in the current (possibly truncated) space.
  *   e_corr, e_tot: correlation and total energy (e_tot = E_ref + e_corr + e_nuc).
  *   iters, res_norm: iterations used and final residual norm.
+ * Converged: res_norm < r_tol and |Delta E| < e_tol.  With FP32 or split-BF16
+ * triples products the residual has a floor set by the products' rounding
+ * (about 2e-7 for FP32 and 1e-5 for split-BF16 at o=10, v=59); such a solve
+ * has also converged when |Delta E| < e_tol, res_norm < 100 r_tol and the
+ * last four residual norms lie within 25% of each other (res_norm then
+ * reports the floor; fno_last_trace gives the history).
  * Returns FNO_ENOCONV (results still written) when max_iter is reached.
  */
 int fno_ccsdt(fno_ctx *ctx, const fno_cc_opts *opts, double *e_corr, double *e_tot, int *iters, double *res_norm);
@@ -186,6 +192,15 @@ int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *
  * solve after fno_eom / fno_batch_eom (per context). */
 int fno_last_flops(const fno_ctx *ctx, double *triples_flops, double *all_flops);
 
+/* Convergence history of the last fno_ccsdt call: for each iteration k
+ * (k < *n), energies[k] = E_corr after the update of iteration k+1 and
+ * res_norms[k] = the Euclidean norm of that iteration's residual over the
+ * unique amplitudes (the quantities the stopping test of fno_ccsdt uses).
+ * At most cap entries are written; *n receives the number of iterations
+ * recorded.  Either array may be NULL.  Host arrays, caller-owned.
+ * Returns FNO_OK, or FNO_EINVAL for a null context or n. */
+int fno_last_trace(const fno_ctx *ctx, double *energies, double *res_norms, int cap, int *n);
+
 /*
  * Diagnostics.
  * fno_debug_tensor copies the whole storage (packed layout, FP64) of the named
@@ -250,8 +265,9 @@ int fno_set_graphs(fno_ctx *ctx, int on);
  * occupied placements concatenated along K, computed by one MFMA GEMM whose
  * operand tiles are gathered from packed T3/T2 into LDS, followed by one
  * P(a/bc) fold into R3 and one occupied-only operator applied to packed T3.
- * Used when 3 <= nvir <= 64 (after truncation) and nocc >= 3.  With on = 0,
- * or outside those sizes, every term runs as its own expand / GEMM / fold
+ * Used for FP64 and FP32 triples products when 3 <= nvir <= 64 (after
+ * truncation) and nocc >= 3.  With on = 0, with split-BF16 products, or
+ * outside those sizes, every term runs as its own expand / GEMM / fold
  * sequence.  Both paths compute the same residual (to rounding); the EOM
  * sigma vectors always use the per-term path.  Returns FNO_OK.
  */

@@ -22,7 +22,7 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops", "fno_profile", "fno_profile_report", "fno_profile_filter",
+           "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_profile", "fno_profile_report", "fno_profile_filter",
            "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
@@ -81,6 +81,7 @@ def library() -> C.CDLL:
         lib.fno_eom_size.restype = C.c_size_t
         lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
+        lib.fno_last_trace.argtypes = [C.c_void_p, dp, dp, C.c_int, C.POINTER(C.c_int)]
         lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
@@ -221,6 +222,14 @@ class Context:
         t, a = C.c_double(), C.c_double()
         self._check(self._lib.fno_last_flops(self._h, C.byref(t), C.byref(a)))
         return t.value, a.value
+
+    def last_trace(self):
+        """(energies, residual norms) per iteration of the last ccsdt() call."""
+        n = C.c_int()
+        self._check(self._lib.fno_last_trace(self._h, None, None, 0, C.byref(n)))
+        e, r = np.zeros(n.value), np.zeros(n.value)
+        self._check(self._lib.fno_last_trace(self._h, _dp(e), _dp(r), n.value, C.byref(n)))
+        return e, r
 
     # ---- profiling
     def profile(self, on: bool = True, only: str | None = None) -> None:

@@ -329,6 +329,18 @@ int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops)
   return FNO_OK;
 }
 
+int fno_last_trace(const fno_ctx* ctx, double* energies, double* res_norms, int cap, int* n) {
+  if (!ctx || !ctx->c || !n) return FNO_EINVAL;
+  const auto& c = *ctx->c;
+  const int m = (int)c.trace_e.size();
+  *n = m;
+  for (int k = 0; k < m && k < cap; ++k) {
+    if (energies) energies[k] = c.trace_e[k];
+    if (res_norms) res_norms[k] = c.trace_r[k];
+  }
+  return FNO_OK;
+}
+
 int fno_profile(fno_ctx* ctx, int on) {
   return guard(ctx, [&](fno::Context& c) {
     c.eng->profile = on != 0;

@@ -77,6 +77,7 @@ class Context {
   void dav_release();
 
   double last_triples_flops = 0, last_all_flops = 0;
+  std::vector<double> trace_e, trace_r;  // per-iteration E_corr and |r| of the last fno_ccsdt
 
   // learned guess: the network used when CCOptions::guess == 1 (not owned)
   Mlp* guess_model = nullptr;

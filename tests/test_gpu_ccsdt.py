@@ -141,13 +141,65 @@ def test_fno_full_space_equals_canonical(P):
     assert abs(e0 - e1) < 1e-10
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
-def test_mixed_precision_energy(P, prec):
-    h = config_hamiltonian("C1")
+# Mixed-precision tolerances, relative to max |R3| (FP64 oracle):
+#  * FP32 products: operands rounded to 24 bits, FP32 accumulation over K up
+#    to ~3,800 per element in the fused pass; measured 1.7e-7 (fused) and
+#    4.3e-8 (per term) at o=4, v=12 -> bound 2e-6;
+#  * split-BF16 (hi*hi + hi*lo + lo*hi of 8-bit halves, FP32 accumulation):
+#    about 16 significant bits per operand; measured 6.2e-6 -> bound 5e-5.
+# R1 and R2 stay FP64 in every mode (1e-11).
+MIXED_R3_TOL = {"fp32": 2e-6, "bf16x3": 5e-5}
+
+
+@pytest.mark.parametrize("prec,fused", [("fp32", True), ("fp32", False), ("bf16x3", True), ("bf16x3", False)])
+def test_mixed_precision_residual_matches_oracle(P, prec, fused):
+    """FP32 / split-BF16 triples products against the FP64 oracle, elementwise (o=4, v=12)."""
+    print(f"mixed residual parity {prec} fused={fused}", flush=True)
+    h = make_hamiltonian(4, 12, 1)
+    amps = random_amps(np.random.default_rng(1), 4, 12)
     with _ctx(P, h) as c:
-        e64 = c.ccsdt(r_tol=1e-9, e_tol=1e-11)["e_tot"]
-        r = c.ccsdt(r_tol=1e-6, e_tol=1e-9, prec=prec, allow_noconv=True)
-    assert abs(r["e_tot"] - e64) < 1e-5, (prec, r["e_tot"] - e64)
+        _set(c, amps)
+        c.set_fused(fused)
+        got = c.cc_residual(prec)
+    R = cc.cc_residual(h.fock, h.eri, 4, amps)
+    refs = (R[1].ravel(), pack(R[2], 2, 2), pack(R[3], 3, 3))
+    for k, (g, r) in enumerate(zip(got[:3], refs)):
+        tol = MIXED_R3_TOL[prec] if k == 2 else 1e-11
+        assert np.abs(g - r).max() < tol * max(1.0, np.abs(r).max()), (k, np.abs(g - r).max())
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_mixed_precision_energy_matches_oracle(P, prec):
+    """Converged mixed-precision CCSDT energy of the o=4, v=12 workload within
+    1e-5 Eh of the FP64 oracle; the solve must converge (for split-BF16 by the
+    residual-floor rule)."""
+    h = config_hamiltonian("C1")
+    ref = cc.solve_ccsdt(h.fock, h.eri, 4, r_tol=1e-10, e_tol=1e-12)
+    with _ctx(P, h) as c:
+        r = c.ccsdt(r_tol=1e-7, e_tol=1e-10, prec=prec, max_iter=80)
+        e, rn = c.last_trace()
+    assert r["converged"]
+    assert len(e) == r["iters"] and rn[-1] == r["res_norm"]
+    assert abs(r["e_tot"] - ref["e_tot"]) < 1e-5, (prec, r["e_tot"] - ref["e_tot"])
+
+
+def test_precision_switch_back_to_back(P):
+    """FP64, FP32 and split-BF16 solves back to back on one context with graph
+    replay on (each switch drops the recorded sweep while the sweep launched
+    ahead by the previous solve may still run): every solve equals the same
+    solve on a fresh context."""
+    print("precision switch back to back", flush=True)
+    h = make_hamiltonian(4, 12, 3)
+    seq = [("fp64", 1e-9), ("fp32", 1e-6), ("bf16x3", 1e-6), ("fp64", 1e-9), ("bf16x3", 1e-6), ("fp32", 1e-6)]
+    with _ctx(P, h) as c:
+        c.set_graphs(True)
+        got = [c.ccsdt(r_tol=rt, e_tol=1e-10, prec=pr, max_iter=60) for pr, rt in seq]
+    for (pr, rt), g in zip(seq, got):
+        with _ctx(P, h) as c:
+            c.set_graphs(True)
+            ref = c.ccsdt(r_tol=rt, e_tol=1e-10, prec=pr, max_iter=60)
+        assert g["converged"] and ref["converged"], pr
+        assert g["iters"] == ref["iters"] and abs(g["e_tot"] - ref["e_tot"]) < 1e-12, (pr, g, ref)
 
 
 def test_full_size_sampled_residual(P):
