@@ -186,6 +186,24 @@ int fno_cc_residual(fno_ctx *ctx, fno_prec prec, double *r1, double *r2, double 
 size_t fno_eom_size(const fno_ctx *ctx, fno_eom_kind kind);
 int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *r, double *sigma, size_t len);
 
+/*
+ * Device-pointer variants of the calls above.  Every d_ buffer is device
+ * memory on the context's device (caller-owned, same packed layouts and
+ * lengths as the host versions); copies and kernels are enqueued on the
+ * context's stream (fno_set_stream), so a caller whose buffers come from
+ * another stream orders them with that stream first.  The calls return when
+ * the work is enqueued, except fno_cc_residual_dev and fno_eom_sigma_dev,
+ * which synchronize the stream before returning (e_corr is read back; the
+ * EOM setup of the intermediates needs it).  Device amplitudes are not
+ * checked for NaN / Inf on entry (a non-finite residual later makes
+ * fno_ccsdt return FNO_ENONFINITE).  Errors as for the host versions.
+ */
+int fno_get_amplitudes_dev(fno_ctx *ctx, int block, double *d_buf, size_t len);
+int fno_set_amplitudes_dev(fno_ctx *ctx, int block, const double *d_buf, size_t len);
+int fno_cc_residual_dev(fno_ctx *ctx, fno_prec prec, double *d_r1, double *d_r2, double *d_r3, double *e_corr);
+int fno_eom_sigma_dev(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *d_r, double *d_sigma,
+                      size_t len);
+
 /* Algorithmic GEMM flops (packed forms) of the triples contractions and of all
  * terms: of one residual evaluation after fno_ccsdt / fno_cc_residual, of the
  * sigma sweep after fno_eom_sigma, and summed over every sigma sweep of the

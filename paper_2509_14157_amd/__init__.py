@@ -22,7 +22,8 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_profile", "fno_profile_report", "fno_profile_filter",
+           "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
+           "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_profile", "fno_profile_report", "fno_profile_filter",
            "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
@@ -82,6 +83,10 @@ def library() -> C.CDLL:
         lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
         lib.fno_last_trace.argtypes = [C.c_void_p, dp, dp, C.c_int, C.POINTER(C.c_int)]
+        lib.fno_get_amplitudes_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]
+        lib.fno_set_amplitudes_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]
+        lib.fno_cc_residual_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, dp]
+        lib.fno_eom_sigma_dev.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t]
         lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
@@ -222,6 +227,28 @@ class Context:
         t, a = C.c_double(), C.c_double()
         self._check(self._lib.fno_last_flops(self._h, C.byref(t), C.byref(a)))
         return t.value, a.value
+
+    # ---- device-pointer variants: arguments are device addresses (int), e.g.
+    # torch tensor .data_ptr() of contiguous float64 tensors on this device
+    def set_stream(self, stream_handle) -> None:
+        """Enqueue on the given HIP stream (an int handle, e.g. torch.cuda.Stream().cuda_stream)."""
+        self._check(self._lib.fno_set_stream(self._h, C.c_void_p(stream_handle)))
+
+    def set_amplitudes_dev(self, block: int, ptr: int, n: int) -> None:
+        self._check(self._lib.fno_set_amplitudes_dev(self._h, block, C.c_void_p(ptr), n))
+
+    def get_amplitudes_dev(self, block: int, ptr: int, n: int) -> None:
+        self._check(self._lib.fno_get_amplitudes_dev(self._h, block, C.c_void_p(ptr), n))
+
+    def cc_residual_dev(self, prec, p1: int, p2: int, p3: int) -> float:
+        ec = C.c_double()
+        self._check(self._lib.fno_cc_residual_dev(self._h, PREC[prec], C.c_void_p(p1), C.c_void_p(p2),
+                                                  C.c_void_p(p3), C.byref(ec)))
+        return ec.value
+
+    def eom_sigma_dev(self, kind: str, ptr_r: int, ptr_sigma: int, n: int, prec="fp64") -> None:
+        self._check(self._lib.fno_eom_sigma_dev(self._h, KIND[kind], PREC[prec], C.c_void_p(ptr_r),
+                                                C.c_void_p(ptr_sigma), n))
 
     def last_trace(self):
         """(energies, residual norms) per iteration of the last ccsdt() call."""

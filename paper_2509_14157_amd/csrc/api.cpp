@@ -305,6 +305,38 @@ int fno_cc_residual(fno_ctx* ctx, fno_prec prec, double* r1, double* r2, double*
   });
 }
 
+int fno_get_amplitudes_dev(fno_ctx* ctx, int block, double* d_buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(d_buf != nullptr, FNO_EINVAL, "null buffer");
+    c.get_amps(block, d_buf, len, true);
+    return FNO_OK;
+  });
+}
+
+int fno_set_amplitudes_dev(fno_ctx* ctx, int block, const double* d_buf, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(d_buf != nullptr, FNO_EINVAL, "null buffer");
+    c.set_amps(block, d_buf, len, true);
+    return FNO_OK;
+  });
+}
+
+int fno_cc_residual_dev(fno_ctx* ctx, fno_prec prec, double* d_r1, double* d_r2, double* d_r3, double* e_corr) {
+  return guard(ctx, [&](fno::Context& c) {
+    c.cc_residual(to_prec(prec), d_r1, d_r2, d_r3, e_corr, true);
+    return FNO_OK;
+  });
+}
+
+int fno_eom_sigma_dev(fno_ctx* ctx, fno_eom_kind kind, fno_prec prec, const double* d_r, double* d_sigma,
+                      size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(d_r && d_sigma, FNO_EINVAL, "null buffer");
+    c.eom_sigma((int)kind, to_prec(prec), d_r, d_sigma, len, true);
+    return FNO_OK;
+  });
+}
+
 size_t fno_eom_size(const fno_ctx* ctx, fno_eom_kind kind) {
   if (!ctx || !ctx->c || !ctx->c->loaded) return 0;
   try {

@@ -456,21 +456,35 @@ size_t Context::amp_size(int block) const {
   return (size_t)tblocks_[block - 1].size;
 }
 
-void Context::get_amps(int block, double* buf, size_t len) {
+void Context::get_amps(int block, double* buf, size_t len, bool dev) {
   FNO_REQUIRE(cc_ready, kESTATE, "no amplitudes: call fno_ccsdt or fno_set_amplitudes first");
   FNO_REQUIRE(block >= 1 && block <= 3 && len == amp_size(block), kEINVAL, "bad amplitude block or length");
-  FNO_HIP(hipMemcpy(buf, amp_ + tblocks_[block - 1].offset, len * sizeof(double), hipMemcpyDeviceToHost));
+  if (dev) {
+    FNO_HIP(hipMemcpyAsync(buf, amp_ + tblocks_[block - 1].offset, len * sizeof(double), hipMemcpyDeviceToDevice,
+                           eng->stream));
+    return;
+  }
+  FNO_HIP(hipMemcpyAsync(buf, amp_ + tblocks_[block - 1].offset, len * sizeof(double), hipMemcpyDeviceToHost,
+                         eng->stream));
+  FNO_HIP(hipStreamSynchronize(eng->stream));
 }
 
-void Context::set_amps(int block, const double* buf, size_t len) {
+void Context::set_amps(int block, const double* buf, size_t len, bool dev) {
   FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
   if (!cc_ready) setup_cc();
   FNO_REQUIRE(block >= 1 && block <= 3 && len == amp_size(block), kEINVAL, "bad amplitude block or length");
+  if (dev) {
+    FNO_HIP(hipMemcpyAsync(amp_ + tblocks_[block - 1].offset, buf, len * sizeof(double), hipMemcpyDeviceToDevice,
+                           eng->stream));
+    return;
+  }
   for (size_t i = 0; i < len; ++i) FNO_REQUIRE(std::isfinite(buf[i]), kENONFINITE, "non-finite amplitude");
-  FNO_HIP(hipMemcpy(amp_ + tblocks_[block - 1].offset, buf, len * sizeof(double), hipMemcpyHostToDevice));
+  FNO_HIP(hipMemcpyAsync(amp_ + tblocks_[block - 1].offset, buf, len * sizeof(double), hipMemcpyHostToDevice,
+                         eng->stream));
+  FNO_HIP(hipStreamSynchronize(eng->stream));
 }
 
-void Context::cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec) {
+void Context::cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec, bool dev) {
   FNO_REQUIRE(loaded, kESTATE, "no Hamiltonian loaded");
   if (!cc_ready) setup_cc();
   eng->prec = p;
@@ -480,7 +494,7 @@ void Context::cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec
   for (int k = 0; k < 3; ++k)
     if (outs[k])
       FNO_HIP(hipMemcpyAsync(outs[k], res_ + tblocks_[k].offset, tblocks_[k].size * sizeof(double),
-                             hipMemcpyDeviceToHost, eng->stream));
+                             dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, eng->stream));
   double E = energy();
   if (ec) *ec = E;
   FNO_HIP(hipStreamSynchronize(eng->stream));

@@ -59,14 +59,15 @@ class Context {
   void load(int o, int v, const double* f, const double* g, double en);
   void truncate(double occt, int keep, int* kept, double* emp2, double* occ);
   int ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, double* rn);
-  void cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec);
+  // dev: the buffers are device memory, copied on the context's stream
+  void cc_residual(Prec p, double* r1, double* r2, double* r3, double* ec, bool dev = false);
   size_t amp_size(int block) const;
-  void get_amps(int block, double* buf, size_t len);
-  void set_amps(int block, const double* buf, size_t len);
+  void get_amps(int block, double* buf, size_t len, bool dev = false);
+  void set_amps(int block, const double* buf, size_t len, bool dev = false);
 
   // EOM
   size_t eom_size(int kind);
-  void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len);
+  void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev = false);
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
   // resumable Davidson (used by eom() and by batched solves over several contexts)
   struct Davidson;

@@ -278,7 +278,7 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
   c.last_all_flops += sp.sweep_all;
 }
 
-void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len) {
+void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev) {
   FNO_REQUIRE(cc_ready, kESTATE, "EOM sigma needs amplitudes (fno_ccsdt or fno_set_amplitudes)");
   FNO_REQUIRE(len == eom_size(kind), kEINVAL, "R vector length mismatch");
   if (eom_) eom_->ready = eom_->ready && eom_->kind == kind;
@@ -286,12 +286,18 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
   release_eom();
   setup_eom(kind, 1);
   Engine& e = *eng;
+  last_triples_flops = last_all_flops = 0;
+  if (dev) {
+    eom_apply(*this, e, *eom_, r, (int64_t)len, 1, sigma, (int64_t)len, p);
+    FNO_HIP(hipStreamSynchronize(e.stream));
+    return;
+  }
   double* dr = alloc((int64_t)len);
   double* ds = alloc((int64_t)len);
-  FNO_HIP(hipMemcpy(dr, r, len * sizeof(double), hipMemcpyHostToDevice));
-  last_triples_flops = last_all_flops = 0;
+  FNO_HIP(hipMemcpyAsync(dr, r, len * sizeof(double), hipMemcpyHostToDevice, e.stream));
   eom_apply(*this, e, *eom_, dr, (int64_t)len, 1, ds, (int64_t)len, p);
-  FNO_HIP(hipMemcpy(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost));
+  FNO_HIP(hipMemcpyAsync(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost, e.stream));
+  FNO_HIP(hipStreamSynchronize(e.stream));
   FNO_HIP(hipFree(dr));
   FNO_HIP(hipFree(ds));
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dr), owned_.end());
@@ -323,6 +329,16 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   FNO_REQUIRE(d->nroots <= 256, kEINVAL, "at most 256 roots");
   d->max_sub = std::min(std::max(opt.max_sub > 0 ? opt.max_sub : 8 * d->nroots, 2 * d->nroots), 512);
   const int64_t dim = d->dim;
+  {
+    // basis and sigma vectors (max_sub each), Ritz vectors and residual
+    // block: refuse up front what the device cannot hold
+    size_t free_b = 0, total_b = 0;
+    FNO_HIP(hipMemGetInfo(&free_b, &total_b));
+    const double need = 8.0 * (double)dim * (2.0 * d->max_sub + 3.0 * d->nroots);
+    FNO_REQUIRE(need <= (double)free_b, kENOMEM,
+                "Davidson storage needs " + std::to_string(need / 1e9) + " GB, the device has " +
+                    std::to_string((double)free_b / 1e9) + " GB free (lower max_sub or nroots)");
+  }
   d->V = alloc((int64_t)d->max_sub * dim);
   d->S = alloc((int64_t)d->max_sub * dim);
   d->X = alloc((int64_t)d->nroots * dim);
