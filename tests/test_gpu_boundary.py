@@ -2,9 +2,9 @@
 statuses under bad input (failure injection from the host: every kernel that
 runs still exits normally).
 
-* fno_set_amplitudes_dev / fno_cc_residual_dev / fno_eom_sigma_dev on torch
-  device tensors, with the context on a torch stream (fno_set_stream), give
-  exactly what the host-pointer calls give;
+* fno_set_amplitudes_dev / fno_cc_residual_dev / fno_eom_sigma_dev on
+  caller-allocated device buffers, with the context on a caller-created
+  stream (fno_set_stream), give exactly what the host-pointer calls give;
 * NaN / Inf in the inputs -> FNO_ENONFINITE; integrals without the
   <pq||rs> symmetry, a non-symmetric Fock matrix, OCCT outside (0, 1] ->
   FNO_EINVAL; calls out of order -> FNO_ESTATE; max_iter = 1 ->
@@ -36,9 +36,56 @@ def _ctx(P, h):
     return c
 
 
-def test_dev_calls_on_a_torch_stream(P):
-    torch = pytest.importorskip("torch")
-    print("dev calls on a torch stream", flush=True)
+class _Hip:
+    """Device buffers and a stream from the HIP runtime the library itself
+    loaded (torch 2.10+rocm7.0 bundles a second HIP runtime with the same
+    SONAME; two runtimes in one process do not share devices or streams, so
+    the caller-side memory here comes from the library's runtime)."""
+
+    def __init__(self):
+        import ctypes
+        self.C = ctypes
+        self.lib = ctypes.CDLL("libamdhip64.so.7")
+        self.bufs = []
+
+    def _ok(self, st):
+        assert st == 0, st
+
+    def alloc(self, n):
+        p = self.C.c_void_p()
+        self._ok(self.lib.hipMalloc(self.C.byref(p), self.C.c_size_t(8 * max(n, 1))))
+        self.bufs.append(p)
+        return p.value
+
+    def upload(self, x):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        p = self.alloc(x.size)
+        self._ok(self.lib.hipMemcpy(self.C.c_void_p(p), x.ctypes.data_as(self.C.c_void_p),
+                                    self.C.c_size_t(8 * x.size), 1))
+        return p
+
+    def download(self, p, n):
+        out = np.zeros(n)
+        self._ok(self.lib.hipMemcpy(out.ctypes.data_as(self.C.c_void_p), self.C.c_void_p(p), self.C.c_size_t(8 * n),
+                                    2))
+        return out
+
+    def stream(self):
+        s = self.C.c_void_p()
+        self._ok(self.lib.hipStreamCreate(self.C.byref(s)))
+        return s.value
+
+    def sync(self, s):
+        self._ok(self.lib.hipStreamSynchronize(self.C.c_void_p(s)))
+
+    def close(self, s):
+        self._ok(self.lib.hipStreamDestroy(self.C.c_void_p(s)))
+        for p in self.bufs:
+            self._ok(self.lib.hipFree(p))
+
+
+def test_dev_calls_on_a_caller_stream(P):
+    print("dev calls on a caller stream", flush=True)
     o, v = 4, 12
     h = make_hamiltonian(o, v, 1)
     rng = np.random.default_rng(4)
@@ -51,29 +98,31 @@ def test_dev_calls_on_a_torch_stream(P):
             c.set_amplitudes(k, packed[k - 1])
         ref = c.cc_residual("fp64")
         sig_ref = c.eom_sigma("EA", rvec)
-    dev = torch.device("cuda", 0)
-    s = torch.cuda.Stream(device=dev)
+    hip = _Hip()
     with _ctx(P, h) as c:
-        c.set_stream(s.cuda_stream)
-        with torch.cuda.stream(s):
-            t = [torch.from_numpy(x).to(dev) for x in packed]
-            r = [torch.zeros(x.size, dtype=torch.float64, device=dev) for x in packed]
-            back = torch.zeros(packed[2].size, dtype=torch.float64, device=dev)
-            rt = torch.from_numpy(rvec).to(dev)
-            st = torch.zeros_like(rt)
-        s.synchronize()
+        s = hip.stream()
+        c.set_stream(s)
+        t = [hip.upload(x) for x in packed]
+        r = [hip.alloc(x.size) for x in packed]
+        back = hip.alloc(packed[2].size)
+        rt = hip.upload(rvec)
+        st = hip.alloc(rvec.size)
         for k in (1, 2, 3):
-            c.set_amplitudes_dev(k, t[k - 1].data_ptr(), t[k - 1].numel())
-        c.get_amplitudes_dev(3, back.data_ptr(), back.numel())
-        ec = c.cc_residual_dev("fp64", r[0].data_ptr(), r[1].data_ptr(), r[2].data_ptr())
-        c.eom_sigma_dev("EA", rt.data_ptr(), st.data_ptr(), rt.numel())
-        s.synchronize()
+            c.set_amplitudes_dev(k, t[k - 1], packed[k - 1].size)
+        c.get_amplitudes_dev(3, back, packed[2].size)
+        ec = c.cc_residual_dev("fp64", r[0], r[1], r[2])
+        c.eom_sigma_dev("EA", rt, st, rvec.size)
+        hip.sync(s)
         c.set_stream(0)
-    assert np.array_equal(back.cpu().numpy(), packed[2])
-    for g, e in zip(r, ref[:3]):
-        assert np.array_equal(g.cpu().numpy(), e)
+        got = [hip.download(p, x.size) for p, x in zip(r, packed)]
+        got_back = hip.download(back, packed[2].size)
+        got_sig = hip.download(st, rvec.size)
+    hip.close(s)
+    assert np.array_equal(got_back, packed[2])
+    for g, e in zip(got, ref[:3]):
+        assert np.array_equal(g, e)
     assert ec == ref[3]
-    assert np.array_equal(st.cpu().numpy(), sig_ref)
+    assert np.array_equal(got_sig, sig_ref)
 
 
 def test_nonfinite_inputs_are_rejected(P):
@@ -127,7 +176,7 @@ def test_bad_symmetry_and_options_are_rejected(P):
 
 def test_max_iter_one_reports_noconv_with_results(P):
     h = make_hamiltonian(4, 12, 1)
-    with P.Context(0) as c:
+    with _ctx(P, h) as c:
         with pytest.raises(P.FnoError) as e:
             c.ccsdt(max_iter=1)
         assert e.value.code == P.FNO_ENOCONV
