@@ -204,6 +204,31 @@ int fno_cc_residual_dev(fno_ctx *ctx, fno_prec prec, double *d_r1, double *d_r2,
 int fno_eom_sigma_dev(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *d_r, double *d_sigma,
                       size_t len);
 
+/*
+ * The fused triples residual (the triples projection of eq 5 in its
+ * T1-dressed form: pp-ladder, hh-ladder, ring, one-body and T2 driver terms)
+ * without a context, on caller device buffers of device hip_device:
+ *   R3 += sum of those terms,
+ * with T3 [C(o,3)][C(v,3)] and T2 [C(o,2)][C(v,2)] packed (colex, holes
+ * slow); the dressed intermediates W3_vvvv [C(v,2)(bc)][C(v,2)(ef)],
+ * F3_vv [v][v], W3_ovvo [o][v][v][o] (m a e i), W3_vvvo [o (k)][v (e)][C(v,2) (bc)],
+ * W3_ovoo [o (m)][v (c)][C(o,2) (jk)], W3_oooo [C(o,2)(mn)][C(o,2)(ij)] and
+ * F3_oo [o (m)][o (i)], all FP64 (the intermediates a context builds from
+ * T1, T2, T3; fno_debug_tensor shows them).  3 <= nocc, nvir <= 64; prec
+ * FNO_FP64 or FNO_FP32 (products; R3 accumulates in FP64).  Work runs on
+ * `stream` (NULL: the device's null stream); the call allocates its working
+ * buffers (about 2 C(o,3) v C(v,2) values of the product type) for its own
+ * duration and returns after the stream has finished.  Inputs are read only,
+ * R3 is caller-owned.  Errors: FNO_EINVAL (sizes, precision, null buffer),
+ * FNO_EDEVICE, FNO_ENOMEM; fno_dev_last_error() gives the message (per host
+ * thread).
+ */
+int fno_triples_residual_dev(int hip_device, int nocc, int nvir, fno_prec prec, const double *T3, const double *T2,
+                             const double *W3_vvvv, const double *F3_vv, const double *W3_ovvo,
+                             const double *W3_vvvo, const double *W3_ovoo, const double *W3_oooo,
+                             const double *F3_oo, double *R3, void *stream);
+const char *fno_dev_last_error(void);
+
 /* Algorithmic GEMM flops (packed forms) of the triples contractions and of all
  * terms: of one residual evaluation after fno_ccsdt / fno_cc_residual, of the
  * sigma sweep after fno_eom_sigma, and summed over every sigma sweep of the

@@ -23,7 +23,7 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
-           "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_profile", "fno_profile_report", "fno_profile_filter",
+           "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error", "fno_profile", "fno_profile_report", "fno_profile_filter",
            "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
@@ -87,6 +87,8 @@ def library() -> C.CDLL:
         lib.fno_set_amplitudes_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]
         lib.fno_cc_residual_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, dp]
         lib.fno_eom_sigma_dev.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t]
+        lib.fno_triples_residual_dev.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 11
+        lib.fno_dev_last_error.restype = C.c_char_p
         lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]
         lib.fno_profile_filter.argtypes = [C.c_void_p, C.c_char_p]
@@ -122,6 +124,19 @@ def library() -> C.CDLL:
                                        C.c_double, C.c_double, dp, dp, dp]
         _lib = lib
     return _lib
+
+
+def triples_residual_dev(device: int, nocc: int, nvir: int, prec: str, ptrs: dict, r3: int, stream: int = 0,
+                         noalloc: bool = False) -> None:
+    """R3 += the fused triples terms on device buffers (addresses as ints; keys of
+    ptrs: T3, T2, W3_vvvv, F3_vv, W3_ovvo, W3_vvvo, W3_ovoo, W3_oooo, F3_oo)."""
+    lib = library()
+    fn = lib.fno_triples_residual_dev_noalloc if noalloc else lib.fno_triples_residual_dev
+    names = ("T3", "T2", "W3_vvvv", "F3_vv", "W3_ovvo", "W3_vvvo", "W3_ovoo", "W3_oooo", "F3_oo")
+    st = fn(device, nocc, nvir, PREC[prec], *[C.c_void_p(ptrs[k]) for k in names], C.c_void_p(r3),
+            C.c_void_p(stream))
+    if st != FNO_OK:
+        raise FnoError(st, lib.fno_dev_last_error().decode())
 
 
 def _dp(a: np.ndarray):

@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 from synthetic import make_hamiltonian
-from tests.helpers import random_amps, random_antisym
+from tests.helpers import HipBuffers, random_amps, random_antisym
 from tests.packing import pack
 from oracle import wick
 
@@ -36,54 +36,6 @@ def _ctx(P, h):
     return c
 
 
-class _Hip:
-    """Device buffers and a stream from the HIP runtime the library itself
-    loaded (torch 2.10+rocm7.0 bundles a second HIP runtime with the same
-    SONAME; two runtimes in one process do not share devices or streams, so
-    the caller-side memory here comes from the library's runtime)."""
-
-    def __init__(self):
-        import ctypes
-        self.C = ctypes
-        self.lib = ctypes.CDLL("libamdhip64.so.7")
-        self.bufs = []
-
-    def _ok(self, st):
-        assert st == 0, st
-
-    def alloc(self, n):
-        p = self.C.c_void_p()
-        self._ok(self.lib.hipMalloc(self.C.byref(p), self.C.c_size_t(8 * max(n, 1))))
-        self.bufs.append(p)
-        return p.value
-
-    def upload(self, x):
-        x = np.ascontiguousarray(x, dtype=np.float64)
-        p = self.alloc(x.size)
-        self._ok(self.lib.hipMemcpy(self.C.c_void_p(p), x.ctypes.data_as(self.C.c_void_p),
-                                    self.C.c_size_t(8 * x.size), 1))
-        return p
-
-    def download(self, p, n):
-        out = np.zeros(n)
-        self._ok(self.lib.hipMemcpy(out.ctypes.data_as(self.C.c_void_p), self.C.c_void_p(p), self.C.c_size_t(8 * n),
-                                    2))
-        return out
-
-    def stream(self):
-        s = self.C.c_void_p()
-        self._ok(self.lib.hipStreamCreate(self.C.byref(s)))
-        return s.value
-
-    def sync(self, s):
-        self._ok(self.lib.hipStreamSynchronize(self.C.c_void_p(s)))
-
-    def close(self, s):
-        self._ok(self.lib.hipStreamDestroy(self.C.c_void_p(s)))
-        for p in self.bufs:
-            self._ok(self.lib.hipFree(p))
-
-
 def test_dev_calls_on_a_caller_stream(P):
     print("dev calls on a caller stream", flush=True)
     o, v = 4, 12
@@ -98,7 +50,7 @@ def test_dev_calls_on_a_caller_stream(P):
             c.set_amplitudes(k, packed[k - 1])
         ref = c.cc_residual("fp64")
         sig_ref = c.eom_sigma("EA", rvec)
-    hip = _Hip()
+    hip = HipBuffers()
     with _ctx(P, h) as c:
         s = hip.stream()
         c.set_stream(s)
@@ -198,3 +150,46 @@ def test_eom_larger_than_the_device_is_enomem(P):
             c.eom("DEA", nroots=4, max_sub=512, max_iter=2)
         assert e.value.code == P.FNO_ENOMEM
         assert "GB" in str(e.value)
+
+
+INTERMEDIATES = ("W3_vvvv", "F3_vv", "W3_ovvo", "W3_vvvo", "W3_ovoo", "W3_oooo", "F3_oo")
+
+
+def triples_dev_inputs(P, o, v, seed):
+    """Amplitudes, the context's dressed intermediates at them and the context's R3 (FP64, FP32)."""
+    h = make_hamiltonian(o, v, seed)
+    amps = random_amps(np.random.default_rng(seed), o, v)
+    with _ctx(P, h) as c:
+        c.set_amplitudes(1, amps[1].ravel())
+        c.set_amplitudes(2, pack(amps[2], 2, 2))
+        c.set_amplitudes(3, pack(amps[3], 3, 3))
+        r32 = c.cc_residual("fp32")[2]
+        r64 = c.cc_residual("fp64")[2]
+        arrays = {k: c.debug_tensor(k) for k in INTERMEDIATES}
+        arrays["T3"] = c.get_amplitudes(3)
+        arrays["T2"] = c.get_amplitudes(2)
+    return arrays, {"fp64": r64, "fp32": r32}
+
+
+@pytest.mark.parametrize("o,v", [(4, 12), (7, 24)])
+def test_triples_residual_dev_matches_context(P, o, v):
+    """The context-free fused triples entry point on device buffers gives the
+    context's triples residual bit for bit (same kernels; R3 starts at zero
+    in both, and no other term adds to R3)."""
+    print(f"triples residual dev o={o} v={v}", flush=True)
+    arrays, ref = triples_dev_inputs(P, o, v, 5)
+    hip = HipBuffers()
+    ptrs = {k: hip.upload(x) for k, x in arrays.items()}
+    n3 = arrays["T3"].size
+    for prec in ("fp64", "fp32"):
+        r3 = hip.upload(np.zeros(n3))
+        P.triples_residual_dev(0, o, v, prec, ptrs, r3)
+        assert np.array_equal(hip.download(r3, n3), ref[prec]), prec
+    s = hip.stream()
+    with pytest.raises(P.FnoError) as e:
+        P.triples_residual_dev(0, o, 65, "fp64", ptrs, r3, s)
+    assert e.value.code == P.FNO_EINVAL
+    with pytest.raises(P.FnoError) as e:
+        P.triples_residual_dev(0, o, v, "bf16x3", ptrs, r3, s)
+    assert e.value.code == P.FNO_EINVAL
+    hip.close(s)
