@@ -229,6 +229,28 @@ int fno_triples_residual_dev(int hip_device, int nocc, int nvir, fno_prec prec, 
                              const double *F3_oo, double *R3, void *stream);
 const char *fno_dev_last_error(void);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): fno_triples_residual_dev
+ * with its working buffers in a static per-device array of 256 MiB (held from
+ * the first call on a device until the process ends) instead of allocated
+ * memory.  Same arguments, layouts and results; the call allocates nothing
+ * (no hipMalloc / hipFree, no allocating library routine), enqueues the work
+ * on `stream` and returns without waiting.  The first call on a device looks
+ * up the array and fills two small index tables (a device synchronization).
+ * Sizes whose working buffers exceed 256 MiB (about 2 C(o,3) v C(v,2)
+ * elements of the product type plus small parts; o=10, v=59 and o=12, v=48
+ * fit in FP64) return FNO_ENOMEM with the required size in
+ * fno_dev_last_error().  Every call on a device shares that device's array,
+ * which keeps the last call's contents: calls that overlap on one device
+ * (other streams, other host threads) race and give wrong results; order
+ * them on one stream or synchronize between them.
+ */
+int fno_triples_residual_dev_noalloc(int hip_device, int nocc, int nvir, fno_prec prec, const double *T3,
+                                     const double *T2, const double *W3_vvvv, const double *F3_vv,
+                                     const double *W3_ovvo, const double *W3_vvvo, const double *W3_ovoo,
+                                     const double *W3_oooo, const double *F3_oo, double *R3, void *stream);
+
 /* Algorithmic GEMM flops (packed forms) of the triples contractions and of all
  * terms: of one residual evaluation after fno_ccsdt / fno_cc_residual, of the
  * sigma sweep after fno_eom_sigma, and summed over every sigma sweep of the

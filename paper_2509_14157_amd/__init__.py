@@ -23,7 +23,8 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
-           "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error", "fno_profile", "fno_profile_report", "fno_profile_filter",
+           "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error",
+           "fno_triples_residual_dev_noalloc", "fno_profile", "fno_profile_report", "fno_profile_filter",
            "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
@@ -88,6 +89,7 @@ def library() -> C.CDLL:
         lib.fno_cc_residual_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, dp]
         lib.fno_eom_sigma_dev.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_size_t]
         lib.fno_triples_residual_dev.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 11
+        lib.fno_triples_residual_dev_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int] + [C.c_void_p] * 11
         lib.fno_dev_last_error.restype = C.c_char_p
         lib.fno_profile.argtypes = [C.c_void_p, C.c_int]
         lib.fno_profile_report.argtypes = [C.c_void_p, C.c_char_p, C.c_size_t]

@@ -7,15 +7,15 @@
 #include <mutex>
 #include <string>
 
-#include "../../include/fnocc.h"
+#include "triples_dev.hpp"
+
 #include "kernels.hpp"
-#include "triples.hpp"
 
 namespace fno {
 namespace {
 
 constexpr int kDevMaxN = 64;  // occupied and virtual sizes these entry points take
-constexpr int kMaxDevices = 64;
+
 constexpr int kDec2 = kDevMaxN * (kDevMaxN - 1) / 2;
 constexpr int kDec3 = kDevMaxN * (kDevMaxN - 1) * (kDevMaxN - 2) / 6;
 
@@ -48,10 +48,14 @@ struct DevState {
   IndexTables tb{};
 };
 std::mutex g_mu;
-DevState g_dev[kMaxDevices];
-thread_local std::string g_err;
+DevState g_dev[kDevMaxDevices];
 
-// the device's decode tables (built at the first call on that device)
+size_t up256(size_t x) { return (x + 255) / 256 * 256; }
+
+}  // namespace
+
+thread_local std::string g_dev_err;
+
 IndexTables dev_tables(int device) {
   std::lock_guard<std::mutex> lk(g_mu);
   DevState& st = g_dev[device];
@@ -71,13 +75,6 @@ IndexTables dev_tables(int device) {
   return st.tb;
 }
 
-struct Layout {
-  size_t t3v, wt, y, aring, fvvp, occ, total;
-};
-
-size_t up256(size_t x) { return (x + 255) / 256 * 256; }
-
-// byte offsets of the working buffers in one scratch block
 Layout layout(int o, int v, Prec p) {
   const size_t es = p == Prec::FP64 ? 8 : 4;
   const size_t nt = (size_t)binom_host(o, 3);
@@ -99,11 +96,6 @@ Layout layout(int o, int v, Prec p) {
   return L;
 }
 
-struct Inputs {
-  const double *T3, *T2, *Wvvvv, *Fvv, *Wovvo, *Wvvvo, *Wovoo, *Woooo, *Foo;
-};
-
-// R3 += the fused triples terms, with the working buffers in `base`
 void run_pass(const IndexTables& tb, int o, int v, Prec prec, const Inputs& in, double* R3, unsigned char* base,
               hipStream_t s) {
   const Layout L = layout(o, v, prec);
@@ -153,11 +145,10 @@ void run_pass(const IndexTables& tb, int o, int v, Prec prec, const Inputs& in, 
   launch_gemm(g, s);
 }
 
-// shared argument checks; returns the working precision
 Prec check_args(int device, int o, int v, fno_prec prec, const Inputs& in, const double* R3) {
   int ndev = 0;
   FNO_HIP(hipGetDeviceCount(&ndev));
-  FNO_REQUIRE(device >= 0 && device < ndev && device < kMaxDevices, kEDEVICE, "no such HIP device");
+  FNO_REQUIRE(device >= 0 && device < ndev && device < kDevMaxDevices, kEDEVICE, "no such HIP device");
   FNO_REQUIRE(o >= 3 && o <= kDevMaxN && v >= 3 && v <= kDevMaxN, kEINVAL,
               "the fused triples residual takes 3 <= nocc <= 64 and 3 <= nvir <= 64");
   FNO_REQUIRE(prec == FNO_FP64 || prec == FNO_FP32, kEINVAL,
@@ -167,26 +158,11 @@ Prec check_args(int device, int o, int v, fno_prec prec, const Inputs& in, const
   return prec == FNO_FP64 ? Prec::FP64 : Prec::FP32;
 }
 
-template <typename F>
-int dev_guard(F&& f) {
-  try {
-    g_err.clear();
-    return f();
-  } catch (const Error& e) {
-    g_err = e.what();
-    return e.code;
-  } catch (const std::exception& e) {
-    g_err = e.what();
-    return kEDEVICE;
-  }
-}
-
-}  // namespace
 }  // namespace fno
 
 extern "C" {
 
-const char* fno_dev_last_error(void) { return fno::g_err.c_str(); }
+const char* fno_dev_last_error(void) { return fno::g_dev_err.c_str(); }
 
 int fno_triples_residual_dev(int hip_device, int nocc, int nvir, fno_prec prec, const double* T3, const double* T2,
                              const double* W3_vvvv, const double* F3_vv, const double* W3_ovvo,
