@@ -39,33 +39,30 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(ham, occt, triples_flops):
-    """The CPU oracle on a bounded sample of the same workload.
-
-    Every contraction class of the singles, doubles and triples residuals is
-    evaluated as the oracle does (dense numpy einsum), but with the first hole
-    index of the output fixed to one value, i.e. 1/o of the output; the time
-    scaled by o is the oracle's seconds per CCSDT iteration.
-    """
-    import numpy as np
-
-    from oracle import cc, fno
-    from tests.packing import unpack_fast
-
+def _cpu_model():
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
-    o = ham.nocc
-    tr = fno.truncate(ham.fock, ham.eri, o, occt=occt)
-    v = tr["nvir"]
-    rng = np.random.default_rng(0)
-    amps = {1: rng.normal(0, 0.01, (o, v)),
-            2: unpack_fast(rng.normal(0, 0.01, math.comb(o, 2) * math.comb(v, 2)), o, v, 2, 2),
-            3: unpack_fast(rng.normal(0, 0.003, math.comb(o, 3) * math.comb(v, 3)), o, v, 3, 3)}
-    T = cc._tensors(tr["fock"], tr["eri"], o, amps)
-    i0 = int(rng.integers(o))
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_slice_seconds(T, o, i0):
+    """Seconds the oracle takes for every contraction class of the R1/R2/R3
+    residuals with the first hole index of the output fixed to i0."""
+    from oracle import cc
+
     t0 = time.perf_counter()
     for k in (1, 2, 3):
         terms, _ = cc._merged_cc(k)
@@ -77,8 +74,38 @@ def cpu_baseline(ham, occt, triples_flops):
                 arrs.append(arr[idx])
                 specs.append("".join(c for c in lets if c != term.out[0]))
             np.einsum(",".join(specs) + "->" + term.out[1:], *arrs, optimize=True)
-    t_slice = time.perf_counter() - t0
-    s_iter = o * t_slice
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(ham, occt, triples_flops):
+    """The CPU oracle on a bounded sample of the same workload.
+
+    Every contraction class of the singles, doubles and triples residuals is
+    evaluated as the oracle does (dense numpy einsum), but with the first hole
+    index of the output fixed to one value, i.e. 1/o of the output; the time
+    scaled by o is the oracle's seconds per CCSDT iteration.  Timed once with
+    the BLAS pool at its default size (all host cores) and once with one
+    thread.
+    """
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from oracle import cc, fno
+    from tests.packing import unpack_fast
+
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+    o = ham.nocc
+    tr = fno.truncate(ham.fock, ham.eri, o, occt=occt)
+    v = tr["nvir"]
+    rng = np.random.default_rng(0)
+    amps = {1: rng.normal(0, 0.01, (o, v)),
+            2: unpack_fast(rng.normal(0, 0.01, math.comb(o, 2) * math.comb(v, 2)), o, v, 2, 2),
+            3: unpack_fast(rng.normal(0, 0.003, math.comb(o, 3) * math.comb(v, 3)), o, v, 3, 3)}
+    T = cc._tensors(tr["fock"], tr["eri"], o, amps)
+    i0 = int(rng.integers(o))
+    t_slice = _oracle_slice_seconds(T, o, i0)
+    with threadpool_limits(1):
+        t_slice1 = _oracle_slice_seconds(T, o, i0)
+    s_iter, s_iter1 = o * t_slice, o * t_slice1
     return {
         "value": triples_flops / s_iter / 1e12,
         "unit": "TFLOP/s",
@@ -86,8 +113,11 @@ def cpu_baseline(ham, occt, triples_flops):
         "kind": "oracle",
         "sample": (f"all Wick contraction classes of the R1/R2/R3 residuals of the same truncated problem "
                    f"(o={o}, v={v}) evaluated densely with the first hole index fixed (1/{o} of the output, "
-                   f"{t_slice:.1f} s); s/iteration = {o} x that = {s_iter:.1f} s"),
+                   f"{t_slice:.1f} s on {threads} BLAS threads); s/iteration = {o} x that = {s_iter:.1f} s"),
         "s_per_iter": s_iter,
+        "cpu_count": os.cpu_count(),
+        "cpu_model": _cpu_model(),
+        "one_thread": {"value": triples_flops / s_iter1 / 1e12, "s_per_iter": s_iter1, "cores": 1},
     }
 
 
@@ -510,7 +540,7 @@ def main():
                    "triples_gflop_per_iter": round(tri / 1e9, 4), "all_gflop_per_iter": round(allf / 1e9, 4),
                    "pct_mfma_peak_whole_iteration": round(100 * value * (3 if args.prec == "bf16x3" else 1) / peak, 2)},
         "roofline": roofline,
-        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")},
+        "cpu_baseline": None if cpu is None else {k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample", "cpu_count", "cpu_model", "one_thread")},
         "kernel_ms_per_iter": {k["name"]: round(k["total_ms"] / witers, 4) for k in breakdown},
         "kernel_ms_per_iter_total": round(kernel_ms_iter, 4),
         "tuned_tiles": wrep.get("tuned", {}),

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfnocc.so")
 
-SOURCES = ["kernels.hip", "gemm.hip", "triples.hip", "triples_dev.hip", "triples_noalloc.hip", "engine.cpp", "linalg.cpp", "context.cpp", "cc.cpp", "eom.cpp", "mlp.cpp",
+SOURCES = ["kernels.hip", "gemm.hip", "triples.hip", "triples_side.hip", "triples_dev.hip", "triples_noalloc.hip", "engine.cpp", "linalg.cpp", "context.cpp", "cc.cpp", "eom.cpp", "mlp.cpp",
            "api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

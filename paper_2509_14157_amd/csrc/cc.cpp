@@ -146,10 +146,19 @@ void Context::setup_cc() {
     launch_denominators(e.tables, md, nh, d_eo, d_ev, den_ + tblocks_[k].offset, e.stream);
   }
   r3_stats_.clear();
+  side_stats_.clear();
   if (r3_y_) {
     const Prec keep = e.prec;
     e.prec = Prec::FP64;
     for (const char* t : kCCR3) r3_stats_.push_back(e.term_shape(t));
+    side_sh_ = side_shape(o, v);
+    side_buf_ = alloc(side_sh_.total);
+    for (const char* t : kCCInter3)
+      if (std::strstr(t, "T3[")) side_stats_.push_back(e.term_shape(t));
+    for (const char* t : kCCR1)
+      if (std::strstr(t, "T3[")) side_stats_.push_back(e.term_shape(t));
+    for (const char* t : kCCR2)
+      if (std::strstr(t, "T3[")) side_stats_.push_back(e.term_shape(t));
     e.prec = keep;
   }
   cc_ready = true;
@@ -341,10 +350,18 @@ void Context::residual_body(Prec tri) {
     // are FP64; the triples residual contractions run in the requested
     // precision and accumulate into the FP64 residual.
     e.fork_mark();
-    e.terms(kCCInter3, count(kCCInter3));
+    const bool side = side_ok(tri);
+    if (side) {
+      // T3 pieces of W3_vvvo / W3_ovoo from T3v, the other intermediates per term
+      for (const char* t : kCCInter3)
+        if (!std::strstr(t, "T3[")) e.term(t);
+      side_products();
+    } else {
+      e.terms(kCCInter3, count(kCCInter3));
+    }
     e.prec = tri;
     if (fused_r3_ok() && tri != Prec::BF16X3)  // split-BF16 products run per term
-      r3_fused(tri);
+      r3_fused(tri, side);
     else
       e.terms(kCCR3, count(kCCR3));
     e.prec = Prec::FP64;
@@ -355,11 +372,55 @@ void Context::residual_body(Prec tri) {
     for (const char* t : kCCR2) (std::strstr(t, "T3[") ? late.push_back(t) : e.term(t));
     e.end_side();
     e.join_side();
-    for (const char* t : late) e.term(t);
+    if (side)
+      side_r12();
+    else
+      for (const char* t : late) e.term(t);
   }
   e.prec = tri;
   e.record = false;
   tally_flops();
+}
+
+bool Context::side_ok(Prec tri) const { return tri == Prec::FP64 && side_buf_ != nullptr && fused_r3_ok(); }
+
+// T3v (FP64) first, then the integral rows, the NT / NN products and the
+// W3_vvvo / W3_ovoo T3 pieces (triples_side.hpp); the R1 / R2 gathers wait for
+// the side lane (side_r12).  The packed-GEMM flops of the replaced terms are
+// recorded as the per-term path would record them.
+void Context::side_products() {
+  Engine& e = *eng;
+  const int o = nocc, v = nvir;
+  const SideShape& sh = side_sh_;
+  double* T3 = amp_ + tblocks_[2].offset;
+  e.timed_launch("fno::r3_t3v_kernel", "T3v", 0,
+                 8.0 * (double)tblocks_[2].size + 8.0 * (double)r3_fused_t3v_elems(o, v),
+                 [&]() { launch_r3_t3v(e.tables, o, v, T3, r3_t3v_, Prec::FP64, e.stream); });
+  e.timed_launch("fno::side_operands_kernel", "side T3 terms: integral rows", 0,
+                 8.0 * (double)(sh.a2 + (int64_t)sh.nt * sh.mt2 * 64 * sh.ep),
+                 [&]() { launch_side_operands(e.tables, sh, e.get("Gd")->d, e.get("Fd")->d, side_buf_, e.stream); });
+  double fl = 0;
+  for (auto& st : side_stats_) fl += st.flops;
+  e.timed_launch("fno::side_nt_kernel + side_nn_kernel", "side T3 terms: products", fl,
+                 8.0 * (double)(r3_fused_y_elems(o, v) + sh.o2 - sh.s + (sh.total - sh.o2)),
+                 [&]() { launch_side_products(e.tables, sh, (const double*)r3_t3v_, side_buf_, e.stream); });
+  e.timed_launch("fno::side_w3_kernel", "side T3 terms: W3_vvvo, W3_ovoo", 0,
+                 8.0 * (double)(sh.total - sh.wp) + 16.0 * o * v * (sh.nv2 + sh.no2),
+                 [&]() { launch_side_w3(e.tables, sh, side_buf_, e.get("W3_vvvo")->d, e.get("W3_ovoo")->d,
+                                        e.stream); });
+  if (e.record)
+    for (auto& st : side_stats_) e.stats.push_back(st);
+}
+
+void Context::side_r12() {
+  Engine& e = *eng;
+  const SideShape& sh = side_sh_;
+  e.timed_launch("fno::side_r12_kernel", "side T3 terms: R1, R2", 0,
+                 8.0 * (double)(sh.wp - sh.o2) + 16.0 * ((double)sh.no2 * sh.nv2 + nocc * nvir),
+                 [&]() {
+                   launch_side_r12(e.tables, sh, side_buf_, res_ + tblocks_[0].offset, res_ + tblocks_[1].offset,
+                                   e.stream);
+                 });
 }
 
 bool Context::fused_r3_ok() const {
@@ -371,7 +432,7 @@ bool Context::fused_r3_ok() const {
 // other term in one fused GEMM, the P(a/bc) fold of Y into R3, and
 // R3 += C T3.  The packed-GEMM flops of the replaced terms are recorded as
 // the per-term path would record them.
-void Context::r3_fused(Prec tri) {
+void Context::r3_fused(Prec tri, bool t3v_ready) {
   Engine& e = *eng;
   const int o = nocc, v = nvir;
   const int nt = (int)binom_host(o, 3), nv3 = (int)binom_host(v, 3);
@@ -379,10 +440,11 @@ void Context::r3_fused(Prec tri) {
   double* R3 = res_ + tblocks_[2].offset;
   const double bytes_t3 = 8.0 * (double)tblocks_[2].size;
   const double esz = tri == Prec::FP64 ? 8.0 : 4.0;
-  e.timed_launch("fno::r3_t3v_kernel + r3_wt_kernel", "R3 fused: T3v and W3_vvvv^T", 0,
-                 bytes_t3 + esz * (double)(r3_fused_y_elems(o, v) + r3_fused_wt_elems(v)) +
-                     8.0 * (double)r3_fused_wt_elems(v),
-                 [&]() { launch_r3_operands(e.tables, o, v, T3, e.get("W3_vvvv")->d, r3_t3v_, r3_wt_, tri, e.stream); });
+  if (!t3v_ready)
+    e.timed_launch("fno::r3_t3v_kernel", "R3 fused: T3v", 0, bytes_t3 + esz * (double)r3_fused_t3v_elems(o, v),
+                   [&]() { launch_r3_t3v(e.tables, o, v, T3, r3_t3v_, tri, e.stream); });
+  e.timed_launch("fno::r3_wt_kernel", "R3 fused: W3_vvvv^T", 0, (8.0 + esz) * (double)r3_fused_wt_elems(v),
+                 [&]() { launch_r3_wt(v, e.get("W3_vvvv")->d, r3_wt_, tri, e.stream); });
   e.timed_launch("fno::r3_ring_operand_kernel", "R3 fused: W3_ovvo rearranged", 0, 16.0 * o * v * o * v,
                  [&]() {
                    launch_r3_ring_operand(e.get("W3_ovvo")->d, e.get("F3_vv")->d, o, v, r3_aring_, r3_fvvp_,

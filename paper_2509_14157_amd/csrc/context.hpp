@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "engine.hpp"
+#include "triples_side.hpp"
 
 namespace fno {
 
@@ -115,7 +116,7 @@ class Context {
   void residual(bool defer_timers = false);
   void residual_body(Prec tri);
   bool fused_r3_ok() const;
-  void r3_fused(Prec tri);
+  void r3_fused(Prec tri, bool t3v_ready);
   double* r3_y_ = nullptr;      // per-triple products Y_t (FP64-sized; FP32 modes use half)
   double* r3_c_ = nullptr;      // occupied-only operator, C(o,3) x C(o,3)
   double* r3_aring_ = nullptr;  // W3_ovvo rearranged for the ring segments
@@ -123,6 +124,14 @@ class Context {
   double* r3_wt_ = nullptr;     // W3_vvvv transposed (FP64-sized)
   double* r3_fvvp_ = nullptr;   // F3_vv padded
   std::vector<GemmStats> r3_stats_;  // packed-GEMM flops of the replaced terms
+  // T3 terms of the intermediates and of R1 / R2 from the FP64 T3v
+  // (triples_side.hpp), used with FP64 triples products
+  bool side_ok(Prec tri) const;
+  void side_products();
+  void side_r12();
+  SideShape side_sh_{};
+  double* side_buf_ = nullptr;
+  std::vector<GemmStats> side_stats_;
   void plain_guess();
   double t3_rms(const double* x);
   void learned_t3(const double* x, double sx, double* t3, double* den3);

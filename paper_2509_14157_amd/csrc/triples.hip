@@ -544,23 +544,35 @@ void launch_r3_ring_operand(const double* Wovvo, const double* Fvv, int o, int v
   FNO_HIP(hipGetLastError());
 }
 
-void launch_r3_operands(const IndexTables& tb, int o, int v, const double* T3, const double* Wvvvv, void* T3v,
-                        void* WT, Prec prec, hipStream_t s) {
+void launch_r3_t3v(const IndexTables& tb, int o, int v, const double* T3, void* T3v, Prec prec, hipStream_t s) {
   const int nv2 = (int)binom_host(v, 2), nv3 = (int)binom_host(v, 3);
   const int64_t ldy = r3_fused_ldy(v), rows = (int64_t)binom_host(o, 3) * v;
-  const int64_t rows_all = r3_fused_t3v_elems(o, v) / ldy, wrows_all = r3_fused_wt_elems(v) / ldy;
+  const int64_t rows_all = r3_fused_t3v_elems(o, v) / ldy;
   const int64_t blocks = rows_all * ((ldy + 255) / 256);
-  const int64_t tiles = (ldy + 31) / 32, wblocks = ((wrows_all + 31) / 32) * tiles;
-  if (prec == Prec::FP64) {
+  if (prec == Prec::FP64)
     r3_t3v_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
                                                                  (double*)T3v);
-    r3_wt_kernel<double><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (double*)WT);
-  } else {
+  else
     r3_t3v_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
                                                                 (float*)T3v);
-    r3_wt_kernel<float><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (float*)WT);
-  }
   FNO_HIP(hipGetLastError());
+}
+
+void launch_r3_wt(int v, const double* Wvvvv, void* WT, Prec prec, hipStream_t s) {
+  const int nv2 = (int)binom_host(v, 2);
+  const int64_t ldy = r3_fused_ldy(v), wrows_all = r3_fused_wt_elems(v) / ldy;
+  const int64_t tiles = (ldy + 31) / 32, wblocks = ((wrows_all + 31) / 32) * tiles;
+  if (prec == Prec::FP64)
+    r3_wt_kernel<double><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (double*)WT);
+  else
+    r3_wt_kernel<float><<<dim3((unsigned)wblocks), 256, 0, s>>>(nv2, ldy, wrows_all, Wvvvv, (float*)WT);
+  FNO_HIP(hipGetLastError());
+}
+
+void launch_r3_operands(const IndexTables& tb, int o, int v, const double* T3, const double* Wvvvv, void* T3v,
+                        void* WT, Prec prec, hipStream_t s) {
+  launch_r3_t3v(tb, o, v, T3, T3v, prec, s);
+  launch_r3_wt(v, Wvvvv, WT, prec, s);
 }
 
 void launch_r3_occ_operator(const IndexTables& tb, int o, const double* Woooo, const double* Foo, double* C,

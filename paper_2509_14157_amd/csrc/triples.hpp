@@ -52,7 +52,10 @@ int64_t r3_fused_t3v_elems(int o, int v);  // with the padding the fused kernel 
 int64_t r3_fused_wt_elems(int v);
 int64_t r3_fused_ldy(int v);
 int64_t r3_fvv_padded_elems(int v);
-// T3v and WT (above) from T3 and W3_vvvv, in the compute type of prec
+// T3v and WT (above) from T3 and W3_vvvv, in the compute type of prec,
+// together or one at a time
+void launch_r3_t3v(const IndexTables& tb, int o, int v, const double* T3, void* T3v, Prec prec, hipStream_t s);
+void launch_r3_wt(int v, const double* Wvvvv, void* WT, Prec prec, hipStream_t s);
 void launch_r3_operands(const IndexTables& tb, int o, int v, const double* T3, const double* Wvvvv, void* T3v,
                         void* WT, Prec prec, hipStream_t s);
 // Y = the products above for every triple (all of Y is written).
