@@ -168,6 +168,62 @@ void Context::setup_cc() {
 // X[a,i] = -t_i^a), annihilation indices with Y = 1 + t1 (Y[a,i] = t_i^a).
 // Each of the four index transformations is one GEMM that rotates the
 // contracted index to the back, so all operands are used in place.
+// All four slots on Gd (already a copy of G): slots 0 and 3 as GEMMs, 1 and
+// 2 as strided passes.
+void Context::dress_gemm_slots(double* gd, const double* t1) {
+  Engine& e = *eng;
+  const int n = nocc + nvir;
+  const int64_t n3 = (int64_t)n * n * n;
+  // slot 0 is a plain GEMM: Gd[a, :] -= sum_i t1[i][a] Gd[i, :]  (v x n^3, K = o)
+  GemmArgs s0{};
+  s0.prec = Prec::FP64;
+  s0.M = nvir;
+  s0.N = n3;
+  s0.K = nocc;
+  s0.A = t1;
+  s0.lda = nvir;
+  s0.a_kfast = false;
+  s0.B = gd;
+  s0.ldb = n3;
+  s0.b_nfast = true;
+  s0.C = gd + (int64_t)nocc * n3;
+  s0.ldc = n3;
+  s0.alpha = -1.0;
+  s0.beta = 1.0;
+  s0.tile = -1;
+  s0.split = 1;
+  launch_gemm(s0, e.stream);
+  // slots 1 and 2: strided slices, one thread per position of the other slots
+  launch_dress_pass(gd, t1, nocc, nvir, 1, true, e.stream);
+  launch_dress_pass(gd, t1, nocc, nvir, 2, false, e.stream);
+  dress_last_slot(gd, t1);
+}
+
+// slot 3: a plain GEMM on the rows of Gd: Gd[:, i] += sum_a Gd[:, a] t1[i][a]  (n^3 x o, K = v)
+void Context::dress_last_slot(double* gd, const double* t1) {
+  Engine& e = *eng;
+  const int n = nocc + nvir;
+  const int64_t n3 = (int64_t)n * n * n;
+  GemmArgs s3{};
+  s3.prec = Prec::FP64;
+  s3.M = n3;
+  s3.N = nocc;
+  s3.K = nvir;
+  s3.A = gd + nocc;
+  s3.lda = n;
+  s3.a_kfast = true;
+  s3.B = t1;
+  s3.ldb = nvir;
+  s3.b_nfast = false;
+  s3.C = gd;
+  s3.ldc = n;
+  s3.alpha = 1.0;
+  s3.beta = 1.0;
+  s3.tile = -1;
+  s3.split = 1;
+  launch_gemm(s3, e.stream);
+}
+
 void Context::dress() {
   Engine& e = *eng;
   const int n = nocc + nvir;
@@ -181,50 +237,17 @@ void Context::dress() {
   // in-place update of one slice (K = o for X, K = v for Y)
   Tensor* gd = e.get("Gd");
   Tensor* g0 = e.get("G");
-  FNO_HIP(hipMemcpyAsync(gd->d, g0->d, (size_t)g0->elems * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
   const double* t1 = e.get("T1")->d;  // t1[i][a], o x v
-  const int64_t n3 = (int64_t)n * n * n;
-  // slot 0 is a plain GEMM: Gd[a, :] -= sum_i t1[i][a] Gd[i, :]  (v x n^3, K = o)
-  GemmArgs s0{};
-  s0.prec = Prec::FP64;
-  s0.M = nvir;
-  s0.N = n3;
-  s0.K = nocc;
-  s0.A = t1;
-  s0.lda = nvir;
-  s0.a_kfast = false;
-  s0.B = gd->d;
-  s0.ldb = n3;
-  s0.b_nfast = true;
-  s0.C = gd->d + (int64_t)nocc * n3;
-  s0.ldc = n3;
-  s0.alpha = -1.0;
-  s0.beta = 1.0;
-  s0.tile = -1;
-  s0.split = 1;
-  launch_gemm(s0, e.stream);
-  // slots 1 and 2: strided slices, one thread per position of the other slots
-  launch_dress_pass(gd->d, t1, nocc, nvir, 1, true, e.stream);
-  launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
-  // slot 3 is a plain GEMM on the rows of Gd: Gd[:, i] += sum_a Gd[:, a] t1[i][a]  (n^3 x o, K = v)
-  GemmArgs s3{};
-  s3.prec = Prec::FP64;
-  s3.M = n3;
-  s3.N = nocc;
-  s3.K = nvir;
-  s3.A = gd->d + nocc;
-  s3.lda = n;
-  s3.a_kfast = true;
-  s3.B = t1;
-  s3.ldb = nvir;
-  s3.b_nfast = false;
-  s3.C = gd->d;
-  s3.ldc = n;
-  s3.alpha = 1.0;
-  s3.beta = 1.0;
-  s3.tile = -1;
-  s3.split = 1;
-  launch_gemm(s3, e.stream);
+  if (launch_dress_first_slot(g0->d, gd->d, t1, nocc, nvir, e.stream)) {
+    // slot 0 done with the copy; slots 1 and 2 are strided passes (one
+    // thread per position of the other slots), slot 3 a GEMM on the rows
+    launch_dress_pass(gd->d, t1, nocc, nvir, 1, true, e.stream);
+    launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
+    dress_last_slot(gd->d, t1);
+  } else {
+    FNO_HIP(hipMemcpyAsync(gd->d, g0->d, (size_t)g0->elems * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
+    dress_gemm_slots(gd->d, t1);
+  }
   // f^ = X h Y + sum_i g^[p i q i]
   e.zero(e.get("Ftmp"));
   e.zero(e.get("Fd"));

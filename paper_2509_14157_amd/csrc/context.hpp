@@ -117,6 +117,8 @@ class Context {
   void residual_body(Prec tri);
   bool fused_r3_ok() const;
   void r3_fused(Prec tri, bool t3v_ready);
+  void dress_gemm_slots(double* gd, const double* t1);
+  void dress_last_slot(double* gd, const double* t1);
   double* r3_y_ = nullptr;      // per-triple products Y_t (FP64-sized; FP32 modes use half)
   double* r3_c_ = nullptr;      // occupied-only operator, C(o,3) x C(o,3)
   double* r3_aring_ = nullptr;  // W3_ovvo rearranged for the ring segments

@@ -1022,6 +1022,7 @@ __global__ void __launch_bounds__(256) dress_pass_kernel(double* __restrict__ g,
 // reads its source slice once and produces every target of the slot (the
 // occupied side, at most kDressMaxOcc values, lives in registers).
 constexpr int kDressMaxOcc = 32;
+template <int MAXO>
 __global__ void __launch_bounds__(256) dress_slice_kernel(double* __restrict__ g, const double* __restrict__ t1,
                                                           int nocc, int nvir, int64_t inner, int creation,
                                                           int64_t total) {
@@ -1030,33 +1031,73 @@ __global__ void __launch_bounds__(256) dress_slice_kernel(double* __restrict__ g
     const int64_t in = e % inner;
     const int64_t outer = e / inner;
     double* base = g + outer * n * inner + in;
-    double occ[kDressMaxOcc];
+    double occ[MAXO];
     if (creation) {
       // g[a] -= sum_i t1[i][a] g[i]
 #pragma unroll
-      for (int i = 0; i < kDressMaxOcc; ++i) occ[i] = i < nocc ? base[(int64_t)i * inner] : 0.0;
+      for (int i = 0; i < MAXO; ++i) occ[i] = i < nocc ? base[(int64_t)i * inner] : 0.0;
       for (int a = 0; a < nvir; ++a) {
         double acc = 0.0;
 #pragma unroll
-        for (int i = 0; i < kDressMaxOcc; ++i)
+        for (int i = 0; i < MAXO; ++i)
           if (i < nocc) acc += t1[(int64_t)i * nvir + a] * occ[i];
         base[(int64_t)(nocc + a) * inner] -= acc;
       }
     } else {
       // g[i] += sum_a t1[i][a] g[a]
 #pragma unroll
-      for (int i = 0; i < kDressMaxOcc; ++i) occ[i] = 0.0;
+      for (int i = 0; i < MAXO; ++i) occ[i] = 0.0;
       for (int a = 0; a < nvir; ++a) {
         const double v = base[(int64_t)(nocc + a) * inner];
 #pragma unroll
-        for (int i = 0; i < kDressMaxOcc; ++i)
+        for (int i = 0; i < MAXO; ++i)
           if (i < nocc) occ[i] += t1[(int64_t)i * nvir + a] * v;
       }
 #pragma unroll
-      for (int i = 0; i < kDressMaxOcc; ++i)
+      for (int i = 0; i < MAXO; ++i)
         if (i < nocc) base[(int64_t)i * inner] += occ[i];
     }
   }
+}
+
+// First creation slot of the dressing fused with the copy from the undressed
+// integrals: Gd[i, :] = G[i, :], Gd[a, :] = G[a, :] - sum_i t1[i][a] G[i, :]
+// over the first index (rows of n^3 elements), one thread per column with
+// the o occupied values in registers.
+template <int MAXO>
+__global__ void __launch_bounds__(256) dress_first_slot_kernel(const double* __restrict__ G, double* __restrict__ Gd,
+                                                               const double* __restrict__ t1, int nocc, int nvir,
+                                                               int64_t n3) {
+  for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n3; c += (int64_t)gridDim.x * blockDim.x) {
+    double occ[MAXO];
+#pragma unroll
+    for (int i = 0; i < MAXO; ++i)
+      if (i < nocc) {
+        occ[i] = G[(int64_t)i * n3 + c];
+        Gd[(int64_t)i * n3 + c] = occ[i];
+      }
+    for (int a = 0; a < nvir; ++a) {
+      double acc = G[(int64_t)(nocc + a) * n3 + c];
+#pragma unroll
+      for (int i = 0; i < MAXO; ++i)
+        if (i < nocc) acc -= t1[(int64_t)i * nvir + a] * occ[i];
+      Gd[(int64_t)(nocc + a) * n3 + c] = acc;
+    }
+  }
+}
+
+bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s) {
+  if (nocc > kDressMaxOcc || nocc == 0 || nvir == 0) return false;
+  const int64_t n = nocc + nvir, n3 = n * n * n;
+  const unsigned blocks = (unsigned)std::min<int64_t>((n3 + 255) / 256, 65536);
+  if (nocc <= 8)
+    dress_first_slot_kernel<8><<<blocks, 256, 0, s>>>(G, Gd, t1, nocc, nvir, n3);
+  else if (nocc <= 16)
+    dress_first_slot_kernel<16><<<blocks, 256, 0, s>>>(G, Gd, t1, nocc, nvir, n3);
+  else
+    dress_first_slot_kernel<kDressMaxOcc><<<blocks, 256, 0, s>>>(G, Gd, t1, nocc, nvir, n3);
+  FNO_HIP(hipGetLastError());
+  return true;
 }
 
 void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos, bool creation, hipStream_t s) {
@@ -1068,7 +1109,13 @@ void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos,
     const int64_t total = outer * inner;
     if (total == 0 || nvir == 0 || nocc == 0) return;
     const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
-    dress_slice_kernel<<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, creation ? 1 : 0, total);
+    const int cr = creation ? 1 : 0;
+    if (nocc <= 8)
+      dress_slice_kernel<8><<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, cr, total);
+    else if (nocc <= 16)
+      dress_slice_kernel<16><<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, cr, total);
+    else
+      dress_slice_kernel<kDressMaxOcc><<<dim3((unsigned)blocks), 256, 0, s>>>(g, t1, nocc, nvir, inner, cr, total);
     FNO_HIP(hipGetLastError());
     return;
   }

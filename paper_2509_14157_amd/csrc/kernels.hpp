@@ -39,6 +39,9 @@ void launch_fold_tab(const FoldTab& t, const void* X, Prec xprec, double* out, d
                      hipStream_t s);
 // One slot of the T1 similarity transform of the integrals, in place (see kernels.hip).
 void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos, bool creation, hipStream_t s);
+// Gd = G with the first creation slot dressed (one streaming pass); false
+// (nothing launched) for more than 32 occupied orbitals
+bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s);
 // y_j = a * x_j for j < count, y_j = 0 for count <= j < rows (n elements each; y_j = y + j*ldy, x_j = x + j*ldx)
 void launch_scale_rows(double* y, int64_t ldy, const double* x, int64_t ldx, double a, int64_t n, int count, int rows,
                        hipStream_t s);

@@ -366,55 +366,65 @@ __global__ void __launch_bounds__(256) side_w3_kernel(IndexTables tb, SideShape 
 //                 + S[t][nto*64 + 64 p(m) + b][a] - S[t][nto*64 + 64 p(m) + a][b] )
 //             - sum_{m<n outside i} (-1)^p(i) O2[t(imn)][p(i)(o+1) + j][ab]
 //             + sum_{m<n outside j} (-1)^p(j) O2[t(jmn)][p(j)(o+1) + i][ab]
+// A block owns 64 consecutive outputs (R1 first, then R2); its four
+// wavefronts take every fourth m and every fourth pair mn, and the four
+// partial sums are added in a fixed order.
 __global__ void __launch_bounds__(256) side_r12_kernel(IndexTables tb, SideShape sh, const double* __restrict__ buf,
                                                        double* __restrict__ R1, double* __restrict__ R2) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double part[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
   const int o = sh.o, v = sh.v;
   const double* S = buf + sh.s;
   const double* O2 = buf + sh.o2;
   const uint8_t* d2 = tb.dec[2];
-  const int64_t n1 = (int64_t)o * v;
+  const int64_t n1 = (int64_t)o * v, n2 = (int64_t)sh.no2 * sh.nv2;
+  double acc = 0;
   if (idx < n1) {
     const int i = (int)(idx / v), a = (int)(idx % v);
-    double acc = 0;
-    for (int q = 0; q < sh.no2; ++q) {
+    for (int q = w; q < sh.no2; q += 4) {
       const int m = d2[2 * q], n = d2[2 * q + 1];
       if (m == i || n == i) continue;
       int s;
       const int rank = tri_rank(i, m, n, s);
       acc += s * S[((int64_t)rank * sh.mts * 64 + q) * 64 + a];
     }
-    R1[idx] += acc;
-    return;
-  }
-  idx -= n1;
-  if (idx >= (int64_t)sh.no2 * sh.nv2) return;
-  const int ij = (int)(idx / sh.nv2), ab = (int)(idx % sh.nv2);
-  const int i = d2[2 * ij], j = d2[2 * ij + 1], a = d2[2 * ab], b = d2[2 * ab + 1];
-  const int64_t ldy = sh.ldy;
-  double acc = 0;
-  for (int m = 0; m < o; ++m) {
-    if (m == i || m == j) continue;
-    int s;
-    const int rank = tri_rank(m, i, j, s);
-    const int p = position(m, i, j);
-    const double* St = S + ((int64_t)rank * sh.mts * 64 + sh.nto * 64 + 64 * p) * 64;
-    acc += s * (O2[((int64_t)rank * sh.rows2 + p * (o + 1) + o) * ldy + ab] + St[b * 64 + a] - St[a * 64 + b]);
-  }
-  for (int q = 0; q < sh.no2; ++q) {
-    const int m = d2[2 * q], n = d2[2 * q + 1];
-    if (m != i && n != i) {
+  } else if (idx < n1 + n2) {
+    const int64_t r2 = idx - n1;
+    const int ij = (int)(r2 / sh.nv2), ab = (int)(r2 % sh.nv2);
+    const int i = d2[2 * ij], j = d2[2 * ij + 1], a = d2[2 * ab], b = d2[2 * ab + 1];
+    const int64_t ldy = sh.ldy;
+    for (int m = w; m < o; m += 4) {
+      if (m == i || m == j) continue;
       int s;
-      const int rank = tri_rank(i, m, n, s);
-      acc -= s * O2[((int64_t)rank * sh.rows2 + position(i, m, n) * (o + 1) + j) * ldy + ab];
+      const int rank = tri_rank(m, i, j, s);
+      const int p = position(m, i, j);
+      const double* St = S + ((int64_t)rank * sh.mts * 64 + sh.nto * 64 + 64 * p) * 64;
+      acc += s * (O2[((int64_t)rank * sh.rows2 + p * (o + 1) + o) * ldy + ab] + St[b * 64 + a] - St[a * 64 + b]);
     }
-    if (m != j && n != j) {
-      int s;
-      const int rank = tri_rank(j, m, n, s);
-      acc += s * O2[((int64_t)rank * sh.rows2 + position(j, m, n) * (o + 1) + i) * ldy + ab];
+    for (int q = w; q < sh.no2; q += 4) {
+      const int m = d2[2 * q], n = d2[2 * q + 1];
+      if (m != i && n != i) {
+        int s;
+        const int rank = tri_rank(i, m, n, s);
+        acc -= s * O2[((int64_t)rank * sh.rows2 + position(i, m, n) * (o + 1) + j) * ldy + ab];
+      }
+      if (m != j && n != j) {
+        int s;
+        const int rank = tri_rank(j, m, n, s);
+        acc += s * O2[((int64_t)rank * sh.rows2 + position(j, m, n) * (o + 1) + i) * ldy + ab];
+      }
     }
   }
-  R2[idx] += acc;
+  part[w][lane] = acc;
+  __syncthreads();
+  if (w == 0 && idx < n1 + n2) {
+    const double sum = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
+    if (idx < n1)
+      R1[idx] += sum;
+    else
+      R2[idx - n1] += sum;
+  }
 }
 
 int64_t up32(int64_t x) { return (x + 31) / 32 * 32; }
@@ -520,7 +530,7 @@ void launch_side_w3(const IndexTables& tb, const SideShape& sh, const double* bu
 void launch_side_r12(const IndexTables& tb, const SideShape& sh, const double* buf, double* R1, double* R2,
                      hipStream_t s) {
   const int64_t n = (int64_t)sh.o * sh.v + (int64_t)sh.no2 * sh.nv2;
-  side_r12_kernel<<<blocks_for(n), 256, 0, s>>>(tb, sh, buf, R1, R2);
+  side_r12_kernel<<<dim3((unsigned)((n + 63) / 64)), 256, 0, s>>>(tb, sh, buf, R1, R2);
   FNO_HIP(hipGetLastError());
 }
 
