@@ -360,8 +360,8 @@ def bench_learned(args, samples_per_run=16384, steps=3000, batch=4096, lr=1e-3):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="fp64", choices=list(PEAK_TFLOPS))
     ap.add_argument("--occt", type=float, default=0.99)
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -727,8 +727,8 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     he[i] = hist + (int64_t)(std::max(m, 1) + i) * nt_;
   }
   double* dcoef = alloc(32);
-  std::vector<int> order;   // history slots, oldest first
-  std::vector<double> B(16 * 16, 0.0);  // error overlaps indexed by slot
+  double* dB = alloc(16 * 16);  // error overlaps indexed by slot
+  std::vector<int> order;       // history slots, oldest first
   double e_old = energy();
   double rnorm = INFINITY, de = 0;
   trace_e.clear();
@@ -809,57 +809,37 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     order.push_back(slot);
     launch_axpby(ht[slot], amp_, 1.0, 0.0, nt_, e.stream);
     launch_jacobi(ht[slot], res_, den_, he[slot], nt_, e.stream);
-    // |r|^2 and every overlap <e_slot|e_s> in two launches and one transfer
+    // |r|^2 and every overlap <e_slot|e_s> in two launches; the DIIS system
+    // is solved on the device, so the host does not wait here: it reads
+    // |r|^2 with the energy, after the next residual has been enqueued
     launch_dots(res_, nt_, 1, res_, nt_, scratch_, dres, e.stream);
     if (m > 0) launch_dots(he[0], nt_, (int)order.size() > 0 ? mm : 0, he[slot], nt_, scratch_, dres + 2, e.stream);
-    double hv[2 + 16];
-    FNO_HIP(hipMemcpyAsync(hv, dres, (2 + (m > 0 ? mm : 0)) * sizeof(double), hipMemcpyDeviceToHost, e.stream));
-    FNO_HIP(hipStreamSynchronize(e.stream));
-    e.flush_timers(cc_prog_);  // a sweep launched ahead has finished: read its timers
-    rnorm = std::sqrt(hv[0]);
-    if (!std::isfinite(rnorm)) {
-      e.prec = Prec::FP64;
-      restore_den();
-      release_guess();
-      throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
-    }
-    bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
+    FNO_HIP(hipMemcpyAsync(pinned() + 1, dres, sizeof(double), hipMemcpyDeviceToHost, e.stream));
+    const bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
     if (m > 0) {
-      for (int s : order) B[slot * 16 + s] = B[s * 16 + slot] = hv[2 + s];
+      DiisSlots ds;
+      ds.k = (int)order.size();
+      for (int a = 0; a < ds.k; ++a) ds.slot[a] = order[a];
+      launch_diis(dB, dres + 2, slot, ds, extrap, mm, dcoef, e.stream);
     }
-    if (extrap) {
-      const int k = (int)order.size();
-      std::vector<double> A((size_t)(k + 1) * (k + 1), -1.0), rhs(k + 1, 0.0);
-      double scale = 0;
-      for (int a = 0; a < k; ++a) scale = std::max(scale, std::fabs(B[order[a] * 16 + order[a]]));
-      if (scale == 0) scale = 1;
-      for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) A[(size_t)a * (k + 1) + b] = B[order[a] * 16 + order[b]] / scale;
-      A[(size_t)k * (k + 1) + k] = 0.0;
-      rhs[k] = -1.0;
-      if (solve(k + 1, A, rhs)) {
-        // combine in slot order: coefficients c[slot]
-        // coefficients in slot order, staged in pinned memory: the copy runs
-        // after the host has moved on, and the buffer is next written only
-        // after the following iteration's synchronization
-        double* c = pinned() + 1;
-        const int nc = std::max(m, 1);
-        for (int a = 0; a < nc; ++a) c[a] = 0.0;
-        for (int a = 0; a < k; ++a) c[order[a]] = rhs[a];
-        FNO_HIP(hipMemcpyAsync(dcoef, c, nc * sizeof(double), hipMemcpyHostToDevice, e.stream));
-        launch_combine(amp_, ht[0], nt_, dcoef, nc, 1.0, 0.0, nt_, e.stream);
-      } else {
-        launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
-      }
-    } else {
+    if (extrap)
+      launch_combine(amp_, ht[0], nt_, dcoef, mm, 1.0, 0.0, nt_, e.stream);
+    else
       launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
-    }
     energy_async();
     if (it < opt.max_iter && !(opt.guess == 1 && it + 1 == 3)) {
       residual(true);
       ahead = true;
     }
     FNO_HIP(hipEventSynchronize(e_ready_));
+    rnorm = std::sqrt(host_pin_[1]);
+    if (!std::isfinite(rnorm)) {
+      FNO_HIP(hipStreamSynchronize(e.stream));
+      e.prec = Prec::FP64;
+      restore_den();
+      release_guess();
+      throw Error(kENONFINITE, "non-finite residual at iteration " + std::to_string(it));
+    }
     const double E = host_pin_[0];
     de = E - e_old;
     e_old = E;
@@ -890,9 +870,11 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   e.flush_timers(cc_prog_);
   owned_.erase(std::remove(owned_.begin(), owned_.end(), hist), owned_.end());
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dcoef), owned_.end());
+  owned_.erase(std::remove(owned_.begin(), owned_.end(), dB), owned_.end());
   owned_.erase(std::remove(owned_.begin(), owned_.end(), dres), owned_.end());
   FNO_HIP(hipFree(hist));
   FNO_HIP(hipFree(dcoef));
+  FNO_HIP(hipFree(dB));
   FNO_HIP(hipFree(dres));
   e_corr = e_old;
   cc_done = true;

@@ -403,6 +403,99 @@ __global__ void __launch_bounds__(256) gemv_acc_kernel(double* __restrict__ y, c
   }
 }
 
+// DIIS step on the device (one workgroup): store the overlaps of the newest
+// error vector (history slot `slot`) with the vectors of the slots in use
+// into the overlap matrix B (16 x 16, by slot), and, when extrapolating, solve
+//   [ B/s  -1 ] [c]   [ 0]
+//   [ -1    0 ] [l] = [-1]     (s = the largest diagonal element)
+// over those slots by Gaussian elimination with partial pivoting, the
+// system in LDS and each elimination step's row updates spread over the
+// threads (every element is updated by the same operations as in a serial
+// elimination).  coef gets the coefficients by slot, or the unit vector of
+// `slot` when the system is singular (a pivot below 1e-300) or no
+// extrapolation is asked for.
+__global__ void __launch_bounds__(256) diis_kernel(double* __restrict__ B, const double* __restrict__ ov, int slot,
+                                                   DiisSlots ord, int extrap, int nc, double* __restrict__ coef) {
+  __shared__ double A[17][18], b[17], f[17];
+  __shared__ int fail, piv;
+  const int tid = threadIdx.x, k = ord.k, n = k + 1;
+  // B entries of the new slot come from ov; the others were stored before
+  auto bval = [&](int qa, int qb) {
+    return qa == slot ? ov[qb] : (qb == slot ? ov[qa] : B[qa * 16 + qb]);
+  };
+  if (extrap && k >= 1) {
+    double scale = 0;
+    for (int a = 0; a < k; ++a) scale = fmax(scale, fabs(bval(ord.slot[a], ord.slot[a])));
+    if (scale == 0) scale = 1;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+      const int r = e / n, c = e % n;
+      A[r][c] = (r < k && c < k) ? bval(ord.slot[r], ord.slot[c]) / scale : ((r == k && c == k) ? 0.0 : -1.0);
+    }
+    for (int r = tid; r < n; r += blockDim.x) b[r] = (r == k) ? -1.0 : 0.0;
+    if (tid == 0) fail = 0;
+    __syncthreads();
+    for (int c = 0; c < n; ++c) {
+      if (tid == 0) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+          if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (fabs(A[p][c]) < 1e-300) fail = 1;
+        piv = p;
+      }
+      __syncthreads();
+      if (fail) break;
+      const int p = piv;
+      if (p != c) {
+        for (int q = tid; q < n; q += blockDim.x) {
+          const double t = A[p][q];
+          A[p][q] = A[c][q];
+          A[c][q] = t;
+        }
+        if (tid == 0) {
+          const double t = b[p];
+          b[p] = b[c];
+          b[c] = t;
+        }
+      }
+      __syncthreads();
+      for (int r = c + 1 + tid; r < n; r += blockDim.x) f[r] = A[r][c] / A[c][c];
+      __syncthreads();
+      const int w = n - c;
+      for (int e = tid; e < (n - c - 1) * w; e += blockDim.x) {
+        const int r = c + 1 + e / w, q = c + e % w;
+        if (f[r] != 0) A[r][q] -= f[r] * A[c][q];
+      }
+      for (int r = c + 1 + tid; r < n; r += blockDim.x)
+        if (f[r] != 0) b[r] -= f[r] * b[c];
+      __syncthreads();
+    }
+    if (!fail && tid == 0) {
+      for (int r = n - 1; r >= 0; --r) {
+        double acc = b[r];
+        for (int q = r + 1; q < n; ++q) acc -= A[r][q] * b[q];
+        b[r] = acc / A[r][r];
+      }
+    }
+    __syncthreads();
+  }
+  const bool solved = extrap && k >= 1 && !fail;
+  for (int c = tid; c < nc; c += blockDim.x) coef[c] = solved ? 0.0 : (c == slot ? 1.0 : 0.0);
+  __syncthreads();
+  if (solved)
+    for (int a = tid; a < k; a += blockDim.x) coef[ord.slot[a]] = b[a];
+  for (int a = tid; a < k; a += blockDim.x) {
+    const int q = ord.slot[a];
+    B[slot * 16 + q] = ov[q];
+    B[q * 16 + slot] = ov[q];
+  }
+}
+
+void launch_diis(double* B, const double* ov, int slot, const DiisSlots& ord, bool extrap, int nc, double* coef,
+                 hipStream_t s) {
+  diis_kernel<<<1, 256, 0, s>>>(B, ov, slot, ord, extrap ? 1 : 0, nc, coef);
+  FNO_HIP(hipGetLastError());
+}
+
 void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, int nvec, double alpha, double beta,
                     int64_t n, hipStream_t s) {
   if (n == 0) return;

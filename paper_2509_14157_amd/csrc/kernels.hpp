@@ -57,6 +57,14 @@ void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial
                     double beta, hipStream_t s);
 void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64_t n, double* partial, double* out,
                  hipStream_t s);
+// History slots of a DIIS step, oldest first.
+struct DiisSlots {
+  int k = 0;
+  int slot[16] = {};
+};
+// The DIIS overlap update and coefficient solve on the device (kernels.hip).
+void launch_diis(double* B, const double* ov, int slot, const DiisSlots& ord, bool extrap, int nc, double* coef,
+                 hipStream_t s);
 void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, int nvec, double alpha, double beta,
                     int64_t n, hipStream_t s);
 
