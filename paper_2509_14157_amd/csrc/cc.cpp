@@ -494,8 +494,13 @@ void Context::r3_fused(Prec tri, bool t3v_ready) {
   for (auto& st : r3_stats_)
     if (st.term.find("W3_oooo") == std::string::npos && st.term.find("F3_oo") == std::string::npos) fl += st.flops;
   const double ybytes = (tri == Prec::FP64 ? 8.0 : 4.0) * (double)r3_fused_y_elems(o, v);
+  // algorithmic bytes: T3v read and Y written once, W3_vvvv^T (C(v,2) rows),
+  // the ring operand, W3_vvvo, W3_ovoo and T2 read once
+  const double no2 = (double)binom_host(o, 2), nv2 = (double)binom_host(v, 2);
+  const double fused_bytes = 2.0 * ybytes + esz * nv2 * (double)a.ldy +
+                             8.0 * ((double)r3_ring_operand_elems(o, v) + o * v * nv2 + o * v * no2 + no2 * nv2);
   e.timed_launch(tri == Prec::FP64 ? "fno::r3_fused_kernel<double>" : "fno::r3_fused_kernel<float>",
-                 "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, 2.0 * ybytes,
+                 "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, fused_bytes,
                  [&]() { launch_r3_fused(e.tables, a, tri, e.stream); });
   e.timed_launch("fno::r3_fold_kernel", "R3 fused: P(a/bc) fold", 0, 3.0 * ybytes / v + 2.0 * bytes_t3,
                  [&]() { launch_r3_fold(e.tables, o, v, r3_y_, a.ldy, tri, R3, e.stream); });
