@@ -366,6 +366,7 @@ def main():
     ap.add_argument("--occt", type=float, default=0.99)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 / split-BF16 section")
+    ap.add_argument("--no-xfno", action="store_true", help="skip the XFNO section")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default GEMM tiles instead of timing every tile on the first launch of a shape")
     ap.add_argument("--no-graphs", action="store_true",
@@ -515,6 +516,30 @@ def main():
                        for pr in ("fp64", "fp32", "bf16x3")) +
              f"; dE fp32 {mixed['fp32']['energy_minus_fp64']:.2e}, bf16x3 {mixed['bf16x3']['energy_minus_fp64']:.2e}")
 
+    # XFNO: FNO-CCSDT and the two lowest IP roots at the paper's three
+    # thresholds on the same o=10, v_full=60 generator with integrals that
+    # decay over the virtuals (so the thresholds keep different counts),
+    # and the linear extrapolation to OCCT = 1
+    xf = {}
+    if args.prec == "fp64" and not args.no_xfno:
+        import paper_2509_14157_amd as P
+        from synthetic import CONFIGS, make_hamiltonian
+        c2 = CONFIGS["C2"]
+        hx = make_hamiltonian(c2["nocc"], c2["nvir"], c2["seed"], evir=c2["evir"], decay=24.0)
+        cx = P.Context(0)
+        cx.load_hamiltonian(hx.fock, hx.eri, hx.nocc)
+        occts = [0.995, 0.9975, 0.999]
+        t0 = time.perf_counter()
+        rx = cx.xfno(occts, kind="IP", nroots=2, allow_noconv=True)
+        wall = time.perf_counter() - t0
+        cx.close()
+        xf = {"workload": "o=10, v_full=60, seed 2, virtual energies U[0.2,6], integrals decaying as exp(-a/24) "
+                          "over the virtuals; FNO-CCSDT + 2 IP roots at each OCCT",
+              "occt": occts, "kept": rx["kept"], "e_cc": [round(x, 10) for x in rx["e_cc"]],
+              "e_cc_extrapolated": round(rx["e_cc_x"], 10), "e_ip_extrapolated": [round(x, 10) for x in rx["e_eom_x"]],
+              "converged": rx["converged"], "seconds": round(wall, 3)}
+        _log(f"[bench] XFNO kept {rx['kept']}, E {rx['e_cc_x']:.8f} (extrapolated) in {wall:.2f} s")
+
     cpu = None
     if not args.no_cpu_baseline:
         _log("[bench] timing the CPU oracle on a bounded sample")
@@ -546,6 +571,7 @@ def main():
         "tuned_tiles": wrep.get("tuned", {}),
         "gpu_busy_frac": round(kernel_ms_iter / (1e3 * s_iter), 4),
         "mixed": mixed,
+        "xfno": xf,
         "energy": res["e_tot"],
     }
     print(json.dumps(line), flush=True)

@@ -156,6 +156,38 @@ int fno_eom(fno_ctx *ctx, fno_eom_kind kind, const fno_eom_opts *opts, double *o
 int fno_batch_eom(int n, fno_ctx *const *ctxs, fno_eom_kind kind, const fno_eom_opts *opts, double *omega,
                   double *res_norm, int *iters);
 
+/*
+ * MP2 correlation energies (eqs 8-9) of the full virtual space and of the
+ * truncated space of the last fno_truncate (the kept semicanonical
+ * natural orbitals).  Either output may be NULL.
+ * Errors: FNO_ESTATE before fno_truncate.
+ */
+int fno_mp2_energies(const fno_ctx *ctx, double *e_full, double *e_trunc);
+
+/*
+ * Extrapolated FNO (XFNO, Computational Details: the M3 values of the result
+ * tables).  At each of npts occupation thresholds the problem is truncated
+ * (fno_truncate), the ground state solved (fno_ccsdt) and, when kind is an
+ * fno_eom_kind, nroots target states found (fno_eom); every total energy is
+ * then fitted by a least-squares line in OCCT and the line evaluated at
+ * OCCT = 1.  The paper computes its M3 values from the thresholds 0.999,
+ * 0.9975 and 0.995 and leaves the extrapolation formula to its supplement;
+ * the linear fit in OCCT is this library's reading of it.
+ *   occt    : npts distinct thresholds in (0, 1], 2 <= npts <= 16.
+ *   cc, eom : solver options (NULL = defaults); kind = 0 skips the EOM part.
+ *   kept    : out, npts kept virtual counts (may be NULL).
+ *   e_cc    : out, npts ground-state total energies.
+ *   e_eom   : out, npts x nroots target total energies, threshold-major (kind != 0).
+ *   e_cc_x, e_eom_x : out, the extrapolated ground-state and nroots target
+ *             total energies.
+ * The context is left truncated at the last threshold, holding its solution.
+ * Errors: FNO_EINVAL (thresholds, outputs), those of fno_truncate, fno_ccsdt
+ * and fno_eom; FNO_ENOCONV when a solve did not converge (with kind != 0 a
+ * ground state that did not converge stops the run).
+ */
+int fno_xfno(fno_ctx *ctx, int npts, const double *occt, const fno_cc_opts *cc, int kind, const fno_eom_opts *eom,
+             int *kept, double *e_cc, double *e_eom, double *e_cc_x, double *e_eom_x);
+
 /* Orbital-space sizes of the current problem (after truncation). */
 int fno_sizes(const fno_ctx *ctx, int *nocc, int *nvir, int *nvir_full);
 

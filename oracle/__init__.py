@@ -8,5 +8,6 @@ implementation of what the GPU library computes and shares no code with it:
 * ``wick`` -- Wick's-theorem expansion of eq (5) and of the EOM sigma vectors;
 * ``cc``   -- CCSDT residuals/energy, Jacobi+DIIS, EOM sigma, Davidson, dense EOM;
 * ``fno``  -- MP2 amplitudes, virtual density and FNO truncation (eqs 8-10);
-* ``mlp``  -- the learned-guess network (forward, backpropagation) and its training data.
+* ``mlp``  -- the learned-guess network (forward, backpropagation) and its training data;
+* ``xfno`` -- XFNO: FNO energies at several thresholds and their linear extrapolation.
 """

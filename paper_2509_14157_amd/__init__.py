@@ -20,7 +20,7 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 
 # exported C symbols (kept in sync with include/fnocc.h)
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
-           "fno_truncate", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
+           "fno_truncate", "fno_mp2_energies", "fno_xfno", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
            "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
            "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error",
@@ -67,6 +67,9 @@ def library() -> C.CDLL:
         lib.fno_set_stream.argtypes = [C.c_void_p, C.c_void_p]
         lib.fno_load_hamiltonian.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_double]
         lib.fno_truncate.argtypes = [C.c_void_p, C.c_double, C.c_int, C.POINTER(C.c_int), dp, dp]
+        lib.fno_mp2_energies.argtypes = [C.c_void_p, dp, dp]
+        lib.fno_xfno.argtypes = [C.c_void_p, C.c_int, dp, C.POINTER(CCOpts), C.c_int, C.POINTER(EOMOpts),
+                                 C.POINTER(C.c_int), dp, dp, dp, dp]
         lib.fno_cc_opts_default.argtypes = [C.POINTER(CCOpts)]
         lib.fno_cc_opts_default.restype = None
         lib.fno_ccsdt.argtypes = [C.c_void_p, C.POINTER(CCOpts), dp, dp, C.POINTER(C.c_int), dp]
@@ -200,6 +203,34 @@ class Context:
         self._check(self._lib.fno_truncate(self._h, float(occt), int(nvir_keep), C.byref(kept), C.byref(emp2),
                                            _dp(occ)))
         return kept.value, emp2.value, occ
+
+    def mp2_energies(self):
+        """(E_MP2 of the full space, E_MP2 of the truncated space) of the last truncation."""
+        ef, et = C.c_double(), C.c_double()
+        self._check(self._lib.fno_mp2_energies(self._h, C.byref(ef), C.byref(et)))
+        return ef.value, et.value
+
+    def xfno(self, occts, kind=None, nroots=2, cc_max_iter=100, r_tol=1e-8, e_tol=1e-10, eom_e_tol=1e-8,
+             eom_r_tol=1e-6, eom_max_iter=60, allow_noconv=False):
+        """fno_xfno: ground-state (and, with kind, EOM target) total energies at each
+        threshold and their linear extrapolation to OCCT = 1."""
+        x = np.ascontiguousarray(occts, dtype=np.float64)
+        n = len(x)
+        co = CCOpts()
+        self._lib.fno_cc_opts_default(C.byref(co))
+        co.max_iter, co.r_tol, co.e_tol = cc_max_iter, r_tol, e_tol
+        eo = EOMOpts()
+        self._lib.fno_eom_opts_default(C.byref(eo))
+        nr = nroots if kind else 0
+        eo.nroots, eo.e_tol, eo.r_tol, eo.max_iter = max(nr, 1), eom_e_tol, eom_r_tol, eom_max_iter
+        kept = (C.c_int * n)()
+        ecc, eeom = np.zeros(n), np.zeros(max(n * nr, 1))
+        ecx, eex = C.c_double(), np.zeros(max(nr, 1))
+        st = self._check(self._lib.fno_xfno(self._h, n, _dp(x), C.byref(co), KIND[kind] if kind else 0, C.byref(eo),
+                                            kept, _dp(ecc), _dp(eeom), C.byref(ecx), _dp(eex)),
+                         allow=(FNO_ENOCONV,) if allow_noconv else ())
+        return dict(kept=list(kept), e_cc=ecc, e_eom=eeom[:n * nr].reshape(n, nr), e_cc_x=ecx.value,
+                    e_eom_x=eex[:nr], converged=(st == FNO_OK))
 
     def sizes(self):
         o, v, vf = C.c_int(), C.c_int(), C.c_int()

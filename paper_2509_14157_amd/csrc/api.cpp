@@ -1,4 +1,5 @@
 // extern "C" boundary: argument checks, error capture, status codes.
+#include <algorithm>
 #include <cstring>
 #include <exception>
 
@@ -262,6 +263,89 @@ int fno_eom(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, double* o
     if (st == FNO_ENOCONV) ctx->err = "EOM Davidson did not converge within max_iter";
     return st;
   });
+}
+
+int fno_mp2_energies(const fno_ctx* ctx, double* e_full, double* e_trunc) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  if (!ctx->c->truncated) return FNO_ESTATE;
+  if (e_full) *e_full = ctx->c->e_mp2_full;
+  if (e_trunc) *e_trunc = ctx->c->e_mp2_trunc;
+  return FNO_OK;
+}
+
+namespace {
+
+// value at x0 of the least-squares line through (x_i, y_i)
+double line_at(int n, const double* x, const double* y, double x0) {
+  double mx = 0, my = 0;
+  for (int i = 0; i < n; ++i) {
+    mx += x[i];
+    my += y[i];
+  }
+  mx /= n;
+  my /= n;
+  double sxy = 0, sxx = 0;
+  for (int i = 0; i < n; ++i) {
+    sxy += (x[i] - mx) * (y[i] - my);
+    sxx += (x[i] - mx) * (x[i] - mx);
+  }
+  return my + (sxy / sxx) * (x0 - mx);
+}
+
+}  // namespace
+
+int fno_xfno(fno_ctx* ctx, int npts, const double* occt, const fno_cc_opts* cc, int kind, const fno_eom_opts* eom,
+             int* kept, double* e_cc, double* e_eom, double* e_cc_x, double* e_eom_x) {
+  if (!ctx || !ctx->c) return FNO_EINVAL;
+  auto fail = [&](int st, const std::string& msg) {
+    ctx->err = msg;
+    return st;
+  };
+  if (npts < 2 || npts > 16 || !occt || !e_cc || !e_cc_x)
+    return fail(FNO_EINVAL, "fno_xfno needs 2..16 thresholds and the e_cc, e_cc_x outputs");
+  for (int p = 0; p < npts; ++p) {
+    if (!(occt[p] > 0.0 && occt[p] <= 1.0)) return fail(FNO_EINVAL, "occt must lie in (0, 1]");
+    for (int q = 0; q < p; ++q)
+      if (occt[q] == occt[p]) return fail(FNO_EINVAL, "fno_xfno needs distinct thresholds");
+  }
+  if (kind != 0 && (kind < FNO_IP || kind > FNO_DEA)) return fail(FNO_EINVAL, "unknown EOM kind");
+  fno_eom_opts eo;
+  if (eom)
+    eo = *eom;
+  else
+    fno_eom_opts_default(&eo);
+  const int nr = kind ? eo.nroots : 0;
+  if (kind && (nr < 1 || !e_eom || !e_eom_x)) return fail(FNO_EINVAL, "EOM points need nroots >= 1 and e_eom, e_eom_x");
+  int worst = FNO_OK;
+  std::vector<double> om(std::max(nr, 1)), et(std::max(nr, 1));
+  for (int p = 0; p < npts; ++p) {
+    int k = 0;
+    int st = fno_truncate(ctx, occt[p], 0, &k, nullptr, nullptr);
+    if (st != FNO_OK) return st;
+    if (kept) kept[p] = k;
+    double ec = 0, etot = 0, rn = 0;
+    int it = 0;
+    st = fno_ccsdt(ctx, cc, &ec, &etot, &it, &rn);
+    if (st == FNO_ENOCONV && kind)
+      return fail(FNO_ENOCONV, "fno_xfno: CCSDT did not converge at occt = " + std::to_string(occt[p]));
+    if (st != FNO_OK && st != FNO_ENOCONV) return st;
+    if (st == FNO_ENOCONV) worst = FNO_ENOCONV;
+    e_cc[p] = etot;
+    if (kind) {
+      st = fno_eom(ctx, (fno_eom_kind)kind, &eo, om.data(), et.data(), nullptr, nullptr);
+      if (st != FNO_OK && st != FNO_ENOCONV) return st;
+      if (st == FNO_ENOCONV) worst = FNO_ENOCONV;
+      for (int r = 0; r < nr; ++r) e_eom[(size_t)p * nr + r] = et[r];
+    }
+  }
+  *e_cc_x = line_at(npts, occt, e_cc, 1.0);
+  for (int r = 0; r < nr; ++r) {
+    std::vector<double> y(npts);
+    for (int p = 0; p < npts; ++p) y[p] = e_eom[(size_t)p * nr + r];
+    e_eom_x[r] = line_at(npts, occt, y.data(), 1.0);
+  }
+  if (worst == FNO_ENOCONV) ctx->err = "fno_xfno: a solve did not converge within max_iter (results written)";
+  return worst;
 }
 
 int fno_sizes(const fno_ctx* ctx, int* nocc, int* nvir, int* nvir_full) {

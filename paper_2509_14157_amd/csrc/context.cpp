@@ -376,6 +376,7 @@ void Context::truncate(double occt, int keep, int* kept, double* emp2, double* o
   wsz.n = {{'n', n}};
   Tensor* Gw = E.create("G", "n,n,n,n", wsz);
   E.term("G[PQRS] += 1 * Rot3[sPQR] * Cf[sS]");
+  E.set_sym(Gw, {{0, 1}, {2, 3}});  // <PQ||RS>: antisymmetric slot pairs
   E.drop("Rot3");
   for (const char* nm : {"MP2num", "MP2t", "MP2den", "Dvv", "Emp2", "Cf", "Gf_vvoo", "Gf_oovv"}) E.drop(nm);
   (void)Gw;
@@ -402,6 +403,34 @@ void Context::truncate(double occt, int keep, int* kept, double* emp2, double* o
     }
   Tensor* H = E.create("Hcore", "n,n", wsz);
   FNO_HIP(hipMemcpy(H->d, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  // E_MP2 in the truncated space: the same formula over the kept
+  // semicanonical virtuals (their orbital energies the diagonal of f2)
+  {
+    SpaceSizes tsz;
+    tsz.n = {{'o', o}, {'v', k}};
+    E.view("Gt_vvoo", E.get("G"), {{o, k}, {o, k}, {0, o}, {0, o}});
+    E.view("Gt_oovv", E.get("G"), {{0, o}, {0, o}, {o, k}, {o, k}});
+    Tensor* tnum = E.create("MP2tnum", "oo,vv", tsz);
+    Tensor* tamp = E.create("MP2tamp", "oo,vv", tsz);
+    Tensor* tden = E.create("MP2tden", "oo,vv", tsz);
+    E.create("Emp2t", "", tsz);
+    E.term("MP2tnum[ijab] += 1 * Gt_vvoo[abij]");
+    std::vector<double> et(o + k);
+    for (int i = 0; i < o; ++i) et[i] = eo[i];
+    for (int a = 0; a < k; ++a) et[o + a] = f2[(size_t)(o + a) * n + (o + a)];
+    double* d_et = alloc(o + k);
+    FNO_HIP(hipMemcpy(d_et, et.data(), et.size() * sizeof(double), hipMemcpyHostToDevice));
+    MatDim mt{};
+    mt.ngroups = 2;
+    mt.grp[0] = {2, o, (int64_t)binom_host(o, 2), {0, 1}};
+    mt.grp[1] = {2, k, (int64_t)binom_host(k, 2), {2, 3}};
+    mt.size = mt.grp[0].count * mt.grp[1].count;
+    launch_denominators(E.tables, mt, 2, d_et, d_et + o, tden->d, E.stream);
+    launch_jacobi(tamp->d, tnum->d, tden->d, nullptr, mt.size, E.stream);
+    E.term("Emp2t[] += 0.25 * Gt_oovv[ijab] * MP2tamp[ijab]");
+    FNO_HIP(hipMemcpy(&e_mp2_trunc, E.get("Emp2t")->d, sizeof(double), hipMemcpyDeviceToHost));
+    for (const char* nm : {"MP2tnum", "MP2tamp", "MP2tden", "Emp2t", "Gt_vvoo", "Gt_oovv"}) E.drop(nm);
+  }
   FNO_HIP(hipDeviceSynchronize());
   // E_ref is unchanged: the occupied block is not rotated
   truncated = true;

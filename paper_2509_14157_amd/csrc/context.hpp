@@ -55,7 +55,7 @@ class Context {
   std::vector<double> fock_full;  // host, full space
   std::vector<double> fock;       // host, working space
   bool loaded = false, truncated = false, cc_ready = false, cc_done = false;
-  double e_ref = 0, e_corr = 0, e_mp2_full = 0;
+  double e_ref = 0, e_corr = 0, e_mp2_full = 0, e_mp2_trunc = 0;
 
   void load(int o, int v, const double* f, const double* g, double en);
   void truncate(double occt, int keep, int* kept, double* emp2, double* occ);

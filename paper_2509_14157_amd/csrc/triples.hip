@@ -62,6 +62,7 @@ __device__ __forceinline__ int tri_rank(int x, int p, int q, int& s) {
 
 constexpr int kBM = 64, kBN = 128, kBK = 16, kThreads = 256;
 constexpr int kSegs = 11;
+constexpr int kPanel = 16;  // triples per panel of the tile order
 
 struct Params {
   R3FusedArgs a;
@@ -70,6 +71,7 @@ struct Params {
   int kt_begin[kSegs + 1];     // first k tile of each segment
   int seg_k[kSegs];            // K of each segment
   int ep;                      // padded e range of the ring segments (multiple of 16)
+  int panel;                   // triples per panel of the tile order
 };
 
 // Element mappings of the staged tiles (uniform per k tile):
@@ -91,17 +93,21 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
   const R3FusedArgs& g = P.a;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // tiles: the column tiles of one triple are consecutive within an XCD's
-  // contiguous range; they run together and walk K in near lockstep, so the
-  // triple's T3v rows, the k slab of W3_vvvv^T and the ring's T3v rows are
-  // shared through the XCD's L2
-  int64_t L;
+  // tiles: each XCD takes a contiguous range of the tile order; the order
+  // walks panels of `panel` triples, column tile by column tile, so the
+  // tiles running together on an XCD share column strips of W3_vvvv^T and
+  // of the ring's T3v rows, and the panel's own T3v rows, through its L2
+  int t, n0;
   {
     const int64_t n = gridDim.x, b = blockIdx.x, q = n / 8, r = n % 8, x = b % 8, k = b / 8;
-    L = x * q + (x < r ? x : r) + k;
+    const int64_t L = x * q + (x < r ? x : r) + k;
+    const int64_t per = (int64_t)P.panel * P.ntn;
+    const int pn = (int)(L / per);
+    const int rem = (int)(L - pn * per);
+    const int pe = min(P.panel, P.nt - pn * P.panel);
+    t = pn * P.panel + rem % pe;
+    n0 = (rem / pe) * kBN;
   }
-  const int t = (int)(L / P.ntn);
-  const int n0 = (int)(L % P.ntn) * kBN;
   const int v = g.v, o = g.o, nv2 = P.nv2;
   const int64_t ldy = g.ldy;
   const uint8_t* d3 = P.tb.dec[3] + 3 * t;
@@ -460,6 +466,7 @@ Params make_params(const IndexTables& tb, const R3FusedArgs& a) {
   P.nt = (int)binom_host(o, 3);
   P.ntn = ceil_div(P.nv2, kBN);
   P.ep = (v + kBK - 1) / kBK * kBK;
+  P.panel = std::min(P.nt, kPanel);
   const int ks[kSegs] = {P.nv2, v, (o - 2) * P.ep, (o - 2) * P.ep, (o - 2) * P.ep, v, v, v, o, o, o};
   int kt = 0;
   for (int s = 0; s < kSegs; ++s) {

@@ -49,8 +49,15 @@ class SyntheticHamiltonian:
 
 def make_hamiltonian(nocc: int, nvir: int, seed: int,
                      eocc=(-2.0, -0.5), evir=(0.3, 3.0), sigma: float = 0.05,
-                     e_nuc: float = 0.0) -> SyntheticHamiltonian:
-    """Draw one seeded Hamiltonian with ``nocc`` occupied and ``nvir`` virtual spin-orbitals."""
+                     e_nuc: float = 0.0, decay: float = 0.0) -> SyntheticHamiltonian:
+    """Draw one seeded Hamiltonian with ``nocc`` occupied and ``nvir`` virtual spin-orbitals.
+
+    ``decay`` > 0 scales every integral <pq||rs> by w_p w_q w_r w_s with
+    w = 1 on occupied orbitals and w = exp(-a / decay) on the a-th virtual (in
+    ascending energy), so the higher virtuals couple more weakly and their MP2
+    natural occupations fall off (as the diffuse functions of a real basis
+    do); the permutational symmetries are kept exactly.
+    """
     if nocc < 0 or nvir < 0:
         raise ValueError("nocc and nvir must be non-negative")
     n = nocc + nvir
@@ -67,9 +74,12 @@ def make_hamiltonian(nocc: int, nvir: int, seed: int,
     phys = acc.transpose(0, 2, 1, 3)            # <pq|rs> = (pr|qs)
     eri = np.ascontiguousarray(phys - phys.transpose(0, 1, 3, 2))
     del acc, phys
+    if decay > 0:
+        w = np.concatenate([np.ones(nocc), np.exp(-np.arange(nvir) / decay)])
+        eri *= np.einsum("p,q,r,s->pqrs", w, w, w, w)
     fock = np.diag(np.concatenate([eo, ev])).astype(np.float64)
     return SyntheticHamiltonian(nocc, nvir, fock, eri, e_nuc, seed,
-                                dict(eocc=tuple(eocc), evir=tuple(evir), sigma=sigma))
+                                dict(eocc=tuple(eocc), evir=tuple(evir), sigma=sigma, decay=decay))
 
 
 def full_virtuals_for(v_kept: int) -> int:
