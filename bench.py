@@ -260,6 +260,26 @@ def bench_eom(args, nroots=8):
                                  "omega": [round(float(x), 9) for x in w]}
                 _log(f"[bench] EOM-{kind} {pr}: {r['iters']} iterations in {dt:.2f} s "
                      f"({trp / dt / 1e12:.2f} TFLOP/s), max |dw| vs fp64 {np.abs(w - ref).max():.2e}")
+            # left eigenvectors (the transposed sigma program), FP64, with the
+            # right vectors for the biorthogonality check
+            c.eom_vectors(kind, nroots=nroots, left=True, max_iter=2, allow_noconv=True)
+            t0 = time.perf_counter()
+            rl = c.eom_vectors(kind, nroots=nroots, left=True, r_tol=1e-5, e_tol=1e-7, max_iter=100,
+                               allow_noconv=True)
+            dt = time.perf_counter() - t0
+            trp, _ = c.last_flops()
+            rr = c.eom_vectors(kind, nroots=nroots, r_tol=1e-5, e_tol=1e-7, max_iter=100, allow_noconv=True)
+            S = rl["vectors"] @ rr["vectors"].T
+            off = float(np.max(np.abs(S - np.diag(np.diag(S)))) / np.min(np.abs(np.diag(S))))
+            wl = np.sort(rl["omega"])
+            out[kind]["left_fp64"] = {"s": round(dt, 3), "iters": rl["iters"], "s_per_iter": round(dt / rl["iters"], 4),
+                                      "converged": rl["converged"], "triples_gflop": round(trp / 1e9, 2),
+                                      "tflops": round(trp / dt / 1e12, 3),
+                                      "max_root_diff_vs_right": float(np.abs(wl - ref).max()),
+                                      "max_offdiag_overlap_left_right": off}
+            _log(f"[bench] EOM-{kind} left fp64: {rl['iters']} iterations in {dt:.2f} s "
+                 f"({trp / dt / 1e12:.2f} TFLOP/s), max |dw| vs right {np.abs(wl - ref).max():.2e}, "
+                 f"off-diagonal l.r {off:.1e}")
     line = {"metric": "triples-contraction TFLOP/s (% MFMA peak) and s/iteration, FP64 vs mixed",
             "value": out["EA"]["fp64"]["tflops"], "unit": "TFLOP/s", "n_gpus": 1, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",

@@ -219,6 +219,30 @@ size_t fno_eom_size(const fno_ctx *ctx, fno_eom_kind kind);
 int fno_eom_sigma(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *r, double *sigma, size_t len);
 
 /*
+ * Left-hand EOM sigma sigma^T = l^T (H-bar - E_CC) over the same R space
+ * (the transpose of fno_eom_sigma in the packed basis), the product that the
+ * left EOM vectors L1..L3 (Introduction: L3 among the rate-determining
+ * six-index quantities) are found with.  Layout and length as fno_eom_sigma.
+ */
+int fno_eom_sigma_left(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const double *l, double *sigma, size_t len);
+
+/*
+ * EOM-CCSDT roots of `kind` with their eigenvectors: right vectors
+ * (H-bar - E_CC) r = omega r (left = 0), or left vectors
+ * l^T (H-bar - E_CC) = omega l^T (left = 1), by the same block Davidson as
+ * fno_eom applied to the corresponding sigma.  Both sides have the same
+ * eigenvalues; a left vector and a right vector of different roots are
+ * orthogonal.
+ *   omega   : nroots eigenvalues, ascending real part.
+ *   vectors : nroots * fno_eom_size(ctx, kind) doubles, root-major, each of
+ *             unit 2-norm (a biorthonormal pair is l / (l.r), r).
+ *   res_norm, iters : as fno_eom (may be NULL).
+ * Errors: as fno_eom.
+ */
+int fno_eom_vectors(fno_ctx *ctx, fno_eom_kind kind, const fno_eom_opts *opts, int left, double *omega,
+                    double *vectors, double *res_norm, int *iters);
+
+/*
  * Device-pointer variants of the calls above.  Every d_ buffer is device
  * memory on the context's device (caller-owned, same packed layouts and
  * lengths as the host versions); copies and kernels are enqueued on the

@@ -264,6 +264,22 @@ def eom_matrix(fock, eri, nocc, amps, kind):
     return M, sp
 
 
+def eom_sigma_left(fock, eri, nocc, amps, kind, lblocks):
+    """Left-hand sigma l^T (H-bar - E_CC) over unique elements: the transpose of
+    the EOM matrix (columns = sigma of unit vectors) applied to l, as blocks."""
+    M, sp = eom_matrix(fock, eri, nocc, amps, kind)
+    return sp.unpack(M.T @ sp.pack(lblocks))
+
+
+def eom_left_dense(fock, eri, nocc, amps, kind, nroots):
+    """Lowest ``nroots`` eigenvalues (by real part) of the explicit EOM matrix and
+    its left eigenvectors (columns l with l^T M = w l^T, unit 2-norm), as blocks."""
+    M, sp = eom_matrix(fock, eri, nocc, amps, kind)
+    w, Lv = np.linalg.eig(M.T)
+    order = np.argsort(w.real)[:nroots]
+    return w[order], [sp.unpack(np.real(Lv[:, j]) / np.linalg.norm(np.real(Lv[:, j]))) for j in order], M, sp
+
+
 def eom_roots_dense(fock, eri, nocc, amps, kind, nroots):
     """Lowest ``nroots`` eigenvalues (by real part) of the explicit EOM matrix."""
     M, sp = eom_matrix(fock, eri, nocc, amps, kind)

@@ -22,7 +22,7 @@ KIND = {"IP": 1, "DIP": 2, "EA": 3, "DEA": 4}
 SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno_load_hamiltonian",
            "fno_truncate", "fno_mp2_energies", "fno_xfno", "fno_cc_opts_default", "fno_ccsdt", "fno_eom_opts_default", "fno_eom", "fno_sizes",
            "fno_get_amplitudes", "fno_set_amplitudes", "fno_amplitude_size", "fno_cc_residual", "fno_eom_size",
-           "fno_eom_sigma", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
+           "fno_eom_sigma", "fno_eom_sigma_left", "fno_eom_vectors", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
            "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error",
            "fno_triples_residual_dev_noalloc", "fno_profile", "fno_profile_report", "fno_profile_filter",
            "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
@@ -85,6 +85,9 @@ def library() -> C.CDLL:
         lib.fno_eom_size.argtypes = [C.c_void_p, C.c_int]
         lib.fno_eom_size.restype = C.c_size_t
         lib.fno_eom_sigma.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
+        lib.fno_eom_sigma_left.argtypes = [C.c_void_p, C.c_int, C.c_int, dp, dp, C.c_size_t]
+        lib.fno_eom_vectors.argtypes = [C.c_void_p, C.c_int, C.POINTER(EOMOpts), C.c_int, dp, dp, dp,
+                                        C.POINTER(C.c_int)]
         lib.fno_last_flops.argtypes = [C.c_void_p, dp, dp]
         lib.fno_last_trace.argtypes = [C.c_void_p, dp, dp, C.c_int, C.POINTER(C.c_int)]
         lib.fno_get_amplitudes_dev.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_size_t]
@@ -375,6 +378,30 @@ class Context:
         out = np.zeros_like(x)
         self._check(self._lib.fno_eom_sigma(self._h, KIND[kind], PREC[prec], _dp(x), _dp(out), x.size))
         return out
+
+    def eom_sigma_left(self, kind: str, l, prec="fp64") -> np.ndarray:
+        """sigma^T = l^T (H-bar - E_CC) (fno_eom_sigma_left)."""
+        x = _f64(l).ravel()
+        out = np.zeros_like(x)
+        self._check(self._lib.fno_eom_sigma_left(self._h, KIND[kind], PREC[prec], _dp(x), _dp(out), x.size))
+        return out
+
+    def eom_vectors(self, kind: str, nroots=4, left=False, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6,
+                    prec="fp64", allow_noconv=False, block=0):
+        """Roots and right (or left) eigenvectors (fno_eom_vectors), vectors as rows."""
+        o = EOMOpts()
+        self._lib.fno_eom_opts_default(C.byref(o))
+        o.nroots, o.max_iter, o.max_sub, o.e_tol, o.r_tol = nroots, max_iter, max_sub, e_tol, r_tol
+        o.prec = PREC[prec]
+        o.block = block
+        dim = self.eom_size(kind)
+        om, rn = np.zeros(nroots), np.zeros(nroots)
+        vec = np.zeros((nroots, dim))
+        it = C.c_int()
+        st = self._check(self._lib.fno_eom_vectors(self._h, KIND[kind], C.byref(o), 1 if left else 0, _dp(om),
+                                                   _dp(vec), _dp(rn), C.byref(it)),
+                         allow=(FNO_ENOCONV,) if allow_noconv else ())
+        return dict(omega=om, vectors=vec, res_norm=rn, iters=it.value, converged=(st == FNO_OK))
 
     def eom(self, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",
             allow_noconv=False, block=0):

@@ -37,14 +37,30 @@ Z) over the vectors of one Davidson block: each sigma term then processes the
 whole block in one GEMM (the batch letter is an output letter of the
 R-carrying factor), instead of one launch per vector.
 
+Left-hand sigma.  The sigma program is linear in R: every term has exactly
+one R-derived factor (a block tensor), the other being a ground-state
+constant.  The left sigma L^T (H-bar - E_CC) is its transpose in the packed
+basis, obtained in reverse mode: the terms run in reverse order, and
+Out += c A B with A R-derived becomes  Abar += c' B Outbar  (Abar, Outbar the
+adjoint block tensors).  The engine applies to a term's output the
+antisymmetrizer P over the output's groups modulo the antisymmetry the
+product already has (H); written out on the packed inner product, the
+transpose of Out = c P(A B) needs c' = c |H'| / |H| with H' the antisymmetry
+of the adjoint product, i.e.
+  c' = c * prod_{gA, gB} |gA & gB|! / prod_{gO, gB} |gO & gB|!
+over the antisymmetric letter groups of A, B and Out (the groups shared by A
+and Out cancel).  Coefficients are written as exact fractions.
+
 Usage: python -m paper_2509_14157_amd.codegen.eom_jvp  (writes csrc/eom_*_terms.inc)
 """
 from __future__ import annotations
 
 import itertools
+import math
 import os
 import re
 import sys
+from fractions import Fraction
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(os.path.dirname(HERE), "csrc")
@@ -351,6 +367,63 @@ class Generator:
             if TERM.match(spec).group(1) in need:
                 self.prep.append(spec)
 
+    # ---------------------------------------------------------- transpose
+    def letter_groups_of(self, name, letters):
+        """Antisymmetric groups (as letter lists) of a tensor of the generated terms."""
+        if name in self.decls:
+            toks = [t for t in self.decls[name].split(",") if t]
+            groups, s = [], 0
+            for tok in toks:
+                groups.append(list(range(s, s + len(tok))))
+                s += len(tok)
+        elif name in self.tensors:
+            groups = self.tensors[name].groups
+        elif name.startswith("GdS_"):
+            groups = dense_sym_groups(list(name[4:]), [(0, 1), (2, 3)])
+        elif name.startswith("FdS_"):
+            groups = [[0], [1]]
+        else:
+            raise KeyError(name)
+        assert sum(len(g) for g in groups) == len(letters), (name, letters)
+        return [[letters[x] for x in g] for g in groups]
+
+    def adjoint_terms(self):
+        """The left-hand sigma program: the generated terms transposed, in reverse order."""
+        blocks = set(self.decls)
+        out = []
+        for t in reversed(self.out_terms):
+            m = TERM.match(t)
+            assert m, t
+            o, lo, sg, coef, a, la, b, lb = m.groups()
+            assert o in blocks, t
+            c = Fraction(coef) if coef else Fraction(1)
+            if sg == "-":
+                c = -c
+            if b is None:
+                assert a in blocks, t
+                x, lx, k, lk = a, la, None, None
+            elif a in blocks and b not in blocks:
+                x, lx, k, lk = a, la, b, lb
+            elif b in blocks and a not in blocks:
+                x, lx, k, lk = b, lb, a, la
+            else:
+                raise ValueError("term not linear in R: " + t)
+            if k is not None:
+                gx = self.letter_groups_of(x, lx)
+                gk = self.letter_groups_of(k, lk)
+                go = self.letter_groups_of(o, lo)
+                num = math.prod(math.factorial(len(set(p) & set(q))) for p in gx for q in gk)
+                den = math.prod(math.factorial(len(set(p) & set(q))) for p in go for q in gk)
+                c = c * Fraction(num, den)
+            op = "+=" if c > 0 else "-="
+            mag = abs(c)
+            ms = str(mag.numerator) if mag.denominator == 1 else f"{mag.numerator}/{mag.denominator}"
+            if k is None:
+                out.append(f"L_{x}[{lx}] {op} {ms} * L_{o}[{lo}]")
+            else:
+                out.append(f"L_{x}[{lx}] {op} {ms} * {k}[{lk}] * L_{o}[{lo}]")
+        return out
+
     def generate(self):
         self.view_blocks()
         for amp, _ in self.rblocks:
@@ -425,6 +498,27 @@ def emit(variant, gen: Generator, outputs):
         lines.append(f'    "{t}",')
     if not gen.prep:
         lines.append('    "",')
+    lines.append("};")
+    # left-hand sigma: adjoint block tensors, the transposed program in reverse
+    # order; its input is the adjoint of the sigma blocks, its output the
+    # adjoint of the R blocks (every other adjoint tensor accumulates)
+    lin = ["L_" + x for x in outputs]
+    lout = ["L_" + x for x in inputs]
+    lines.append(f"// left-hand sigma L^T (H-bar - E_CC): the transposed program (see the generator)")
+    lines.append(f"static const char* const kEom{v}LDecl[] = {{")
+    for name in sorted(gen.decls):
+        lines.append(f'    "L_{name} : {gen.decls[name]}",')
+    lines.append("};")
+    lines.append(f"static const char* const kEom{v}LIn[] = {{" + ", ".join(f'"{x}"' for x in lin) + "};")
+    lines.append(f"static const char* const kEom{v}LOut[] = {{" + ", ".join(f'"{x}"' for x in lout) + "};")
+    lines.append(f"static const char* const kEom{v}LZero[] = {{")
+    for name in sorted(gen.decls):
+        if "L_" + name not in lin:
+            lines.append(f'    "L_{name}",')
+    lines.append("};")
+    lines.append(f"static const char* const kEom{v}LTerms[] = {{")
+    for t in gen.adjoint_terms():
+        lines.append(f'    "{t}",')
     lines.append("};")
     return "\n".join(lines) + "\n"
 

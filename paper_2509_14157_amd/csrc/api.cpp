@@ -438,6 +438,37 @@ int fno_eom_sigma(fno_ctx* ctx, fno_eom_kind kind, fno_prec prec, const double* 
   });
 }
 
+int fno_eom_sigma_left(fno_ctx* ctx, fno_eom_kind kind, fno_prec prec, const double* l, double* sigma, size_t len) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(l && sigma, FNO_EINVAL, "null buffer");
+    c.eom_sigma((int)kind, to_prec(prec), l, sigma, len, false, true);
+    return FNO_OK;
+  });
+}
+
+int fno_eom_vectors(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, int left, double* omega,
+                    double* vectors, double* res_norm, int* iters) {
+  return guard(ctx, [&](fno::Context& c) {
+    FNO_REQUIRE(kind >= FNO_IP && kind <= FNO_DEA, FNO_EINVAL, "unknown EOM kind");
+    FNO_REQUIRE(left == 0 || left == 1, FNO_EINVAL, "left must be 0 (right vectors) or 1 (left vectors)");
+    FNO_REQUIRE(c.cc_done, FNO_ESTATE, "fno_eom_vectors needs a converged fno_ccsdt first");
+    FNO_REQUIRE(omega != nullptr && vectors != nullptr, FNO_EINVAL, "omega and vectors are required");
+    fno::EOMOptions eo = eom_options(opts);
+    eo.left = left == 1;
+    fno::EOMResult r;
+    r.want_vectors = true;
+    int st = c.eom((int)kind, eo, r);
+    for (int k = 0; k < eo.nroots; ++k) {
+      omega[k] = r.omega[k];
+      if (res_norm) res_norm[k] = r.res_norm[k];
+    }
+    std::copy(r.vectors.begin(), r.vectors.end(), vectors);
+    if (iters) *iters = r.iters;
+    if (st == FNO_ENOCONV) ctx->err = "EOM Davidson did not converge within max_iter";
+    return st;
+  });
+}
+
 int fno_last_flops(const fno_ctx* ctx, double* triples_flops, double* all_flops) {
   if (!ctx || !ctx->c) return FNO_EINVAL;
   if (triples_flops) *triples_flops = ctx->c->last_triples_flops;

@@ -28,7 +28,10 @@ void Context::set_stream(hipStream_t s) {
   eng->stream = s ? s : eng->own_stream();
   // recordings remember the stream they were last launched on
   cc_prog_.clear();
-  if (eom_) eom_->prog.clear();
+  if (eom_) {
+    eom_->rg.prog.clear();
+    eom_->lg.prog.clear();
+  }
 }
 
 void Context::reset_engine(std::unique_ptr<Engine> e) {

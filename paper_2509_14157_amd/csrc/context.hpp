@@ -25,12 +25,15 @@ struct EOMOptions {
   int block = 0;  // vectors per sigma evaluation (0 = nroots)
   double e_tol = 1e-8, r_tol = 1e-6;
   Prec prec = Prec::FP64;
+  bool left = false;  // left eigenvectors: the solver applies the transposed sigma
 };
 
 struct EOMResult {
   std::vector<double> omega, res_norm;
   int iters = 0;
   bool converged = false;
+  bool want_vectors = false;
+  std::vector<double> vectors;  // nroots x dim Ritz vectors (unit 2-norm) when asked for
 };
 
 // Block layout of an amplitude-like vector: (holes, particles) per block.
@@ -68,7 +71,7 @@ class Context {
 
   // EOM
   size_t eom_size(int kind);
-  void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev = false);
+  void eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev = false, bool left = false);
   int eom(int kind, const EOMOptions& opt, EOMResult& res);
   // resumable Davidson (used by eom() and by batched solves over several contexts)
   struct Davidson;

@@ -44,12 +44,22 @@ std::pair<std::string, std::string> split_decl2(const char* d) {
             count(kEom##V##Terms), kEom##V##PrimDecl, count(kEom##V##PrimDecl), kEom##V##Prep,           \
             count(kEom##V##Prep)}
 
-EomTables tables_for(int kind) {
+// the left-hand program: adjoint tensors, inputs (adjoints of the sigma
+// blocks), outputs (adjoints of the R blocks), zero list and terms; views
+// and T-only intermediates are those of the right-hand program
+#define FNO_EOM_LTABLES(V)                                                                                  \
+  EomTables{kEom##V##LDecl,     count(kEom##V##LDecl), kEom##V##Views,  count(kEom##V##Views),           \
+            kEom##V##Blocks,    kEom##V##Sign,         kEom##V##LIn,    kEom##V##LOut,                    \
+            count(kEom##V##LIn), kEom##V##LZero,       count(kEom##V##LZero), kEom##V##LTerms,           \
+            count(kEom##V##LTerms), kEom##V##PrimDecl, count(kEom##V##PrimDecl), kEom##V##Prep,          \
+            count(kEom##V##Prep)}
+
+EomTables tables_for(int kind, bool left = false) {
   switch (kind) {
-    case 1: return FNO_EOM_TABLES(IP);
-    case 2: return FNO_EOM_TABLES(DIP);
-    case 3: return FNO_EOM_TABLES(EA);
-    case 4: return FNO_EOM_TABLES(DEA);
+    case 1: return left ? FNO_EOM_LTABLES(IP) : FNO_EOM_TABLES(IP);
+    case 2: return left ? FNO_EOM_LTABLES(DIP) : FNO_EOM_TABLES(DIP);
+    case 3: return left ? FNO_EOM_LTABLES(EA) : FNO_EOM_TABLES(EA);
+    case 4: return left ? FNO_EOM_LTABLES(DEA) : FNO_EOM_TABLES(DEA);
     default: throw Error(kEINVAL, "unknown EOM variant");
   }
 }
@@ -79,6 +89,7 @@ void Context::setup_eom(int kind, int nb) {
   sp->kind = kind;
   sp->nb = nb;
   sp->tab = tables_for(kind);
+  sp->ltab = tables_for(kind, true);
   const EomTables& t = sp->tab;
   auto make = [&](const char* decl) {
     if (!decl[0]) return;
@@ -183,12 +194,32 @@ size_t Context::eom_size(int kind) {
   return (size_t)d;
 }
 
-// sigma_j = (H-bar - E_CC) r_j for `count` <= nb device vectors (packed R
-// layout, leading dimensions ldr / lds); the block tensors hold nb vectors
-// each, those beyond `count` are zero.
+// The adjoint tensors of the left-hand program, created on first use.
+static void ensure_left(Engine& e, Context::EomSpace& sp, const SpaceSizes& sz) {
+  if (sp.left_made) return;
+  const EomTables& t = sp.ltab;
+  for (int i = 0; i < t.ndecl; ++i) {
+    auto d = split_decl2(t.decl[i]);
+    FNO_REQUIRE(!e.has(d.first), kEDEVICE, "EOM tensor already exists: " + d.first);
+    e.create(d.first, d.second, sz);
+    sp.created.push_back(d.first);
+  }
+  for (int b = 0; b < t.nblocks; ++b)
+    FNO_REQUIRE(sp.blocks[b].size * sp.nb == e.get(t.in[b])->elems &&
+                    sp.blocks[b].size * sp.nb == e.get(t.out[b])->elems,
+                kEDEVICE, "EOM left block layout mismatch");
+  sp.left_made = true;
+}
+
+// sigma_j = (H-bar - E_CC) r_j (left: sigma_j^T = r_j^T (H-bar - E_CC), the
+// transposed program) for `count` <= nb device vectors (packed R layout,
+// leading dimensions ldr / lds); the block tensors hold nb vectors each,
+// those beyond `count` are zero.
 static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double* r, int64_t ldr, int count,
-                      double* sigma, int64_t lds, Prec prec) {
-  const EomTables& t = sp.tab;
+                      double* sigma, int64_t lds, Prec prec, bool left = false) {
+  const EomTables& t = left ? sp.ltab : sp.tab;
+  SigmaGraph& g = left ? sp.lg : sp.rg;
+  FNO_REQUIRE(!left || sp.left_made, kESTATE, "left-hand EOM tensors not set up");
   FNO_REQUIRE(count >= 1 && count <= sp.nb, kEINVAL, "bad EOM block count");
   for (int b = 0; b < t.nblocks; ++b) {
     const int64_t sz = sp.blocks[b].size;
@@ -234,39 +265,39 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
     sp.sweep_all = af;
   };
   const bool graphs = c.use_graphs;
-  if (graphs && sp.prog.valid() && sp.prog.epoch == e.epoch && sp.prog.prec == (int)prec &&
-      sp.prog.profiled == e.profile && sp.prog.filter == e.profile_filter) {
-    e.replay(sp.prog);
+  if (graphs && g.prog.valid() && g.prog.epoch == e.epoch && g.prog.prec == (int)prec &&
+      g.prog.profiled == e.profile && g.prog.filter == e.profile_filter) {
+    e.replay(g.prog);
   } else {
-    sp.prog.clear();
+    g.prog.clear();
     bool done = false;
-    if (graphs && sp.stable && sp.stable_epoch == e.epoch && sp.stable_prec == (int)prec &&
-        sp.stable_profiled == e.profile && sp.stable_filter == e.profile_filter) {
-      e.begin_record(sp.prog);
-      sp.prog.prec = (int)prec;
+    if (graphs && g.stable && g.stable_epoch == e.epoch && g.stable_prec == (int)prec &&
+        g.stable_profiled == e.profile && g.stable_filter == e.profile_filter) {
+      e.begin_record(g.prog);
+      g.prog.prec = (int)prec;
       bool recorded = false;
       try {
         sweep();
-        e.end_record(sp.prog);
+        e.end_record(g.prog);
         recorded = true;
       } catch (const Error&) {
         e.abort_record();
         e.prec = Prec::FP64;
-        sp.stable = false;
+        g.stable = false;
       }
-      if (recorded && sp.prog.valid()) {
-        e.replay(sp.prog);
+      if (recorded && g.prog.valid()) {
+        e.replay(g.prog);
         done = true;
       }
     }
     if (!done) {
       const uint64_t before = e.epoch;
       sweep();
-      sp.stable = e.epoch == before;
-      sp.stable_epoch = e.epoch;
-      sp.stable_prec = (int)prec;
-      sp.stable_profiled = e.profile;
-      sp.stable_filter = e.profile_filter;
+      g.stable = e.epoch == before;
+      g.stable_epoch = e.epoch;
+      g.stable_prec = (int)prec;
+      g.stable_profiled = e.profile;
+      g.stable_filter = e.profile_filter;
     }
   }
   for (int b = 0; b < t.nblocks; ++b) {
@@ -278,7 +309,7 @@ static void eom_apply(Context& c, Engine& e, Context::EomSpace& sp, const double
   c.last_all_flops += sp.sweep_all;
 }
 
-void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev) {
+void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t len, bool dev, bool left) {
   FNO_REQUIRE(cc_ready, kESTATE, "EOM sigma needs amplitudes (fno_ccsdt or fno_set_amplitudes)");
   FNO_REQUIRE(len == eom_size(kind), kEINVAL, "R vector length mismatch");
   if (eom_) eom_->ready = eom_->ready && eom_->kind == kind;
@@ -286,16 +317,17 @@ void Context::eom_sigma(int kind, Prec p, const double* r, double* sigma, size_t
   release_eom();
   setup_eom(kind, 1);
   Engine& e = *eng;
+  if (left) ensure_left(e, *eom_, sz_);
   last_triples_flops = last_all_flops = 0;
   if (dev) {
-    eom_apply(*this, e, *eom_, r, (int64_t)len, 1, sigma, (int64_t)len, p);
+    eom_apply(*this, e, *eom_, r, (int64_t)len, 1, sigma, (int64_t)len, p, left);
     FNO_HIP(hipStreamSynchronize(e.stream));
     return;
   }
   double* dr = alloc((int64_t)len);
   double* ds = alloc((int64_t)len);
   FNO_HIP(hipMemcpyAsync(dr, r, len * sizeof(double), hipMemcpyHostToDevice, e.stream));
-  eom_apply(*this, e, *eom_, dr, (int64_t)len, 1, ds, (int64_t)len, p);
+  eom_apply(*this, e, *eom_, dr, (int64_t)len, 1, ds, (int64_t)len, p, left);
   FNO_HIP(hipMemcpyAsync(sigma, ds, len * sizeof(double), hipMemcpyDeviceToHost, e.stream));
   FNO_HIP(hipStreamSynchronize(e.stream));
   FNO_HIP(hipFree(dr));
@@ -320,6 +352,7 @@ Context::Davidson* Context::dav_begin(int kind, const EOMOptions& opt) {
   setup_eom(kind, std::min(std::max(opt.block > 0 ? opt.block : opt.nroots, 1), 16));
   EomSpace& sp = *eom_;
   Engine& e = *eng;
+  if (opt.left) ensure_left(e, sp, sz_);
   auto d = std::make_unique<Davidson>();
   d->kind = kind;
   d->opt = opt;
@@ -385,7 +418,8 @@ void Context::dav_sigma(Davidson& d) {
   Engine& e = *eng;
   while (d.ns < d.nv) {
     const int cnt = std::min(sp.nb, d.nv - d.ns);
-    eom_apply(*this, e, sp, d.V + (int64_t)d.ns * d.dim, d.dim, cnt, d.S + (int64_t)d.ns * d.dim, d.dim, d.opt.prec);
+    eom_apply(*this, e, sp, d.V + (int64_t)d.ns * d.dim, d.dim, cnt, d.S + (int64_t)d.ns * d.dim, d.dim, d.opt.prec,
+              d.opt.left);
     d.ns += cnt;
   }
 }
@@ -698,6 +732,10 @@ int Context::dav_end(EOMResult& res) {
   res.res_norm = d.rn;
   res.iters = std::min(d.it, d.opt.max_iter);
   res.converged = d.status == kOK;
+  if (res.want_vectors) {
+    res.vectors.resize((size_t)d.nroots * (size_t)d.dim);
+    FNO_HIP(hipMemcpy(res.vectors.data(), d.X, res.vectors.size() * sizeof(double), hipMemcpyDeviceToHost));
+  }
   const int st = d.status;
   dav_release();
   return st;

@@ -28,23 +28,30 @@ struct EomTables {
   int nprep;
 };
 
-struct Context::EomSpace {
-  int kind = 0;
-  EomTables tab{};
-  std::vector<Block> blocks;   // (nh, np), packed sizes and offsets in the R vector
-  int64_t dim = 0;
-  int nb = 1;                  // vectors per sigma evaluation (batch slot of every R-derived tensor)
-  double* diag = nullptr;      // zeroth-order diagonal sum e_particles - sum e_holes
-  std::vector<std::string> created;  // engine tensors owned by this variant
-  bool ready = false;
-  // the sigma sweep (zeroing + terms) replayed from hipGraphs once a
-  // host-launched sweep allocated nothing (same rules as the CC residual)
+// Graph state of one sigma program (right- or left-hand).
+struct SigmaGraph {
   Program prog;
   bool stable = false;
   uint64_t stable_epoch = 0;
   int stable_prec = -1;
   bool stable_profiled = false;
   std::string stable_filter;
+};
+
+struct Context::EomSpace {
+  int kind = 0;
+  EomTables tab{};
+  EomTables ltab{};            // the left-hand (transposed) program; shares views and T-only intermediates
+  bool left_made = false;      // its adjoint tensors exist
+  std::vector<Block> blocks;   // (nh, np), packed sizes and offsets in the R vector
+  int64_t dim = 0;
+  int nb = 1;                  // vectors per sigma evaluation (batch slot of every R-derived tensor)
+  double* diag = nullptr;      // zeroth-order diagonal sum e_particles - sum e_holes
+  std::vector<std::string> created;  // engine tensors owned by this variant
+  bool ready = false;
+  // the sigma sweeps (zeroing + terms) replayed from hipGraphs once a
+  // host-launched sweep allocated nothing (same rules as the CC residual)
+  SigmaGraph rg, lg;
   double sweep_tri = 0, sweep_all = 0;  // algorithmic flops of one sweep
 };
 

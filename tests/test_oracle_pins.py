@@ -278,3 +278,33 @@ def test_diis_and_plain_jacobi_reach_same_solution():
     assert a["converged"] and b["converged"]
     assert abs(a["e_tot"] - b["e_tot"]) < 1e-10
     assert a["iters"] <= b["iters"]
+
+
+# ------------------------------------------------------------ left EOM sigma
+@pytest.mark.parametrize("kind,o,v,seed", [("IP", 3, 4, 31), ("EA", 2, 5, 32), ("DIP", 4, 3, 33), ("DEA", 2, 4, 34)])
+def test_left_sigma_is_the_transpose(kind, o, v, seed):
+    """<l, sigma(r)> = <sigma_left(l), r> over unique elements for random l, r:
+    the left sigma is the transpose of the right one (the oracle's right sigma
+    is pinned to the determinant commutator above)."""
+    h = make_hamiltonian(o, v, seed)
+    rng = np.random.default_rng(seed)
+    amps = random_amps(rng, o, v)
+    _, blocks = wick.EOM_SPACES[kind]
+    sp = cc._Space(o, v, list(blocks))
+    lv, rv = rng.normal(size=sp.dim), rng.normal(size=sp.dim)
+    sig = sp.pack(cc.eom_sigma(h.fock, h.eri, o, amps, kind, sp.unpack(rv)))
+    sigl = sp.pack(cc.eom_sigma_left(h.fock, h.eri, o, amps, kind, sp.unpack(lv)))
+    assert abs(lv @ sig - sigl @ rv) < 1e-12 * max(1.0, abs(lv @ sig))
+
+
+def test_left_roots_are_the_fci_energies_for_three_electrons():
+    """EOM-IP is exact for three electrons (above): its left eigenvalues, like
+    the right ones, are the FCI energies of the two-electron sector."""
+    h = make_hamiltonian(3, 5, 21)
+    res = cc.solve_ccsdt(h.fock, h.eri, 3, r_tol=1e-12, e_tol=1e-14)
+    w, L, M, sp = cc.eom_left_dense(h.fock, h.eri, 3, res["amps"], "IP", 4)
+    fci = det.DetModel(h.fock, h.eri, 3).fci(2)[:4]
+    assert np.abs(np.sort(res["e_tot"] + w.real) - fci).max() < 1e-9
+    for wk, lk in zip(w, L):
+        lp = sp.pack(lk)
+        assert np.linalg.norm(M.T @ lp - wk.real * lp) < 1e-9
