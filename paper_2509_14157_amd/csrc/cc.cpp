@@ -384,7 +384,7 @@ void Context::residual_body(Prec tri) {
     }
     e.prec = tri;
     if (fused_r3_ok() && tri != Prec::BF16X3)  // split-BF16 products run per term
-      r3_fused(tri, side);
+      r3_fused(tri, side && tri == Prec::FP64);
     else
       e.terms(kCCR3, count(kCCR3));
     e.prec = Prec::FP64;
@@ -405,7 +405,10 @@ void Context::residual_body(Prec tri) {
   tally_flops();
 }
 
-bool Context::side_ok(Prec tri) const { return tri == Prec::FP64 && side_buf_ != nullptr && fused_r3_ok(); }
+// The side products read an FP64 T3v and finish before the fused kernel, so
+// every precision can use them: with FP32 products the fused kernel then
+// rebuilds the same buffer in FP32.
+bool Context::side_ok(Prec) const { return side_buf_ != nullptr && fused_r3_ok(); }
 
 // T3v (FP64) first, then the integral rows, the NT / NN products and the
 // W3_vvvo / W3_ovoo T3 pieces (triples_side.hpp); the R1 / R2 gathers wait for

@@ -130,7 +130,7 @@ class Context {
   double* r3_fvvp_ = nullptr;   // F3_vv padded
   std::vector<GemmStats> r3_stats_;  // packed-GEMM flops of the replaced terms
   // T3 terms of the intermediates and of R1 / R2 from the FP64 T3v
-  // (triples_side.hpp), used with FP64 triples products
+  // (triples_side.hpp), FP64 whatever the precision of the triples products
   bool side_ok(Prec tri) const;
   void side_products();
   void side_r12();
