@@ -285,19 +285,29 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
   };
 
   const int nk = P.kt_begin[kSegs];
+  // MFMAs of one LDS stage: the operands of k step s + 1 are read into the
+  // other register set while the MFMAs of step s issue (the scheduler is asked
+  // to interleave the LDS reads with the MFMAs), so a step's LDS latency is
+  // covered by the previous step's matrix work
   auto mma_stage = [&](int cur) {
-#pragma unroll
-    for (int ks = 0; ks < kBK; ks += 4) {
+    T af[2][2], bf[2][4];
+    auto read = [&](int ks, int r) {
       const int kr = ks + (lane >> 4);
-      T af[2], bf[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) af[r][i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bf[r][j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+    };
+    __builtin_amdgcn_iglp_opt(0);
+    read(0, 0);
+#pragma unroll
+    for (int st = 0; st < kBK / 4; ++st) {
+      const int r = st & 1;
+      if (st + 1 < kBK / 4) read(4 * (st + 1), r ^ 1);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[i], bf[j], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[r][i], bf[r][j], acc[i][j]);
     }
   };
   // one k tile in flight: the loads of tile kt + 1 are issued before the
