@@ -271,7 +271,7 @@ int fno_eom_sigma_dev(fno_ctx *ctx, fno_eom_kind kind, fno_prec prec, const doub
  * W3_ovoo [o (m)][v (c)][C(o,2) (jk)], W3_oooo [C(o,2)(mn)][C(o,2)(ij)] and
  * F3_oo [o (m)][o (i)], all FP64 (the intermediates a context builds from
  * T1, T2, T3; fno_debug_tensor shows them).  3 <= nocc, nvir <= 64; prec
- * FNO_FP64 or FNO_FP32 (products; R3 accumulates in FP64).  Work runs on
+ * FNO_FP64, FNO_FP32 or FNO_BF16X3 (products; R3 accumulates in FP64).  Work runs on
  * `stream` (NULL: the device's null stream); the call allocates its working
  * buffers (about 2 C(o,3) v C(v,2) values of the product type) for its own
  * duration and returns after the stream has finished.  Inputs are read only,

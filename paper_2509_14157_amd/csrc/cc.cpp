@@ -383,7 +383,7 @@ void Context::residual_body(Prec tri) {
       e.terms(kCCInter3, count(kCCInter3));
     }
     e.prec = tri;
-    if (fused_r3_ok() && tri != Prec::BF16X3)  // split-BF16 products run per term
+    if (fused_r3_ok())
       r3_fused(tri, side && tri == Prec::FP64);
     else
       e.terms(kCCR3, count(kCCR3));
@@ -422,7 +422,7 @@ void Context::side_products() {
   e.timed_launch("fno::r3_t3v_kernel", "T3v", 0,
                  8.0 * (double)tblocks_[2].size + 8.0 * (double)r3_fused_t3v_elems(o, v),
                  [&]() { launch_r3_t3v(e.tables, o, v, T3, r3_t3v_, Prec::FP64, e.stream); });
-  e.timed_launch("fno::side_operands_kernel", "side T3 terms: integral rows", 0,
+  e.timed_launch("fno::side_slab_kernel + side_a2_kernel", "side T3 terms: integral rows", 0,
                  8.0 * (double)(sh.a2 + (int64_t)sh.nt * sh.mt2 * 64 * sh.ep),
                  [&]() { launch_side_operands(e.tables, sh, e.get("Gd")->d, e.get("Fd")->d, side_buf_, e.stream); });
   double fl = 0;
@@ -502,7 +502,9 @@ void Context::r3_fused(Prec tri, bool t3v_ready) {
   const double no2 = (double)binom_host(o, 2), nv2 = (double)binom_host(v, 2);
   const double fused_bytes = 2.0 * ybytes + esz * nv2 * (double)a.ldy +
                              8.0 * ((double)r3_ring_operand_elems(o, v) + o * v * nv2 + o * v * no2 + no2 * nv2);
-  e.timed_launch(tri == Prec::FP64 ? "fno::r3_fused_kernel<double>" : "fno::r3_fused_kernel<float>",
+  e.timed_launch(tri == Prec::FP64   ? "fno::r3_fused_kernel<double>"
+                 : tri == Prec::FP32 ? "fno::r3_fused_kernel<float>"
+                                     : "fno::r3_fused_kernel<float, true>",
                  "R3 fused: pp-ladder, ring, drivers, one-body vv", fl, fused_bytes,
                  [&]() { launch_r3_fused(e.tables, a, tri, e.stream); });
   e.timed_launch("fno::r3_fold_kernel", "R3 fused: P(a/bc) fold", 0, 3.0 * ybytes / v + 2.0 * bytes_t3,

@@ -1182,10 +1182,12 @@ void Engine::execute(const Plan& p, double scale) {
   int64_t lda = p.lda, ldb = p.ldb;
   // rows of a table-expanded operand start 16-byte aligned, so the GEMM can
   // use vector loads: 16-element boundaries for wide rows, 4-element ones
-  // for rows of 16..127 (at most 19% padding); narrower rows stay packed
-  auto padded = [](bool tab_ok, int64_t cols) {
+  // (8 for the 2-byte split-BF16 halves) for rows of 16..127; narrower rows
+  // stay packed
+  const int64_t mid_align = prec == Prec::BF16X3 ? 8 : 4;
+  auto padded = [mid_align](bool tab_ok, int64_t cols) {
     if (!tab_ok || cols < 16) return cols;
-    return cols >= 128 ? (cols + 15) / 16 * 16 : (cols + 3) / 4 * 4;
+    return cols >= 128 ? (cols + 15) / 16 * 16 : (cols + mid_align - 1) / mid_align * mid_align;
   };
   auto expand_into = [&](const Tensor* t, bool tab_ok, const ExpandTab& tab, const OperandDesc& od, const MatDim& r,
                          const MatDim& c, void* hi, void* lo, int64_t ld) {

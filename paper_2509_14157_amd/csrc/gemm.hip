@@ -456,17 +456,107 @@ __global__ void __launch_bounds__(256, 2) gemm_db_kernel(int64_t M, int64_t N, i
 }
 
 // ---------------------------------------------------------------------------
-// Split-BF16 path: operands arrive as hi/lo BF16 pairs.  BK = 32.
-template <int BM, int BN, bool AK, bool BN_FAST>
-__global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, int64_t K,
-                                                          const __bf16* __restrict__ Ah,
-                                                          const __bf16* __restrict__ Al, int64_t lda,
-                                                          const __bf16* __restrict__ Bh,
-                                                          const __bf16* __restrict__ Bl, int64_t ldb,
-                                                          float* __restrict__ C, int64_t ldc, float alpha,
-                                                          float beta, int64_t kchunk, int64_t cz, int m_fast) {
-  constexpr int BK = 32;
-  {
+// Split-BF16 path: operands arrive as hi/lo BF16 pairs (x = hi + lo); three
+// v_mfma_f32_16x16x32_bf16 per k step (lo*hi + hi*lo + hi*hi) with FP32
+// accumulation.  The LDS tiles hold every operand row k-contiguous ([m][k]
+// and [n][k], hi and lo apart), so the eight k values of one MFMA lane
+// (row = lane % 16, k = 8 (lane / 16) + 0..7) are one 16-byte LDS read.
+// BK = 32 is one MFMA k step; two LDS stages, one barrier per k tile, the
+// next tile in flight from global memory while the MFMAs of this one run.
+// Staging of an operand tile of R rows (R = 32, 64, 128) and 32 k values:
+//   k fastest in memory: runs of 8 k values of one row, each one 16-byte
+//     load and one 16-byte LDS write (R / 32 runs per thread);
+//   rows fastest in memory: runs of 8 rows at KQ = R / 32 consecutive k
+//     values per thread, transposed in registers into 8 LDS writes of KQ k
+//     values; the lanes of a wavefront walk k first, so that each LDS write
+//     instruction covers whole rows.
+// VEC: every run starts 16-byte aligned (leading dimensions are multiples
+// of 8); runs crossing an operand edge, and every run of VEC = false, load
+// element by element.
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+
+constexpr int kB3K = 32;       // k values per staged tile
+constexpr int kB3KP = 32 + 8;  // LDS row length (bf16): 80-byte rows, conflict-free 16-byte reads
+
+template <bool VEC>
+__device__ __forceinline__ bf8_t b3_run(const __bf16* p, int64_t fast, int64_t end, bool ok) {
+  const __bf16 z = (__bf16)0.0f;
+  bf8_t v = (bf8_t){z, z, z, z, z, z, z, z};
+  if (!ok) return v;
+  if (VEC && fast + 8 <= end) return *(const bf8_t*)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+    if (fast + i < end) v[i] = p[i];
+  return v;
+}
+
+// one operand's staging: R rows of the tile, memory k-fast (KF) or rows-fast
+template <int R, bool KF, bool VEC>
+struct B3Op {
+  static constexpr int KQ = R / 32;                // rows-fast: k values per thread
+  static constexpr int NR = KF ? R / 32 : KQ;      // runs held per thread
+  static constexpr int KQN = kB3K / KQ;            // rows-fast: k groups per row block
+  bf8_t r[NR];
+
+  __device__ __forceinline__ void load(const __bf16* hi, const __bf16* lo, int64_t ld, int64_t rows, int64_t K,
+                                       int64_t r0, int64_t k0, int tid) {
+    if constexpr (KF) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const int u = tid + j * 256;
+        const int arr = u / (4 * R), rem = u % (4 * R), row = rem >> 2, k8 = rem & 3;
+        const int64_t gr = r0 + row, gk = k0 + 8 * k8;
+        const __bf16* base = arr ? lo : hi;
+        r[j] = b3_run<VEC>(base + (gr < rows ? gr : 0) * ld + gk, gk, K, gr < rows);
+      }
+    } else {
+      const int arr = tid >> 7, u = tid & 127, kq = u % KQN, rb = u / KQN;
+      const __bf16* base = arr ? lo : hi;
+      const int64_t gr = r0 + 8 * rb;
+#pragma unroll
+      for (int q = 0; q < KQ; ++q) {
+        const int64_t gk = k0 + kq * KQ + q;
+        r[q] = b3_run<VEC>(base + (gk < K ? gk : 0) * ld + gr, gr, rows, gk < K);
+      }
+    }
+  }
+
+  // S: this stage's [2 (hi, lo)][R][kB3KP]
+  __device__ __forceinline__ void store(__bf16 (*S)[R][kB3KP], int tid) const {
+    if constexpr (KF) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        const int u = tid + j * 256;
+        const int arr = u / (4 * R), rem = u % (4 * R), row = rem >> 2, k8 = rem & 3;
+        *(bf8_t*)&S[arr][row][8 * k8] = r[j];
+      }
+    } else {
+      const int arr = tid >> 7, u = tid & 127, kq = u % KQN, rb = u / KQN;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        __bf16* d = &S[arr][8 * rb + i][kq * KQ];
+        if constexpr (KQ == 4) {
+          *(bf4_t*)d = (bf4_t){r[0][i], r[1][i], r[2][i], r[3][i]};
+        } else if constexpr (KQ == 2) {
+          *(bf2_t*)d = (bf2_t){r[0][i], r[1][i]};
+        } else {
+          *d = r[0][i];
+        }
+      }
+    }
+  }
+};
+
+template <int BM, int BN, bool AK, bool BN_FAST, bool VEC>
+__global__ void __launch_bounds__(256, 2) gemm_bf16x3_kernel(int64_t M, int64_t N, int64_t K,
+                                                             const __bf16* __restrict__ Ah,
+                                                             const __bf16* __restrict__ Al, int64_t lda,
+                                                             const __bf16* __restrict__ Bh,
+                                                             const __bf16* __restrict__ Bl, int64_t ldb,
+                                                             float* __restrict__ C, int64_t ldc, float alpha,
+                                                             float beta, int64_t kchunk, int64_t cz, int m_fast) {
+  {  // split-K: this z-slice owns K range [z*kchunk, z*kchunk + kchunk)
     const int64_t k0 = (int64_t)blockIdx.z * kchunk;
     const int64_t ao = AK ? k0 : k0 * lda, bo = BN_FAST ? k0 * ldb : k0;
     Ah += ao;
@@ -478,12 +568,8 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
   }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
-  constexpr int A_PER = BM * BK / 256;
-  constexpr int B_PER = BN * BK / 256;
-  // LDS layout [row][k] so that a lane's 8 consecutive k values are one 16-byte read.
-  constexpr int KP = BK + 8;
-  __shared__ __bf16 Ash[BM][KP], Asl[BM][KP];
-  __shared__ __bf16 Bsh[BN][KP], Bsl[BN][KP];
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][2][BM][kB3KP];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][2][BN][kB3KP];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -498,112 +584,56 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
 #pragma unroll
     for (int j = 0; j < TN; ++j) acc[i][j] = (f4_t){0, 0, 0, 0};
 
-  __bf16 rah[A_PER], ral[A_PER], rbh[B_PER], rbl[B_PER];
-  const __bf16 zero = (__bf16)0.0f;
-  auto load_tiles = [&](int64_t k0) {
-#pragma unroll
-    for (int p = 0; p < A_PER; ++p) {
-      int e = tid + p * 256;
-      int mm, kk;
-      if (AK) {
-        kk = e % BK;
-        mm = e / BK;
-      } else {
-        mm = e % BM;
-        kk = e / BM;
-      }
-      int64_t gm = m0 + mm, gk = k0 + kk;
-      __bf16 h = zero, l = zero;
-      if (gm < M && gk < K) {
-        int64_t o = AK ? gm * lda + gk : gk * lda + gm;
-        h = Ah[o];
-        l = Al[o];
-      }
-      rah[p] = h;
-      ral[p] = l;
-    }
-#pragma unroll
-    for (int p = 0; p < B_PER; ++p) {
-      int e = tid + p * 256;
-      int nn, kk;
-      if (BN_FAST) {
-        nn = e % BN;
-        kk = e / BN;
-      } else {
-        kk = e % BK;
-        nn = e / BK;
-      }
-      int64_t gn = n0 + nn, gk = k0 + kk;
-      __bf16 h = zero, l = zero;
-      if (gn < N && gk < K) {
-        int64_t o = BN_FAST ? gk * ldb + gn : gn * ldb + gk;
-        h = Bh[o];
-        l = Bl[o];
-      }
-      rbh[p] = h;
-      rbl[p] = l;
-    }
-  };
-  auto store_tiles = [&]() {
-#pragma unroll
-    for (int p = 0; p < A_PER; ++p) {
-      int e = tid + p * 256;
-      int mm, kk;
-      if (AK) {
-        kk = e % BK;
-        mm = e / BK;
-      } else {
-        mm = e % BM;
-        kk = e / BM;
-      }
-      Ash[mm][kk] = rah[p];
-      Asl[mm][kk] = ral[p];
-    }
-#pragma unroll
-    for (int p = 0; p < B_PER; ++p) {
-      int e = tid + p * 256;
-      int nn, kk;
-      if (BN_FAST) {
-        nn = e % BN;
-        kk = e / BN;
-      } else {
-        kk = e % BK;
-        nn = e / BK;
-      }
-      Bsh[nn][kk] = rbh[p];
-      Bsl[nn][kk] = rbl[p];
-    }
-  };
-
-  const int64_t nk = (K + BK - 1) / BK;
-  if (nk > 0) load_tiles(0);
+  B3Op<BM, AK, VEC> sa;
+  B3Op<BN, !BN_FAST, VEC> sb;
+  const int64_t nk = (K + kB3K - 1) / kB3K;
+  if (nk > 0) {
+    sa.load(Ah, Al, lda, M, K, m0, 0, tid);
+    sb.load(Bh, Bl, ldb, N, K, n0, 0, tid);
+    sa.store(As[0], tid);
+    sb.store(Bs[0], tid);
+  }
+  __syncthreads();
+  const int kb = 8 * (lane >> 4);
   for (int64_t kt = 0; kt < nk; ++kt) {
-    __syncthreads();
-    store_tiles();
-    __syncthreads();
-    if (kt + 1 < nk) load_tiles((kt + 1) * BK);
-    const int kb = 8 * (lane >> 4);
+    const int cur = (int)(kt & 1);
+    const bool more = kt + 1 < nk;
+    if (more) {
+      sa.load(Ah, Al, lda, M, K, m0, (kt + 1) * kB3K, tid);
+      sb.load(Bh, Bl, ldb, N, K, n0, (kt + 1) * kB3K, tid);
+    }
     bf8_t ah[TM], al[TM], bh[TN], bl[TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i) {
       const int r = wm * WM + i * 16 + (lane & 15);
-      ah[i] = *(const bf8_t*)&Ash[r][kb];
-      al[i] = *(const bf8_t*)&Asl[r][kb];
+      ah[i] = *(const bf8_t*)&As[cur][0][r][kb];
+      al[i] = *(const bf8_t*)&As[cur][1][r][kb];
     }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
       const int c = wn * WN + j * 16 + (lane & 15);
-      bh[j] = *(const bf8_t*)&Bsh[c][kb];
-      bl[j] = *(const bf8_t*)&Bsl[c][kb];
+      bh[j] = *(const bf8_t*)&Bs[cur][0][c][kb];
+      bl[j] = *(const bf8_t*)&Bs[cur][1][c][kb];
     }
+    // the three products in three sweeps over the accumulators: consecutive
+    // MFMAs never wait on each other's result
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-      }
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      sa.store(As[cur ^ 1], tid);
+      sb.store(Bs[cur ^ 1], tid);
+    }
+    __syncthreads();
   }
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -621,7 +651,6 @@ __global__ void __launch_bounds__(256) gemm_bf16x3_kernel(int64_t M, int64_t N, 
       }
     }
 }
-
 // ---------------------------------------------------------------------------
 // Tile table used by the planner and the autotuner.
 struct TileCfg {
@@ -770,31 +799,47 @@ static void launch_k4(const GemmArgs& g, hipStream_t s) {
   }
 }
 
+// Every operand row (and split-K slice, cut at multiples of 32 k) of both
+// split-BF16 operands starts 16-byte aligned: the vector-load staging applies.
+static bool b3_rows_aligned(const GemmArgs& g) {
+  auto al = [](const void* p) { return ((uintptr_t)p % 16) == 0; };
+  return al(g.A) && al(g.A_lo) && al(g.B) && al(g.B_lo) && g.lda % 8 == 0 && g.ldb % 8 == 0;
+}
+
+template <int BM, int BN, bool AK, bool BF>
+static void b3_launch(dim3 grid, hipStream_t s, const GemmArgs& g, float* C, int64_t ldc, float al, float be,
+                      int64_t kchunk, int64_t cz, int mf, bool vec) {
+  const __bf16 *Ah = (const __bf16*)g.A, *Al = (const __bf16*)g.A_lo;
+  const __bf16 *Bh = (const __bf16*)g.B, *Bl = (const __bf16*)g.B_lo;
+  if (vec)
+    gemm_bf16x3_kernel<BM, BN, AK, BF, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C, ldc,
+                                                                  al, be, kchunk, cz, mf);
+  else
+    gemm_bf16x3_kernel<BM, BN, AK, BF, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
+                                                                   ldc, al, be, kchunk, cz, mf);
+}
+
 template <int BM, int BN>
 static void launch_b3(const GemmArgs& g, hipStream_t s) {
   const int split = g.split > 1 ? g.split : 1;
-  const int64_t kchunk = split > 1 ? (((g.K + split - 1) / split + 31) / 32) * 32 : (g.K > 0 ? g.K : 1);
+  const int64_t kchunk =
+      split > 1 ? (((g.K + split - 1) / split + kB3K - 1) / kB3K) * kB3K : (g.K > 0 ? g.K : 1);
   const int nz = split > 1 ? (int)((g.K + kchunk - 1) / kchunk) : 1;
   dim3 grid((unsigned)(((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM)), 1u, (unsigned)nz);
   const int mf = m_fast_order(g);
-  const __bf16 *Ah = (const __bf16*)g.A, *Al = (const __bf16*)g.A_lo;
-  const __bf16 *Bh = (const __bf16*)g.B, *Bl = (const __bf16*)g.B_lo;
   float* C = split > 1 ? (float*)g.ws : (float*)g.C;
   const int64_t ldc = split > 1 ? g.N : g.ldc;
   const int64_t cz = split > 1 ? g.M * g.N : 0;
   float al = split > 1 ? 1.0f : (float)g.alpha, be = split > 1 ? 0.0f : (float)g.beta;
+  const bool vec = b3_rows_aligned(g);
   if (g.a_kfast && g.b_nfast)
-    gemm_bf16x3_kernel<BM, BN, true, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                               ldc, al, be, kchunk, cz, mf);
+    b3_launch<BM, BN, true, true>(grid, s, g, C, ldc, al, be, kchunk, cz, mf, vec);
   else if (g.a_kfast)
-    gemm_bf16x3_kernel<BM, BN, true, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                ldc, al, be, kchunk, cz, mf);
+    b3_launch<BM, BN, true, false>(grid, s, g, C, ldc, al, be, kchunk, cz, mf, vec);
   else if (g.b_nfast)
-    gemm_bf16x3_kernel<BM, BN, false, true><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                ldc, al, be, kchunk, cz, mf);
+    b3_launch<BM, BN, false, true>(grid, s, g, C, ldc, al, be, kchunk, cz, mf, vec);
   else
-    gemm_bf16x3_kernel<BM, BN, false, false><<<grid, 256, 0, s>>>(g.M, g.N, g.K, Ah, Al, g.lda, Bh, Bl, g.ldb, C,
-                                                                 ldc, al, be, kchunk, cz, mf);
+    b3_launch<BM, BN, false, false>(grid, s, g, C, ldc, al, be, kchunk, cz, mf, vec);
   if (split > 1) {
     launch_splitk_reduce<float>((const float*)g.ws, nz, g.M, g.N, (float*)g.C, g.ldc, (float)g.alpha,
                                 (float)g.beta, s);
@@ -912,7 +957,8 @@ std::string gemm_label(const GemmArgs& g) {
   std::string lay = std::string(g.a_kfast ? "true" : "false") + ", " + (g.b_nfast ? "true" : "false");
   if (g.prec == Prec::BF16X3) {
     if (kTiles[t].bm == 256 || kTiles[t].bn == 256) bm = "128", bn = "64";
-    return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ">";
+    return "fno::gemm_bf16x3_kernel<" + bm + ", " + bn + ", " + lay + ", " + (b3_rows_aligned(g) ? "true" : "false") +
+           ">";
   }
   if (kTiles[t].bk > 0)
     return std::string("fno::gemm_db_kernel<") + (g.prec == Prec::FP64 ? "double" : "float") + ", " + bm + ", " +

@@ -74,22 +74,51 @@ struct Params {
   int panel;                   // triples per panel of the tile order
 };
 
+// LDS tiles of one k tile, two stages.  FP64 / FP32: k-major tiles, one
+// element per lane per v_mfma_*_16x16x4 step.  Split-BF16: the staged FP32
+// values split into hi + lo BF16 halves (x = hi + lo to about 16 bits),
+// stored with k contiguous per row, so that the four k values of a lane of
+// v_mfma_f32_16x16x16_bf16 (row = lane % 16, k = 4 (lane / 16) + 0..3) are
+// one 8-byte LDS read; rows padded to 40 bytes.
+constexpr int kB3Row = kBK + 4;
+template <typename T, bool B3>
+struct FusedTiles {
+  T As[2][kBK][kBM + 1];
+  __attribute__((aligned(16))) T Bs[2][kBK][kBN + ((sizeof(T) == 8) ? 2 : 4)];  // B rows 16-byte aligned
+};
+template <>
+struct FusedTiles<float, true> {
+  __attribute__((aligned(16))) unsigned short Ah[2][2][kBM][kB3Row];  // [stage][hi, lo][row a][k]
+  __attribute__((aligned(16))) unsigned short Bh[2][2][kBN][kB3Row];  // [stage][hi, lo][column bc][k]
+};
+
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef unsigned short u4_t __attribute__((ext_vector_type(4)));
+
+// x = hi + lo, both rounded to nearest even BF16 (hi from x, lo from x - hi)
+__device__ __forceinline__ void split_bf16(float x, unsigned short& h, unsigned short& l) {
+  const __bf16 hb = (__bf16)x;
+  const __bf16 lb = (__bf16)(x - (float)hb);
+  h = __builtin_bit_cast(unsigned short, hb);
+  l = __builtin_bit_cast(unsigned short, lb);
+}
+
 // Element mappings of the staged tiles (uniform per k tile):
 //   A: 0 = rows of 16-byte vectors along k (pp-ladder, rows of T3v),
 //      1 = one element per lane with k fastest, 2 = one element per lane with
 //      the row fastest (k uniform per wavefront)
 //   B: 0 = rows of 16-byte vectors along the columns (k uniform per vector
 //      row: W3_vvvv^T, T3v), 1 = one element per lane, column fastest
-template <typename T>
+// (B3: split-BF16 products from FP32 operands, T = float)
+template <typename T, bool B3 = false>
 __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
   constexpr int VW = 16 / sizeof(T);          // elements per 16-byte vector
   constexpr int AV = kBM * kBK / VW / kThreads;  // A vectors per thread
   constexpr int BV = kBK * kBN / VW / kThreads;  // B vectors per thread
-  constexpr int PAD = (sizeof(T) == 8) ? 2 : 4;  // keeps B rows 16-byte aligned
   typedef T Vec __attribute__((ext_vector_type(VW)));
   static_assert(AV * VW == 4 && BV * VW == 8, "slot counts");
-  __shared__ T As[2][kBK][kBM + 1];
-  __shared__ __attribute__((aligned(16))) T Bs[2][kBK][kBN + PAD];
+  static_assert(!B3 || sizeof(T) == 4, "split-BF16 stages FP32 values");
+  __shared__ FusedTiles<T, B3> L;
   const R3FusedArgs& g = P.a;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -158,9 +187,18 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       }
     }
   };
+  // k of the i-th B element a thread stages in the element-wise modes:
+  // split-BF16 gives each thread 8 consecutive k of one column (stored as
+  // k-contiguous LDS runs), the other precisions k = tid / 128 + 2 i
+  auto bk = [&](int i) { return B3 ? 8 * (tid >> 7) + i : (tid >> 7) + 2 * i; };
   // B[kk][n] = scale * bbase[kk * ldb + n]  (bbase already at column n0)
   auto load_b_rows = [&](Regs& R, const T* bbase, int64_t ldb, T scale) {
     R.bmode = 0;
+    if constexpr (B3) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) R.b[i] = scale * bbase[(int64_t)bk(i) * ldb + (tid & (kBN - 1))];
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < BV; ++i) {
       const int q = tid + kThreads * i;
@@ -221,7 +259,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       R.bmode = 1;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i, c = n0 + (tid & (kBN - 1));
+        const int k = k0 + bk(i), c = n0 + (tid & (kBN - 1));
         R.b[i] = (T)((k < K && c < nv2) ? g.Wvvvo[((int64_t)x * v + k) * nv2 + c] : 0.0);
       }
     } else {
@@ -240,7 +278,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       R.bmode = 1;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        const int k = k0 + (tid >> 7) + 2 * i, c = n0 + (tid & (kBN - 1));
+        const int k = k0 + bk(i), c = n0 + (tid & (kBN - 1));
         double val = 0;
         if (k < K && c < nv2 && k != x) {
           const int lo = k < x ? k : x, hi = k < x ? x : k;
@@ -253,20 +291,61 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
   };
 
   auto store_tile = [&](int st, const Regs& R) {
+    if constexpr (B3) {
+      // A rows: 4 consecutive k of row a per vector (mode 0) or single
+      // elements; B: 8 consecutive k of one column per thread
+      unsigned short h, l;
+      if (R.amode == 0) {
+        const int a = tid / (kBK / VW), kv = (tid % (kBK / VW)) * VW;
+        u4_t vh, vl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          split_bf16(R.a[j], h, l);
+          vh[j] = h;
+          vl[j] = l;
+        }
+        *(u4_t*)&L.Ah[st][0][a][kv] = vh;
+        *(u4_t*)&L.Ah[st][1][a][kv] = vl;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int k = R.amode == 1 ? (tid & 15) : wave + 4 * i;
+          const int a = R.amode == 1 ? (tid >> 4) + 16 * i : lane;
+          split_bf16(R.a[i], h, l);
+          L.Ah[st][0][a][k] = h;
+          L.Ah[st][1][a][k] = l;
+        }
+      }
+      {  // both B modes: 8 consecutive k of column c, two 8-byte runs per half
+        const int c = tid & (kBN - 1), k8 = bk(0);
+        u4_t vh[2], vl[2];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          split_bf16(R.b[i], h, l);
+          vh[i >> 2][i & 3] = h;
+          vl[i >> 2][i & 3] = l;
+        }
+        *(u4_t*)&L.Bh[st][0][c][k8] = vh[0];
+        *(u4_t*)&L.Bh[st][0][c][k8 + 4] = vh[1];
+        *(u4_t*)&L.Bh[st][1][c][k8] = vl[0];
+        *(u4_t*)&L.Bh[st][1][c][k8 + 4] = vl[1];
+      }
+      return;
+    } else {
     if (R.amode == 0) {
 #pragma unroll
       for (int i = 0; i < AV; ++i) {
         const int q = tid + kThreads * i;
         const int a = q / (kBK / VW), kv = (q % (kBK / VW)) * VW;
 #pragma unroll
-        for (int j = 0; j < VW; ++j) As[st][kv + j][a] = R.a[i * VW + j];
+        for (int j = 0; j < VW; ++j) L.As[st][kv + j][a] = R.a[i * VW + j];
       }
     } else if (R.amode == 1) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) As[st][tid & 15][(tid >> 4) + 16 * i] = R.a[i];
+      for (int i = 0; i < 4; ++i) L.As[st][tid & 15][(tid >> 4) + 16 * i] = R.a[i];
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) As[st][wave + 4 * i][lane] = R.a[i];
+      for (int i = 0; i < 4; ++i) L.As[st][wave + 4 * i][lane] = R.a[i];
     }
     if (R.bmode == 0) {
 #pragma unroll
@@ -276,11 +355,12 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
         Vec x;
 #pragma unroll
         for (int j = 0; j < VW; ++j) x[j] = R.b[i * VW + j];
-        *(Vec*)&Bs[st][kk][nv] = x;
+        *(Vec*)&L.Bs[st][kk][nv] = x;
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[st][(tid >> 7) + 2 * i][tid & (kBN - 1)] = R.b[i];
+      for (int i = 0; i < 8; ++i) L.Bs[st][(tid >> 7) + 2 * i][tid & (kBN - 1)] = R.b[i];
+    }
     }
   };
 
@@ -290,13 +370,44 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
   // to interleave the LDS reads with the MFMAs), so a step's LDS latency is
   // covered by the previous step's matrix work
   auto mma_stage = [&](int cur) {
+    if constexpr (B3) {
+      // one 16 x 16 x 16 step per tile and block: lo*hi, hi*lo, then hi*hi,
+      // each a sweep over the 8 accumulators
+      const int kb = 4 * (lane >> 4);
+      s4_t ah[2], al[2], bh[4], bl[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = wm * 32 + i * 16 + (lane & 15);
+        ah[i] = *(const s4_t*)&L.Ah[cur][0][r][kb];
+        al[i] = *(const s4_t*)&L.Ah[cur][1][r][kb];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int c = wn * 64 + j * 16 + (lane & 15);
+        bh[j] = *(const s4_t*)&L.Bh[cur][0][c][kb];
+        bl[j] = *(const s4_t*)&L.Bh[cur][1][c][kb];
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      return;
+    } else {
     T af[2][2], bf[2][4];
     auto read = [&](int ks, int r) {
       const int kr = ks + (lane >> 4);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[r][i] = As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) af[r][i] = L.As[cur][kr][wm * 32 + i * 16 + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bf[r][j] = Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
+      for (int j = 0; j < 4; ++j) bf[r][j] = L.Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
     };
     __builtin_amdgcn_iglp_opt(0);
     read(0, 0);
@@ -308,6 +419,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[r][i], bf[r][j], acc[i][j]);
+    }
     }
   };
   // one k tile in flight: the loads of tile kt + 1 are issued before the
@@ -343,24 +455,47 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
 }
 
 // T3v[t][x][p] = T3[t, x, p0, p1] (p = pair p0 < p1; zero for x in the pair
-// and for p >= C(v,2)): a thread per element, pairs fastest
+// and for p >= C(v,2)), one workgroup per occupied triple t and largest
+// letter c.  The colex block T3[t, (a < b < c)] (C(c,2) values, contiguous)
+// is read once, coalesced, and staged in LDS; it supplies
+//   row c, pairs p < C(c,2):            T3v[t][c][a + C(b,2)] = T3[t, abc]
+//   rows x <= c, pairs (p0, c):         T3v[t][x][p0 + C(c,2)] = -T3[t, p0 x c] (p0 < x)
+//                                                               +T3[t, x p0 c] (p0 > x)
+//                                                               0              (p0 == x or x == c)
+// and the padding pairs p >= C(v,2) of row c.  Every element of T3v is
+// written by exactly one workgroup; the workgroups after the last triple
+// write the padding rows.
+constexpr int kT3vMaxV = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(256) r3_t3v_kernel(IndexTables tb, int v, int nv2, int nv3, int64_t ldy,
-                                                     int64_t rows, int64_t rows_all, const double* __restrict__ T3,
-                                                     T* __restrict__ T3v) {
-  const int64_t blk_per_row = (ldy + 255) / 256;
-  const int64_t row = blockIdx.x / blk_per_row;  // (t, x); rows >= `rows` are padding
-  const int64_t p = (blockIdx.x % blk_per_row) * 256 + threadIdx.x;
-  if (row >= rows_all || p >= ldy) return;
-  const int t = (int)(row / v), x = (int)(row % v);
-  double val = 0;
-  if (row < rows && p < nv2) {
-    const int p0 = tb.dec[2][2 * p], p1 = tb.dec[2][2 * p + 1];
-    int sg;
-    const int r = tri_rank(x, p0, p1, sg);
-    if (sg) val = sg * T3[(int64_t)t * nv3 + r];
+__global__ void __launch_bounds__(256) r3_t3v_kernel(int v, int nv2, int nv3, int64_t ldy, int64_t rows,
+                                                     const double* __restrict__ T3, T* __restrict__ T3v) {
+  __shared__ double blk[kT3vMaxV * (kT3vMaxV - 1) / 2];
+  const int64_t nblk = rows;  // one per (t, c)
+  const int tid = threadIdx.x;
+  if ((int64_t)blockIdx.x >= nblk) {  // padding row
+    T* dst = T3v + (rows + ((int64_t)blockIdx.x - nblk)) * ldy;
+    for (int64_t i = tid; i < ldy; i += 256) dst[i] = (T)0;
+    return;
   }
-  T3v[row * ldy + p] = (T)val;
+  const int t = (int)(blockIdx.x / v), c = (int)(blockIdx.x % v);
+  const int nc = cb2(c);
+  const double* src = T3 + (int64_t)t * nv3 + cb3(c);
+  T* rowc = T3v + ((int64_t)t * v + c) * ldy;
+  for (int i = tid; i < nc; i += 256) {
+    const double x = src[i];
+    blk[i] = x;
+    rowc[i] = (T)x;
+  }
+  for (int i = nc + tid; i < nc + c; i += 256) rowc[i] = (T)0;
+  for (int64_t i = nv2 + tid; i < ldy; i += 256) rowc[i] = (T)0;
+  __syncthreads();
+  T* band = T3v + (int64_t)t * v * ldy + nc;
+  for (int e = tid; e < c * c; e += 256) {
+    const int x = e / c, p0 = e - x * c;
+    const double val = p0 < x ? -blk[p0 + cb2(x)] : (p0 > x ? blk[x + cb2(p0)] : 0.0);
+    band[(int64_t)x * ldy + p0] = (T)val;
+  }
 }
 
 // WT[ef][bc] = W[bc][ef] (square C(v,2) matrix, rows of WT padded to ldy with
@@ -530,8 +665,10 @@ void launch_r3_fused(const IndexTables& tb, const R3FusedArgs& a, Prec prec, hip
   FNO_REQUIRE(tiles < (1ll << 31), kEINVAL, "too many tiles");
   if (prec == Prec::FP64)
     r3_fused_kernel<double><<<dim3((unsigned)tiles), kThreads, 0, s>>>(P);
-  else
+  else if (prec == Prec::FP32)
     r3_fused_kernel<float><<<dim3((unsigned)tiles), kThreads, 0, s>>>(P);
+  else
+    r3_fused_kernel<float, true><<<dim3((unsigned)tiles), kThreads, 0, s>>>(P);
   FNO_HIP(hipGetLastError());
 }
 
@@ -565,13 +702,12 @@ void launch_r3_t3v(const IndexTables& tb, int o, int v, const double* T3, void* 
   const int nv2 = (int)binom_host(v, 2), nv3 = (int)binom_host(v, 3);
   const int64_t ldy = r3_fused_ldy(v), rows = (int64_t)binom_host(o, 3) * v;
   const int64_t rows_all = r3_fused_t3v_elems(o, v) / ldy;
-  const int64_t blocks = rows_all * ((ldy + 255) / 256);
+  FNO_REQUIRE(v <= kT3vMaxV, kEINVAL, "T3v: more than 64 virtual orbitals");
+  const int64_t blocks = rows_all;  // rows (t, c) first, then the padding rows
   if (prec == Prec::FP64)
-    r3_t3v_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
-                                                                 (double*)T3v);
+    r3_t3v_kernel<double><<<dim3((unsigned)blocks), 256, 0, s>>>(v, nv2, nv3, ldy, rows, T3, (double*)T3v);
   else
-    r3_t3v_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(tb, v, nv2, nv3, ldy, rows, rows_all, T3,
-                                                                (float*)T3v);
+    r3_t3v_kernel<float><<<dim3((unsigned)blocks), 256, 0, s>>>(v, nv2, nv3, ldy, rows, T3, (float*)T3v);
   FNO_HIP(hipGetLastError());
 }
 

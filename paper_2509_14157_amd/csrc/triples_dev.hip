@@ -151,11 +151,11 @@ Prec check_args(int device, int o, int v, fno_prec prec, const Inputs& in, const
   FNO_REQUIRE(device >= 0 && device < ndev && device < kDevMaxDevices, kEDEVICE, "no such HIP device");
   FNO_REQUIRE(o >= 3 && o <= kDevMaxN && v >= 3 && v <= kDevMaxN, kEINVAL,
               "the fused triples residual takes 3 <= nocc <= 64 and 3 <= nvir <= 64");
-  FNO_REQUIRE(prec == FNO_FP64 || prec == FNO_FP32, kEINVAL,
-              "the fused triples residual runs FP64 or FP32 products (split-BF16 runs per term)");
+  FNO_REQUIRE(prec == FNO_FP64 || prec == FNO_FP32 || prec == FNO_BF16X3, kEINVAL,
+              "the fused triples residual runs FP64, FP32 or split-BF16 products");
   FNO_REQUIRE(in.T3 && in.T2 && in.Wvvvv && in.Fvv && in.Wovvo && in.Wvvvo && in.Wovoo && in.Woooo && in.Foo && R3,
               kEINVAL, "null device buffer");
-  return prec == FNO_FP64 ? Prec::FP64 : Prec::FP32;
+  return prec == FNO_FP64 ? Prec::FP64 : (prec == FNO_FP32 ? Prec::FP32 : Prec::BF16X3);
 }
 
 }  // namespace fno

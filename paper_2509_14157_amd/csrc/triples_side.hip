@@ -1,8 +1,8 @@
 // T3 terms outside the triples residual from T3v (see triples_side.hpp).
 //
 // Kernels, in launch order:
-//   side_operands_kernel  integral rows of the products, 16-byte aligned and
-//                         zero padded (GoP, GvP, Gx, A2 below)
+//   side_slab_kernel      integral rows of the products, 16-byte aligned and
+//   side_a2_kernel        zero padded (GoP, GvP, Gx; A2 below)
 //   side_nt_kernel        S_t = A T3v[t]^T per triple: 64 x 64 tiles, both
 //                         operands read along the pair index ef
 //   side_nn_kernel<0>     W3_vvvo partial sums: per k, the pairs mn outside k
@@ -62,55 +62,74 @@ struct OpArgs {
 // GoP[q][ef]     = <mn||ef>        q = (m < n) < C(o,2), rows up to nto*64
 // GvP[m][b][ef]  = <bm||ef>        b < 64 rows per m
 // Gx[q][e][f]    = <mn||fe>        e < 64, f < ep
-// A2[t][r][e]    = <pair_p||j e>   r = p (o + 1) + j, j < o
-//                = F[t_p][e]       r = p (o + 1) + o
-// (ef a pair e < f, columns padded to ldy; every other element zero)
-__global__ void __launch_bounds__(256) side_operands_kernel(OpArgs P) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// (ef a pair e < f, columns padded to ldy; every other element zero), one
+// workgroup per row of GoP (with the Gx block of the same q) or of GvP.  The
+// two fixed indices select the v x v slab Gd[p][q][o + r][o + s], which is
+// read along s (contiguous in Gd), staged in LDS and written out in pair
+// order and, for Gx, transposed.
+__global__ void __launch_bounds__(256) side_slab_kernel(OpArgs P) {
+  __shared__ double sl[64][65];
   const SideShape& sh = P.sh;
   const int o = sh.o, v = sh.v, n = sh.n;
   const uint8_t* d2 = P.tb.dec[2];
-  auto G = [&](int p, int q, int r, int s) { return P.Gd[(((int64_t)p * n + q) * n + r) * n + s]; };
-  if (i < P.n_goP) {
-    const int64_t q = i / sh.ldy, c = i % sh.ldy;
-    double val = 0;
-    if (q < sh.no2 && c < sh.nv2) val = G(d2[2 * q], d2[2 * q + 1], o + d2[2 * c], o + d2[2 * c + 1]);
-    P.buf[sh.goP + i] = val;
-    return;
-  }
-  i -= P.n_goP;
-  if (i < P.n_gvP) {
-    const int64_t row = i / sh.ldy, c = i % sh.ldy;
-    const int m = (int)(row / 64), b = (int)(row % 64);
-    double val = 0;
-    if (b < v && c < sh.nv2) val = G(o + b, m, o + d2[2 * c], o + d2[2 * c + 1]);
-    P.buf[sh.gvP + i] = val;
-    return;
-  }
-  i -= P.n_gvP;
-  if (i < P.n_gx) {
-    const int64_t per = 64 * (int64_t)sh.ep;
-    const int q = (int)(i / per);
-    const int rem = (int)(i % per), e = rem / sh.ep, f = rem % sh.ep;
-    double val = 0;
-    if (e < v && f < v) val = G(d2[2 * q], d2[2 * q + 1], o + f, o + e);
-    P.buf[sh.gx + i] = val;
-    return;
-  }
-  i -= P.n_gx;
-  if (i < P.n_a2) {
-    const int64_t per = (int64_t)sh.mt2 * 64 * sh.ep;
-    const int t = (int)(i / per);
-    const int rem = (int)(i % per), r = rem / sh.ep, e = rem % sh.ep;
-    const int p = r / (o + 1), j = r % (o + 1);
-    double val = 0;
-    if (p < 3 && e < v) {
-      const uint8_t* d3 = P.tb.dec[3] + 3 * t;
-      const int x = d3[p], q0 = d3[p == 0 ? 1 : 0], q1 = d3[p == 2 ? 1 : 2];
-      val = j < o ? G(q0, q1, j, o + e) : P.Fd[(int64_t)x * n + o + e];
+  const int tid = threadIdx.x;
+  const int64_t ngo = (int64_t)sh.nto * 64, row = blockIdx.x;
+  int p = 0, q = 0;
+  bool live;
+  double* dst;
+  if (row < ngo) {
+    live = row < sh.no2;
+    if (live) {
+      p = d2[2 * row];
+      q = d2[2 * row + 1];
     }
-    P.buf[sh.a2 + i] = val;
+    dst = P.buf + sh.goP + row * sh.ldy;
+  } else {
+    const int64_t r2 = row - ngo;
+    const int m = (int)(r2 / 64), b = (int)(r2 % 64);
+    live = b < v;
+    p = o + b;
+    q = m;
+    dst = P.buf + sh.gvP + r2 * sh.ldy;
   }
+  if (live) {  // uniform per workgroup
+    const double* g = P.Gd + (((int64_t)p * n + q) * n + o) * n + o;
+    for (int e = tid; e < v * v; e += 256) {
+      const int r = e / v, c = e - r * v;
+      sl[r][c] = g[(int64_t)r * n + c];
+    }
+  }
+  __syncthreads();
+  for (int64_t c = tid; c < sh.ldy; c += 256) dst[c] = (live && c < sh.nv2) ? sl[d2[2 * c]][d2[2 * c + 1]] : 0.0;
+  if (row < sh.no2) {
+    double* gx = P.buf + sh.gx + row * 64 * sh.ep;
+    for (int e = tid; e < 64 * sh.ep; e += 256) {
+      const int r = e / sh.ep, f = e - r * sh.ep;
+      gx[e] = (r < v && f < v) ? sl[f][r] : 0.0;
+    }
+  }
+}
+
+// A2[t][r][e]    = <pair_p||j e>   r = p (o + 1) + j, j < o
+//                = F[t_p][e]       r = p (o + 1) + o
+// (e < ep; every other element zero), a thread per element (rows of Gd and
+// Fd read along e)
+__global__ void __launch_bounds__(256) side_a2_kernel(OpArgs P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P.n_a2) return;
+  const SideShape& sh = P.sh;
+  const int o = sh.o, v = sh.v, n = sh.n;
+  const int64_t per = (int64_t)sh.mt2 * 64 * sh.ep;
+  const int t = (int)(i / per);
+  const int rem = (int)(i % per), r = rem / sh.ep, e = rem % sh.ep;
+  const int p = r / (o + 1), j = r % (o + 1);
+  double val = 0;
+  if (p < 3 && e < v) {
+    const uint8_t* d3 = P.tb.dec[3] + 3 * t;
+    const int x = d3[p], q0 = d3[p == 0 ? 1 : 0], q1 = d3[p == 2 ? 1 : 2];
+    val = j < o ? P.Gd[(((int64_t)q0 * n + q1) * n + j) * n + o + e] : P.Fd[(int64_t)x * n + o + e];
+  }
+  P.buf[sh.a2 + i] = val;
 }
 
 struct NTArgs {
@@ -490,7 +509,8 @@ void launch_side_operands(const IndexTables& tb, const SideShape& sh, const doub
   P.n_gvP = (int64_t)sh.o * 64 * sh.ldy;
   P.n_gx = (int64_t)sh.no2 * 64 * sh.ep;
   P.n_a2 = (int64_t)sh.nt * sh.mt2 * 64 * sh.ep;
-  side_operands_kernel<<<blocks_for(P.n_goP + P.n_gvP + P.n_gx + P.n_a2), 256, 0, s>>>(P);
+  side_slab_kernel<<<dim3((unsigned)((int64_t)(sh.nto + sh.o) * 64)), 256, 0, s>>>(P);
+  side_a2_kernel<<<blocks_for(P.n_a2), 256, 0, s>>>(P);
   FNO_HIP(hipGetLastError());
 }
 

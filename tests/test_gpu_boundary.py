@@ -156,7 +156,7 @@ INTERMEDIATES = ("W3_vvvv", "F3_vv", "W3_ovvo", "W3_vvvo", "W3_ovoo", "W3_oooo",
 
 
 def triples_dev_inputs(P, o, v, seed):
-    """Amplitudes, the context's dressed intermediates at them and the context's R3 (FP64, FP32)."""
+    """Amplitudes, the context's dressed intermediates at them and the context's R3 (FP64, FP32, split-BF16)."""
     h = make_hamiltonian(o, v, seed)
     amps = random_amps(np.random.default_rng(seed), o, v)
     with _ctx(P, h) as c:
@@ -164,11 +164,12 @@ def triples_dev_inputs(P, o, v, seed):
         c.set_amplitudes(2, pack(amps[2], 2, 2))
         c.set_amplitudes(3, pack(amps[3], 3, 3))
         r32 = c.cc_residual("fp32")[2]
+        rb3 = c.cc_residual("bf16x3")[2]
         r64 = c.cc_residual("fp64")[2]
         arrays = {k: c.debug_tensor(k) for k in INTERMEDIATES}
         arrays["T3"] = c.get_amplitudes(3)
         arrays["T2"] = c.get_amplitudes(2)
-    return arrays, {"fp64": r64, "fp32": r32}
+    return arrays, {"fp64": r64, "fp32": r32, "bf16x3": rb3}
 
 
 @pytest.mark.parametrize("o,v", [(4, 12), (7, 24)])
@@ -181,15 +182,12 @@ def test_triples_residual_dev_matches_context(P, o, v):
     hip = HipBuffers()
     ptrs = {k: hip.upload(x) for k, x in arrays.items()}
     n3 = arrays["T3"].size
-    for prec in ("fp64", "fp32"):
+    for prec in ("fp64", "fp32", "bf16x3"):
         r3 = hip.upload(np.zeros(n3))
         P.triples_residual_dev(0, o, v, prec, ptrs, r3)
         assert np.array_equal(hip.download(r3, n3), ref[prec]), prec
     s = hip.stream()
     with pytest.raises(P.FnoError) as e:
         P.triples_residual_dev(0, o, 65, "fp64", ptrs, r3, s)
-    assert e.value.code == P.FNO_EINVAL
-    with pytest.raises(P.FnoError) as e:
-        P.triples_residual_dev(0, o, v, "bf16x3", ptrs, r3, s)
     assert e.value.code == P.FNO_EINVAL
     hip.close(s)

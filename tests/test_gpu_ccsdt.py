@@ -146,7 +146,7 @@ def test_fno_full_space_equals_canonical(P):
 #    to ~3,800 per element in the fused pass; measured 1.7e-7 (fused) and
 #    4.3e-8 (per term) at o=4, v=12 -> bound 2e-6;
 #  * split-BF16 (hi*hi + hi*lo + lo*hi of 8-bit halves, FP32 accumulation):
-#    about 16 significant bits per operand; measured 6.2e-6 -> bound 5e-5.
+#    about 16 significant bits per operand; measured 6.2e-6 (per term) -> bound 5e-5.
 # R1 and R2 stay FP64 in every mode (1e-11).
 MIXED_R3_TOL = {"fp32": 2e-6, "bf16x3": 5e-5}
 
@@ -165,6 +165,25 @@ def test_mixed_precision_residual_matches_oracle(P, prec, fused):
     refs = (R[1].ravel(), pack(R[2], 2, 2), pack(R[3], 3, 3))
     for k, (g, r) in enumerate(zip(got[:3], refs)):
         tol = MIXED_R3_TOL[prec] if k == 2 else 1e-11
+        assert np.abs(g - r).max() < tol * max(1.0, np.abs(r).max()), (k, np.abs(g - r).max())
+
+
+@pytest.mark.parametrize("o,v,seed", [(7, 24, 9), (8, 30, 6)])
+def test_fused_bf16x3_residual_matches_oracle(P, o, v, seed):
+    """The split-BF16 fused triples pass at sizes with several column tiles, a
+    ragged last one and ragged k tiles in every K segment: R3 against the FP64
+    oracle within the split-BF16 bound, R1 and R2 (FP64) within 1e-11."""
+    print(f"fused split-BF16 R3 parity o={o} v={v} seed={seed}", flush=True)
+    h = make_hamiltonian(o, v, seed)
+    amps = random_amps(np.random.default_rng(seed), o, v)
+    with _ctx(P, h) as c:
+        _set(c, amps)
+        c.set_fused(True)
+        got = c.cc_residual("bf16x3")
+    R = cc.cc_residual(h.fock, h.eri, o, amps)
+    refs = (R[1].ravel(), pack(R[2], 2, 2), pack(R[3], 3, 3))
+    for k, (g, r) in enumerate(zip(got[:3], refs)):
+        tol = MIXED_R3_TOL["bf16x3"] if k == 2 else 1e-11
         assert np.abs(g - r).max() < tol * max(1.0, np.abs(r).max()), (k, np.abs(g - r).max())
 
 

@@ -3,7 +3,7 @@
 Long-K shapes with a tiny output take the deterministic split-K path.
 
 Ragged shapes exercise the bounds of every tile; shapes whose leading dimensions are
-multiples of 4 run the 16-byte vector-load kernels.  Errors are measured
+multiples of 4 run the 16-byte vector-load kernels (multiples of 8 for split-BF16).  Errors are measured
 against sum_k |alpha a_ik b_kj| + |beta c_ij| (the scale of the rounding
 bound of each dot product): FP64 1e-13, FP32 1e-5, split-BF16 1e-4.
 """
@@ -28,9 +28,12 @@ def test_gemm_all_tiles_and_layouts(ctx, prec):
     bad = []
     for tile in range(17):  # every tile: 6 single-, 5 double-buffered, 256x64, 64x256, two with k depth 32, two FP32-only
         # (16, 16, 4), (132, 68, 40) and (260, 196, 36) have every leading dimension a
-        # multiple of 4: they take the 16-byte vector loads, with ragged M, N and K edges
+        # multiple of 4: they take the 16-byte vector loads, with ragged M, N and K edges;
+        # the last three have every leading dimension a multiple of 8, which the
+        # split-BF16 vector staging needs (ragged edges of 8, split-K with aligned slices)
         for (M, N, K) in ((37, 53, 29), (130, 70, 45), (16, 16, 4), (1, 70, 33), (257, 129, 3),
-                          (3, 5, 5000), (1, 1, 70001), (132, 68, 40), (260, 196, 36)):
+                          (3, 5, 5000), (1, 1, 70001), (132, 68, 40), (260, 196, 36),
+                          (264, 136, 72), (40, 48, 1000), (8, 16, 4096)):
             for ak in (True, False):
                 for bn in (True, False):
                     A = rng.normal(size=(M, K))

@@ -23,7 +23,8 @@ def test_noalloc_matches_allocating_entry_point(P):
     print("no-alloc triples residual: two calls, second smaller", flush=True)
     hip = HipBuffers()
     s = hip.stream()
-    for (o, v, seed), prec in (((7, 24, 9), "fp64"), ((4, 12, 3), "fp64"), ((5, 14, 2), "fp32")):
+    for (o, v, seed), prec in (((7, 24, 9), "fp64"), ((4, 12, 3), "fp64"), ((5, 14, 2), "fp32"),
+                               ((6, 16, 4), "bf16x3")):
         arrays, _ = triples_dev_inputs(P, o, v, seed)
         ptrs = {k: hip.upload(x) for k, x in arrays.items()}
         n3 = arrays["T3"].size
