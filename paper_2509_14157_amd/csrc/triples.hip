@@ -422,19 +422,46 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
     }
     }
   };
-  // one k tile in flight: the loads of tile kt + 1 are issued before the
-  // MFMAs of tile kt and stored to the other LDS stage after them
-  Regs R;
-  load_tile(0, R);
-  store_tile(0, R);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    const bool more = kt + 1 < nk;
-    if (more) load_tile(kt + 1, R);
-    mma_stage(cur);
-    if (more) store_tile(cur ^ 1, R);
+  if constexpr (sizeof(T) == 4 && !B3) {
+    // FP32: two k tiles in flight (the MFMA work of one tile is too short to
+    // cover a global load): the loads of tile kt + 2 are issued before the
+    // MFMAs of tile kt, while tile kt + 1, loaded one step earlier, is stored
+    // to the other LDS stage after them.  (Split-BF16 keeps one tile in
+    // flight: the second register set costs it a wave per SIMD, which loses
+    // more than the deeper prefetch gains.)
+    Regs R0, R1;
+    load_tile(0, R0);
+    store_tile(0, R0);
+    if (nk > 1) load_tile(1, R1);
     __syncthreads();
+    auto step = [&](int kt, Regs& Rfree, Regs& Rnext) {
+      const int cur = kt & 1;
+      if (kt + 2 < nk) load_tile(kt + 2, Rfree);
+      mma_stage(cur);
+      if (kt + 1 < nk) store_tile(cur ^ 1, Rnext);
+      __syncthreads();
+    };
+    int kt = 0;
+    for (; kt + 1 < nk; kt += 2) {
+      step(kt, R0, R1);
+      step(kt + 1, R1, R0);
+    }
+    if (kt < nk) step(kt, R0, R1);
+  } else {
+    // one k tile in flight: the loads of tile kt + 1 are issued before the
+    // MFMAs of tile kt and stored to the other LDS stage after them
+    Regs R;
+    load_tile(0, R);
+    store_tile(0, R);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      const bool more = kt + 1 < nk;
+      if (more) load_tile(kt + 1, R);
+      mma_stage(cur);
+      if (more) store_tile(cur ^ 1, R);
+      __syncthreads();
+    }
   }
 
   // C/D layout of the 16x16 block: lane l holds column l % 16; FP64 rows
