@@ -391,6 +391,9 @@ def main():
                     help="keep the default GEMM tiles instead of timing every tile on the first launch of a shape")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every kernel from the host instead of replaying hipGraphs (for tracers)")
+    ap.add_argument("--no-fused", action="store_true",
+                    help="contract the triples residual term by term (expansion, GEMM, fold) instead of the "
+                         "fused pass (for comparisons and for profiling the per-term GEMMs)")
     ap.add_argument("--profile-json", default=None, help="write the per-kernel event timings here")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 512 MiB five times (calibrates rocprofv3 byte counters)")
@@ -442,6 +445,7 @@ def main():
     # the state where the residual sweep can be recorded into hipGraphs
     warm = max(args.warmup, 1)
     ctx.set_graphs(False)
+    ctx.set_fused(not args.no_fused)
     ctx.set_autotune(not args.no_autotune)  # tiles are chosen in the first warm-up sweep
     ctx.profile(True)
     wres = ctx.ccsdt(max_iter=warm, prec=args.prec, allow_noconv=True)
