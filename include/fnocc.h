@@ -157,6 +157,23 @@ int fno_batch_eom(int n, fno_ctx *const *ctxs, fno_eom_kind kind, const fno_eom_
                   double *res_norm, int *iters);
 
 /*
+ * The same solve as fno_batch_eom for callers that batch many small
+ * instances, with one persistent grouped launch per contraction: each sigma
+ * round takes one block of pending vectors of every instance and, term by
+ * term, issues every instance's operand expansions, then the GEMMs of all
+ * instances as one persistent launch per kernel instantiation (workgroups
+ * take (instance, term, tile) items from a device work queue; the block's
+ * roots are inside each GEMM), then every instance's fold, on one batch
+ * stream.  Every GEMM runs with its default tile and without split-K, so
+ * each instance's roots are bit-identical to those of a grouped batch that
+ * holds that instance alone (they differ from fno_eom's in the last bits).
+ * All contexts must be on one device.  Arguments, results and errors as for
+ * fno_batch_eom.
+ */
+int fno_batch_eom_grouped(int n, fno_ctx *const *ctxs, fno_eom_kind kind, const fno_eom_opts *opts, double *omega,
+                          double *res_norm, int *iters);
+
+/*
  * MP2 correlation energies (eqs 8-9) of the full virtual space and of the
  * truncated space of the last fno_truncate (the kept semicanonical
  * natural orbitals).  Either output may be NULL.

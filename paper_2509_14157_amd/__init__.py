@@ -25,7 +25,7 @@ SYMBOLS = ["fno_create", "fno_destroy", "fno_last_error", "fno_set_stream", "fno
            "fno_eom_sigma", "fno_eom_sigma_left", "fno_eom_vectors", "fno_last_flops", "fno_last_trace", "fno_get_amplitudes_dev",
            "fno_set_amplitudes_dev", "fno_cc_residual_dev", "fno_eom_sigma_dev", "fno_triples_residual_dev", "fno_dev_last_error",
            "fno_triples_residual_dev_noalloc", "fno_profile", "fno_profile_report", "fno_profile_filter",
-           "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_mlp_num_params", "fno_mlp_create",
+           "fno_set_graphs", "fno_set_fused", "fno_set_autotune", "fno_batch_eom", "fno_batch_eom_grouped", "fno_mlp_num_params", "fno_mlp_create",
            "fno_mlp_destroy", "fno_mlp_last_error", "fno_mlp_collect", "fno_mlp_samples", "fno_mlp_train",
            "fno_mlp_save", "fno_mlp_load", "fno_mlp_params", "fno_mlp_loss_grad", "fno_mlp_predict", "fno_mlp_dataset",
            "fno_set_guess_model", "fno_last_guess_accepted", "fno_debug_tensor_size", "fno_debug_tensor", "fno_debug_gemm"]
@@ -124,6 +124,8 @@ def library() -> C.CDLL:
         lib.fno_set_guess_model.argtypes = [C.c_void_p, C.c_void_p]
         lib.fno_last_guess_accepted.argtypes = [C.c_void_p]
         lib.fno_batch_eom.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(EOMOpts), dp, dp,
+                                      C.POINTER(C.c_int)]
+        lib.fno_batch_eom_grouped.argtypes = [C.c_int, C.POINTER(C.c_void_p), C.c_int, C.POINTER(EOMOpts), dp, dp,
                                       C.POINTER(C.c_int)]
         lib.fno_debug_tensor_size.argtypes = [C.c_void_p, C.c_char_p]
         lib.fno_debug_tensor_size.restype = C.c_size_t
@@ -507,8 +509,9 @@ class Mlp:
 
 
 def batch_eom(contexts, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8, r_tol=1e-6, prec="fp64",
-              allow_noconv=False, block=0):
-    """EOM roots for several contexts at once (fno_batch_eom); returns a list of result dicts."""
+              allow_noconv=False, block=0, grouped=False):
+    """EOM roots for several contexts at once (fno_batch_eom, or fno_batch_eom_grouped with
+    grouped=True); returns a list of result dicts."""
     lib = library()
     n = len(contexts)
     o = EOMOpts()
@@ -519,7 +522,8 @@ def batch_eom(contexts, kind: str, nroots=4, max_iter=60, max_sub=0, e_tol=1e-8,
     handles = (C.c_void_p * n)(*[c._h.value if isinstance(c._h, C.c_void_p) else c._h for c in contexts])
     om, rn = np.zeros(n * nroots), np.zeros(n * nroots)
     its = (C.c_int * n)()
-    st = lib.fno_batch_eom(n, handles, KIND[kind], C.byref(o), _dp(om), _dp(rn), its)
+    fn = lib.fno_batch_eom_grouped if grouped else lib.fno_batch_eom
+    st = fn(n, handles, KIND[kind], C.byref(o), _dp(om), _dp(rn), its)
     if st != FNO_OK and not (allow_noconv and st == FNO_ENOCONV):
         raise FnoError(st, lib.fno_last_error(contexts[0]._h).decode())
     return [dict(omega=om[i * nroots:(i + 1) * nroots].copy(), res_norm=rn[i * nroots:(i + 1) * nroots].copy(),

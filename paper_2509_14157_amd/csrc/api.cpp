@@ -183,8 +183,9 @@ fno::EOMOptions eom_options(const fno_eom_opts* opts) {
 }
 }  // namespace
 
-int fno_batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts* opts, double* omega,
-                  double* res_norm, int* iters) {
+namespace {
+int batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts* opts, double* omega,
+              double* res_norm, int* iters, bool grouped) {
   if (n <= 0 || !ctxs || !omega) return FNO_EINVAL;
   for (int i = 0; i < n; ++i)
     if (!ctxs[i] || !ctxs[i]->c) return FNO_EINVAL;
@@ -207,11 +208,26 @@ int fno_batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_
       d[i] = ctxs[i]->c->dav_begin((int)kind, eo);
     }
     // lockstep: the sigma work of every instance is issued on its own stream
-    // before any host wait, then each instance does its subspace step
+    // before any host wait (or, grouped, as grouped rounds on one batch
+    // stream), then each instance does its subspace step
+    std::vector<fno::Context*> cs(n);
+    for (int i = 0; i < n; ++i) cs[i] = ctxs[i]->c;
+    fno::Context::GroupedBuffers gb;  // owns the batch stream
+    if (grouped) {
+      for (int i = 1; i < n; ++i)
+        FNO_REQUIRE(cs[i]->device == cs[0]->device, FNO_EINVAL, "a grouped batch runs on one device");
+      FNO_HIP(hipSetDevice(cs[0]->device));
+      FNO_HIP(hipStreamCreate(&gb.stream));
+    }
     for (bool all_done = false; !all_done;) {
-      for (int i = 0; i < n; ++i) {
-        failed = i;
-        if (!d[i]->done) ctxs[i]->c->dav_sigma(*d[i]);
+      if (grouped) {
+        failed = 0;
+        fno::Context::dav_sigma_grouped(cs, d, gb);
+      } else {
+        for (int i = 0; i < n; ++i) {
+          failed = i;
+          if (!d[i]->done) ctxs[i]->c->dav_sigma(*d[i]);
+        }
       }
       all_done = true;
       for (int i = 0; i < n; ++i) {
@@ -243,6 +259,18 @@ int fno_batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_
     ctxs[0]->err = e.what();
     return FNO_EDEVICE;
   }
+}
+
+}  // namespace
+
+int fno_batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts* opts, double* omega,
+                  double* res_norm, int* iters) {
+  return batch_eom(n, ctxs, kind, opts, omega, res_norm, iters, false);
+}
+
+int fno_batch_eom_grouped(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts* opts, double* omega,
+                          double* res_norm, int* iters) {
+  return batch_eom(n, ctxs, kind, opts, omega, res_norm, iters, true);
 }
 
 int fno_eom(fno_ctx* ctx, fno_eom_kind kind, const fno_eom_opts* opts, double* omega, double* e_tot,

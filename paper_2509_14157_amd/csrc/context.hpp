@@ -80,6 +80,21 @@ class Context {
   bool dav_update(Davidson& d);   // one iteration's host work; true when finished
   int dav_end(EOMResult& res);    // results, releases the solver; status kOK / kENOCONV
   void dav_release();
+  // Grouped sigma rounds over several contexts (fno_batch_eom_grouped): the
+  // pending Davidson vectors of every instance, one block per instance and
+  // round, term by term: every instance's expansions, then one grouped GEMM
+  // launch per kernel instantiation over all of them (a device work queue of
+  // (instance, term, tile) items, the roots of a block inside each GEMM), then
+  // every instance's fold; all on the batch's stream `gs`.
+  struct GroupedBuffers {
+    void *pin = nullptr, *dev = nullptr, *queue = nullptr;  // item tables (pinned host, device), queue counters
+    size_t items = 0;                                      // capacity of each table, in items
+    hipStream_t stream = nullptr;                          // the batch stream (destroyed with the buffers)
+    void reserve(size_t n);
+    ~GroupedBuffers();
+  };
+  static void dav_sigma_grouped(const std::vector<Context*>& cs, const std::vector<Davidson*>& ds,
+                                GroupedBuffers& gb);
 
   double last_triples_flops = 0, last_all_flops = 0;
   std::vector<double> trace_e, trace_r;  // per-iteration E_corr and |r| of the last fno_ccsdt

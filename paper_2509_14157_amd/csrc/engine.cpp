@@ -1310,6 +1310,7 @@ void Engine::execute(const Plan& p, double scale) {
   g.ldb = ldb;
   g.b_nfast = b_nfast;
   g.tile = -1;
+  bool deferred = false;  // the GEMM went to the sink (and so does the fold)
   auto timed_gemm = [&]() {
     // a full contraction to one number (energies): a deterministic dot
     // product, two small launches instead of a split-K GEMM and its reduction
@@ -1318,6 +1319,15 @@ void Engine::execute(const Plan& p, double scale) {
     if (g.M == 1 && g.N == 1 && prec == Prec::FP64 && a_contig && b_contig) {
       double* part = (double*)workspace(5, (size_t)dot_partial_blocks(g.K) * sizeof(double));
       launch_dot_acc((const double*)g.A, (const double*)g.B, g.K, part, (double*)g.C, g.alpha, g.beta, stream);
+      return;
+    }
+    if (sink) {
+      GemmArgs d = g;
+      d.tile = -1;
+      d.split = 1;
+      d.ws = nullptr;
+      sink->gemms.push_back(d);
+      deferred = true;
       return;
     }
     g.split = gemm_split_factor(g);
@@ -1375,21 +1385,26 @@ void Engine::execute(const Plan& p, double scale) {
     g.alpha = factor;
     g.beta = 0.0;
     timed_gemm();
-    const bool tm = timed(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel") && !rec_;
-    hipEvent_t e0 = tm ? event() : nullptr;
-    if (e0) FNO_HIP(hipEventRecord(e0, stream));
-    if (p.f_tab_ok)
-      launch_fold_tab(p.f_tab, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32, p.out->d, p.alpha * scale,
-                      p.odims.size, stream);
+    const Prec xp = prec == Prec::FP64 ? Prec::FP64 : Prec::FP32;
+    auto fold = [this, &p, X, xp, xsz, scale]() {
+      const bool tm = timed(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel") && !rec_;
+      hipEvent_t e0 = tm ? event() : nullptr;
+      if (e0) FNO_HIP(hipEventRecord(e0, stream));
+      if (p.f_tab_ok)
+        launch_fold_tab(p.f_tab, X, xp, p.out->d, p.alpha * scale, p.odims.size, stream);
+      else
+        launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, xp, p.out->d, p.alpha * scale, stream);
+      if (e0) {
+        hipEvent_t e1 = event();
+        FNO_HIP(hipEventRecord(e1, stream));
+        prof_mark(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel", p.spec, 0,
+                  (double)p.odims.size * (16.0 + (double)p.fc.ncombo * (double)xsz), e0, e1);
+      }
+    };
+    if (deferred)
+      sink->after.push_back(fold);
     else
-      launch_fold(tables, p.od, p.odims, p.M, p.N, p.fc, X, prec == Prec::FP64 ? Prec::FP64 : Prec::FP32,
-                  p.out->d, p.alpha * scale, stream);
-    if (e0) {
-      hipEvent_t e1 = event();
-      FNO_HIP(hipEventRecord(e1, stream));
-      prof_mark(p.f_tab_ok ? "fno::fold_tab" : "fno::fold_kernel", p.spec, 0,
-                (double)p.odims.size * (16.0 + (double)p.fc.ncombo * (double)xsz), e0, e1);
-    }
+      fold();
   }
   if (record) stats.push_back({p.spec, Msz, Nsz, Ksz, p.flops});
 }

@@ -177,6 +177,17 @@ class Engine {
   bool record = false;
   std::vector<GemmStats> stats;
 
+  // Deferred GEMMs: while `sink` is set, a term issues its expansions and
+  // hands its GEMM (default tile, no split-K) and the rest of the term (the
+  // fold) to the sink instead of running them.  The caller runs the GEMMs
+  // (for instance one grouped launch over several engines' terms) and then
+  // the deferred rests in order, before this engine issues its next term.
+  struct GemmSink {
+    std::vector<GemmArgs> gemms;
+    std::vector<std::function<void()>> after;
+  };
+  GemmSink* sink = nullptr;
+
   // --- a second lane.  fork_mark() notes the main stream's current point;
   // terms issued between begin_side() and end_side() run on a side stream
   // (with its own workspaces) that starts from that point, concurrently with

@@ -424,6 +424,156 @@ void Context::dav_sigma(Davidson& d) {
   }
 }
 
+void Context::GroupedBuffers::reserve(size_t n) {
+  if (n <= items) return;
+  if (stream) FNO_HIP(hipStreamSynchronize(stream));
+  if (pin) (void)hipHostFree(pin);
+  if (dev) (void)hipFree(dev);
+  pin = dev = nullptr;
+  items = 0;
+  FNO_HIP(hipHostMalloc(&pin, n * gemm_group_item_bytes(), hipHostMallocDefault));
+  FNO_HIP(hipMalloc(&dev, n * gemm_group_item_bytes()));
+  if (!queue) FNO_HIP(hipMalloc(&queue, 8 * (size_t)gemm_group_max_launches()));
+  items = n;
+}
+
+Context::GroupedBuffers::~GroupedBuffers() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  if (pin) (void)hipHostFree(pin);
+  if (dev) (void)hipFree(dev);
+  if (queue) (void)hipFree(queue);
+  if (stream) (void)hipStreamDestroy(stream);
+}
+
+void Context::dav_sigma_grouped(const std::vector<Context*>& cs, const std::vector<Davidson*>& ds,
+                                GroupedBuffers& gb) {
+  const hipStream_t S = gb.stream;
+  FNO_REQUIRE(S != nullptr, kEINVAL, "grouped sigma: no batch stream");
+  for (;;) {
+    std::vector<int> act;
+    for (size_t i = 0; i < cs.size(); ++i)
+      if (!ds[i]->done && ds[i]->ns < ds[i]->nv) act.push_back((int)i);
+    if (act.empty()) return;
+    // the round runs on S, after each instance's own work so far; every
+    // instance's engine issues to S until the round has been issued
+    std::vector<hipStream_t> own(act.size());
+    for (size_t j = 0; j < act.size(); ++j) {
+      Engine& e = *cs[act[j]]->eng;
+      FNO_HIP(hipStreamSynchronize(e.stream));
+      own[j] = e.stream;
+      e.stream = S;
+    }
+    struct Restore {
+      const std::vector<Context*>& cs;
+      const std::vector<int>& act;
+      const std::vector<hipStream_t>& own;
+      ~Restore() {
+        for (size_t j = 0; j < act.size(); ++j) {
+          Engine& e = *cs[act[j]]->eng;
+          e.stream = own[j];
+          e.sink = nullptr;
+          e.prec = Prec::FP64;
+          e.record = false;
+        }
+      }
+    } restore{cs, act, own};
+    std::vector<int> cnt(act.size());
+    std::vector<const EomTables*> tab(act.size());
+    std::vector<std::unique_ptr<CacheScope>> scope(act.size());
+    for (size_t j = 0; j < act.size(); ++j) {
+      Context& c = *cs[act[j]];
+      Davidson& d = *ds[act[j]];
+      Engine& e = *c.eng;
+      EomSpace& sp = *c.eom_;
+      const bool left = d.opt.left;
+      FNO_REQUIRE(!left || sp.left_made, kESTATE, "left-hand EOM tensors not set up");
+      const EomTables& t = left ? sp.ltab : sp.tab;
+      tab[j] = &t;
+      FNO_REQUIRE(t.nterms == tab[0]->nterms, kEINVAL, "grouped sigma: instances of different EOM kinds");
+      cnt[j] = std::min(sp.nb, d.nv - d.ns);
+      const double* r = d.V + (int64_t)d.ns * d.dim;
+      for (int b = 0; b < t.nblocks; ++b) {
+        const int64_t sz = sp.blocks[b].size;
+        launch_scale_rows(e.get(t.in[b])->d, sz, r + sp.blocks[b].offset, d.dim, (double)t.sign[b], sz, cnt[j],
+                          sp.nb, S);
+      }
+      std::vector<Tensor*> cleared;
+      for (int i = 0; i < t.nzero; ++i) cleared.push_back(e.get(t.zero[i]));
+      e.zero_many(cleared);
+      e.stats.clear();
+      e.record = true;
+      std::vector<std::string> inputs;
+      for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
+      scope[j].reset(new CacheScope(e, inputs));
+    }
+    const int nterms = tab[0]->nterms;
+    gb.reserve((size_t)nterms * act.size());
+    std::vector<Engine::GemmSink> sink(act.size());
+    const size_t isz = gemm_group_item_bytes();
+    for (int k = 0; k < nterms; ++k) {
+      std::vector<GemmArgs> all;
+      for (size_t j = 0; j < act.size(); ++j) {
+        Context& c = *cs[act[j]];
+        Engine& e = *c.eng;
+        EomSpace& sp = *c.eom_;
+        const EomTables& t = *tab[j];
+        const std::string s(t.terms[k]);
+        bool tri = false;  // contractions that read or write the R3 block run in the requested precision
+        for (int b = 0; b < t.nblocks; ++b)
+          if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
+            tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
+            tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
+          }
+        e.prec = tri ? ds[act[j]]->opt.prec : Prec::FP64;
+        e.sink = &sink[j];
+        e.term(s);
+        e.sink = nullptr;
+        all.insert(all.end(), sink[j].gemms.begin(), sink[j].gemms.end());
+      }
+      // each term has its own region of the pinned table: the copies of
+      // earlier terms may still be pending when this one is written
+      launch_gemm_grouped(all, (char*)gb.pin + (size_t)k * act.size() * isz, gb.dev, gb.queue, S);
+      for (size_t j = 0; j < act.size(); ++j) {
+        for (auto& f : sink[j].after) f();
+        sink[j].gemms.clear();
+        sink[j].after.clear();
+      }
+    }
+    for (size_t j = 0; j < act.size(); ++j) {
+      Context& c = *cs[act[j]];
+      Davidson& d = *ds[act[j]];
+      Engine& e = *c.eng;
+      EomSpace& sp = *c.eom_;
+      const EomTables& t = *tab[j];
+      scope[j].reset();
+      e.prec = Prec::FP64;
+      e.record = false;
+      double tf = 0, af = 0;
+      for (auto& st : e.stats) {
+        af += st.flops;
+        for (int b = 0; b < t.nblocks; ++b)
+          if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
+              (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
+               st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
+            tf += st.flops;
+            break;
+          }
+      }
+      c.last_triples_flops += tf;
+      c.last_all_flops += af;
+      double* sigma = d.S + (int64_t)d.ns * d.dim;
+      for (int b = 0; b < t.nblocks; ++b) {
+        const int64_t sz = sp.blocks[b].size;
+        launch_scale_rows(sigma + sp.blocks[b].offset, d.dim, e.get(t.out[b])->d, sz, (double)t.sign[b], sz,
+                          cnt[j], cnt[j], S);
+      }
+      d.ns += cnt[j];
+    }
+    // the instances' own streams continue after the round
+    FNO_HIP(hipStreamSynchronize(S));
+  }
+}
+
 namespace {
 // Block operations of the Davidson solver as FP64 MFMA GEMMs over vectors
 // stored one after another (stride dim): each pass streams a block of

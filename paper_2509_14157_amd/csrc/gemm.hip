@@ -50,9 +50,9 @@ __device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
 // with M fastest (m_fast: consecutive tiles share a B column strip) or N
 // fastest (consecutive tiles share an A row strip).  The operand whose strips
 // are shared is then read from HBM about once instead of once per tile row.
-__device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, int m_fast, int64_t& m0, int64_t& n0) {
+__device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, int m_fast, int64_t& m0, int64_t& n0,
+                                        int64_t L) {
   const int64_t MT = (M + BM - 1) / BM, NT = (N + BN - 1) / BN, T = MT * NT;
-  const int64_t L = blockIdx.x;
   const int64_t q = T / 8, r = T % 8, x = L % 8, k = L / 8;
   const int64_t t = x * q + (x < r ? x : r) + k;
   const int64_t mt = m_fast ? t % MT : t / NT;
@@ -65,15 +65,17 @@ __device__ __forceinline__ void tile_of(int64_t M, int64_t N, int BM, int BN, in
 // 16x16x4 path (FP64 / FP32).  BK k values staged per tile (BK / 4 MFMA k-steps
 // per pair of barriers): 16, or 32 for the FP32 tiles, whose MFMA steps take
 // half as long, so the barriers and loads weigh twice as much per flop.
+// (bx: the workgroup's linear tile index, bz: its split-K slice)
 template <typename T, int BM, int BN, bool AK, bool BN_FAST, int BK, int VW>
 __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, const T* __restrict__ A, int64_t lda,
                                              const T* __restrict__ B, int64_t ldb, T* __restrict__ C, int64_t ldc,
-                                             T alpha, T beta, int64_t kchunk, int64_t cz, int m_fast) {
+                                             T alpha, T beta, int64_t kchunk, int64_t cz, int m_fast, int64_t bx,
+                                             int64_t bz) {
   {  // split-K: this z-slice owns K range [z*kchunk, z*kchunk + kchunk)
-    const int64_t k0 = (int64_t)blockIdx.z * kchunk;
+    const int64_t k0 = bz * kchunk;
     A += AK ? k0 : k0 * lda;
     B += BN_FAST ? k0 * ldb : k0;
-    C += (int64_t)blockIdx.z * cz;
+    C += bz * cz;
     K = (K - k0 < kchunk) ? K - k0 : kchunk;
   }
   constexpr int WM = BM / 2, WN = BN / 2;
@@ -94,7 +96,7 @@ __device__ __forceinline__ void gemm_k4_body(int64_t M, int64_t N, int64_t K, co
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t m0, n0;
-  tile_of(M, N, BM, BN, m_fast, m0, n0);
+  tile_of(M, N, BM, BN, m_fast, m0, n0, bx);
 
   typename Acc<T>::type acc[TM][TN];
 #pragma unroll
@@ -305,7 +307,8 @@ __global__ void __launch_bounds__(256, 2) gemm_k4_kernel(int64_t M, int64_t N, i
                                                       int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                       T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                       int64_t kchunk, int64_t cz, int m_fast) {
-  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast, blockIdx.x,
+                                                   blockIdx.z);
 }
 
 // Same tile with 16-byte global loads (4 floats or 2 doubles per load); the
@@ -316,7 +319,7 @@ __global__ void __launch_bounds__(256, 2) gemm_k4v_kernel(int64_t M, int64_t N, 
                                                        T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                        int64_t kchunk, int64_t cz, int m_fast) {
   gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, 16 / sizeof(T)>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz,
-                                                           m_fast);
+                                                           m_fast, blockIdx.x, blockIdx.z);
 }
 
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
@@ -324,7 +327,8 @@ __global__ void __launch_bounds__(256, 2) gemm_k32_kernel(int64_t M, int64_t N, 
                                                        int64_t lda, const T* __restrict__ B, int64_t ldb,
                                                        T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                        int64_t kchunk, int64_t cz, int m_fast) {
-  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast);
+  gemm_k4_body<T, BM, BN, AK, BN_FAST, 32, 1>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz, m_fast, blockIdx.x,
+                                                   blockIdx.z);
 }
 
 template <typename T, int BM, int BN, bool AK, bool BN_FAST>
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(256, 2) gemm_k32v_kernel(int64_t M, int64_t N,
                                                         T* __restrict__ C, int64_t ldc, T alpha, T beta,
                                                         int64_t kchunk, int64_t cz, int m_fast) {
   gemm_k4_body<T, BM, BN, AK, BN_FAST, 32, 16 / sizeof(T)>(M, N, K, A, lda, B, ldb, C, ldc, alpha, beta, kchunk, cz,
-                                                           m_fast);
+                                                           m_fast, blockIdx.x, blockIdx.z);
 }
 
 // Double-buffered 16x16x4 path (FP64 / FP32): two LDS stages, one barrier per
@@ -366,7 +370,7 @@ __global__ void __launch_bounds__(256, 2) gemm_db_kernel(int64_t M, int64_t N, i
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t m0, n0;
-  tile_of(M, N, BM, BN, m_fast, m0, n0);
+  tile_of(M, N, BM, BN, m_fast, m0, n0, blockIdx.x);
 
   typename Acc<T>::type acc[TM][TN];
 #pragma unroll
@@ -576,7 +580,7 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16x3_kernel(int64_t M, int64_t 
   const int wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t m0, n0;
-  tile_of(M, N, BM, BN, m_fast, m0, n0);
+  tile_of(M, N, BM, BN, m_fast, m0, n0, blockIdx.x);
 
   f4_t acc[TM][TN];
 #pragma unroll
@@ -651,6 +655,53 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16x3_kernel(int64_t M, int64_t 
       }
     }
 }
+// ---------------------------------------------------------------------------
+// Grouped GEMMs: one persistent launch computes the tiles of many GEMMs that
+// share a kernel instantiation.  Each workgroup takes the next index of a
+// device work queue (one counter per launch), finds the GEMM the index
+// belongs to (each item holds its first index; its tiles follow), and runs
+// that tile through the body of the single-GEMM kernel, so every tile gives
+// the bits the single launch gives; workgroups leave when the queue is
+// exhausted.
+struct GroupItem {
+  int64_t M, N, K, lda, ldb, ldc;
+  const void* A;
+  const void* B;
+  void* C;
+  double alpha, beta;
+  int64_t first;
+  int m_fast;
+};
+
+__global__ void grouped_reset_kernel(unsigned long long* __restrict__ q, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) q[i] = 0;
+}
+
+template <typename T, int BM, int BN, bool AK, bool BN_FAST, int VW>
+__global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupItem* __restrict__ items, int nitems,
+                                                              int64_t total, unsigned long long* __restrict__ queue) {
+  __shared__ int64_t w_s;
+  for (;;) {
+    if (threadIdx.x == 0) w_s = (int64_t)atomicAdd(queue, 1ull);
+    __syncthreads();
+    const int64_t w = w_s;
+    if (w >= total) return;  // uniform over the workgroup
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (items[mid].first <= w)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const GroupItem& it = items[lo];
+    gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, VW>(it.M, it.N, it.K, (const T*)it.A, it.lda, (const T*)it.B, it.ldb,
+                                                 (T*)it.C, it.ldc, (T)it.alpha, (T)it.beta, it.K > 0 ? it.K : 1, 0,
+                                                 it.m_fast, w - it.first, 0);
+    __syncthreads();  // the tile's LDS and w_s are reused by the next index
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Tile table used by the planner and the autotuner.
 struct TileCfg {
@@ -991,6 +1042,126 @@ void launch_gemm(const GemmArgs& g, hipStream_t s) {
     case 14: dispatch_k32<128, 64>(g, s); break;
     case 15: dispatch_f32<256, 128>(g, s); break;
     default: dispatch_f32<128, 256>(g, s); break;
+  }
+  FNO_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------------------------------------
+// Grouped launches (host side)
+size_t gemm_group_item_bytes() { return sizeof(GroupItem); }
+
+namespace {
+constexpr int kGroupTiles = 6;  // the single-buffered 16-deep tiles (the defaults)
+constexpr int kGroupKeys = 2 * kGroupTiles * 8;  // precision x tile x (A layout, B layout, vector loads)
+
+template <typename T, int BM, int BN>
+void grouped_launch_tile(int key_lay, const GroupItem* dev, int n, int64_t total, unsigned long long* q,
+                         hipStream_t s) {
+  const unsigned grid = (unsigned)std::min<int64_t>(total, 1024);
+  const bool ak = key_lay & 1, bf = key_lay & 2, vec = key_lay & 4;
+  constexpr int V = 16 / sizeof(T);
+  if constexpr (k4_vectorizable<T, BM, BN, 16>()) {
+    if (vec) {
+      if (ak && bf)
+        gemm_grouped_kernel<T, BM, BN, true, true, V><<<grid, 256, 0, s>>>(dev, n, total, q);
+      else if (ak)
+        gemm_grouped_kernel<T, BM, BN, true, false, V><<<grid, 256, 0, s>>>(dev, n, total, q);
+      else if (bf)
+        gemm_grouped_kernel<T, BM, BN, false, true, V><<<grid, 256, 0, s>>>(dev, n, total, q);
+      else
+        gemm_grouped_kernel<T, BM, BN, false, false, V><<<grid, 256, 0, s>>>(dev, n, total, q);
+      return;
+    }
+  }
+  if (ak && bf)
+    gemm_grouped_kernel<T, BM, BN, true, true, 1><<<grid, 256, 0, s>>>(dev, n, total, q);
+  else if (ak)
+    gemm_grouped_kernel<T, BM, BN, true, false, 1><<<grid, 256, 0, s>>>(dev, n, total, q);
+  else if (bf)
+    gemm_grouped_kernel<T, BM, BN, false, true, 1><<<grid, 256, 0, s>>>(dev, n, total, q);
+  else
+    gemm_grouped_kernel<T, BM, BN, false, false, 1><<<grid, 256, 0, s>>>(dev, n, total, q);
+}
+
+template <typename T>
+void grouped_launch(int tile, int key_lay, const GroupItem* dev, int n, int64_t total, unsigned long long* q,
+                    hipStream_t s) {
+  switch (tile) {
+    case 0: grouped_launch_tile<T, 64, 64>(key_lay, dev, n, total, q, s); break;
+    case 1: grouped_launch_tile<T, 128, 64>(key_lay, dev, n, total, q, s); break;
+    case 2: grouped_launch_tile<T, 64, 128>(key_lay, dev, n, total, q, s); break;
+    case 3: grouped_launch_tile<T, 128, 128>(key_lay, dev, n, total, q, s); break;
+    case 4: grouped_launch_tile<T, 32, 64>(key_lay, dev, n, total, q, s); break;
+    default: grouped_launch_tile<T, 64, 32>(key_lay, dev, n, total, q, s); break;
+  }
+}
+}  // namespace
+
+int gemm_group_max_launches() { return kGroupKeys; }
+
+void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, void* queue, hipStream_t s) {
+  // bucket the GEMMs by kernel instantiation; the others run one by one
+  std::vector<std::vector<int>> bucket(kGroupKeys);
+  for (int i = 0; i < (int)gs.size(); ++i) {
+    GemmArgs g = gs[i];
+    g.tile = -1;
+    g.split = 1;
+    if (g.M == 0 || g.N == 0) continue;
+    const int t = default_tile(g);
+    if (g.prec == Prec::BF16X3 || t >= kGroupTiles) {
+      g.tile = t;
+      launch_gemm(g, s);
+      continue;
+    }
+    const bool vec = gemm_rows_aligned(g);
+    const int lay = (g.a_kfast ? 1 : 0) | (g.b_nfast ? 2 : 0) | (vec ? 4 : 0);
+    bucket[((g.prec == Prec::FP64 ? 0 : 1) * kGroupTiles + t) * 8 + lay].push_back(i);
+  }
+  GroupItem* hp = (GroupItem*)pin;
+  int used = 0;
+  struct Launch {
+    int key, off, n;
+    int64_t total;
+  };
+  std::vector<Launch> launches;
+  for (int key = 0; key < kGroupKeys; ++key) {
+    if (bucket[key].empty()) continue;
+    const int tile = (key / 8) % kGroupTiles;
+    Launch L{key, used, 0, 0};
+    for (int i : bucket[key]) {
+      const GemmArgs& g = gs[i];
+      GroupItem it{};
+      it.M = g.M;
+      it.N = g.N;
+      it.K = g.K;
+      it.lda = g.lda;
+      it.ldb = g.ldb;
+      it.ldc = g.ldc;
+      it.A = g.A;
+      it.B = g.B;
+      it.C = g.C;
+      it.alpha = g.alpha;
+      it.beta = g.beta;
+      it.first = L.total;
+      it.m_fast = m_fast_order(g);
+      L.total += ((g.M + kTiles[tile].bm - 1) / kTiles[tile].bm) * ((g.N + kTiles[tile].bn - 1) / kTiles[tile].bn);
+      hp[used++] = it;
+      ++L.n;
+    }
+    launches.push_back(L);
+  }
+  if (launches.empty()) return;
+  FNO_HIP(hipMemcpyAsync(dev, hp, sizeof(GroupItem) * (size_t)used, hipMemcpyHostToDevice, s));
+  unsigned long long* q = (unsigned long long*)queue;
+  grouped_reset_kernel<<<1, 128, 0, s>>>(q, (int)launches.size());
+  for (size_t j = 0; j < launches.size(); ++j) {
+    const Launch& L = launches[j];
+    const int tile = (L.key / 8) % kGroupTiles, lay = L.key % 8;
+    const GroupItem* d = (const GroupItem*)dev + L.off;
+    if (L.key / (8 * kGroupTiles) == 0)
+      grouped_launch<double>(tile, lay, d, L.n, L.total, q + j, s);
+    else
+      grouped_launch<float>(tile, lay, d, L.n, L.total, q + j, s);
   }
   FNO_HIP(hipGetLastError());
 }

@@ -104,6 +104,18 @@ void launch_gemm(const GemmArgs& g, hipStream_t s);
 std::string gemm_label(const GemmArgs& g);
 int gemm_num_tiles(Prec p);
 int gemm_default_tile(const GemmArgs& g);  // the tile launch_gemm uses for tile = -1
+// Grouped GEMMs: the GEMMs of `gs` (independent: no output read by another)
+// in one persistent launch per kernel instantiation, each workgroup taking
+// tiles of any of them from a device work queue.  Every GEMM runs with its
+// default tile and without split-K and gives the bits launch_gemm gives with
+// those settings (split-BF16 and the non-default tiles run one by one).
+// pin: pinned host table and dev: device table of gs.size() items of
+// gemm_group_item_bytes() each (the host table must stay unchanged until the
+// stream has passed the launch); queue: gemm_group_max_launches() 8-byte
+// counters.
+size_t gemm_group_item_bytes();
+int gemm_group_max_launches();
+void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, void* queue, hipStream_t s);
 
 
 // ---- learned guess: MLP building blocks (FP32) and T3 feature / guess kernels

@@ -95,3 +95,29 @@ def test_autotune_setting_survives_truncation(P):
         rep = c.profile_report()
         c.profile(False)
     assert len(rep["tuned"]) > 0
+
+
+@pytest.mark.parametrize("kind,prec", [("IP", "fp64"), ("EA", "fp64"), ("DIP", "fp64"), ("DEA", "fp32")])
+def test_grouped_batch_matches_grouped_single(P, kind, prec):
+    """fno_batch_eom_grouped: per sigma round and term, the GEMMs of every instance in
+    one persistent launch per kernel instantiation, tiles taken from a device work
+    queue.  Each instance's roots and iteration count are bitwise those of a grouped
+    batch that holds that instance alone (the grouping changes nothing), and agree
+    with fno_eom's (which may split K and so rounds differently): 1e-9 Eh in FP64,
+    1e-6 Eh with FP32 triples products."""
+    print(f"grouped batch {kind} {prec}", flush=True)
+    ctxs = [_solved(P, o, v, s) for o, v, s in [(4, 8, 41), (5, 6, 42), (4, 9, 43), (6, 10, 46)]]
+    try:
+        kw = dict(nroots=3, r_tol=1e-7, e_tol=1e-10, prec=prec)
+        alone = [P.batch_eom([c], kind, grouped=True, **kw)[0] for c in ctxs]
+        group = P.batch_eom(ctxs, kind, grouped=True, **kw)
+        single = [c.eom(kind, **kw) for c in ctxs]
+        tol = 1e-9 if prec == "fp64" else 1e-6
+        for a, g, s in zip(alone, group, single):
+            assert a["converged"] and g["converged"] and s["converged"]
+            assert g["iters"] == a["iters"]
+            assert np.array_equal(g["omega"], a["omega"])
+            assert np.abs(g["omega"] - s["omega"]).max() < tol, (g["omega"], s["omega"])
+    finally:
+        for c in ctxs:
+            c.close()
