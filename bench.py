@@ -160,7 +160,8 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
     """16 uneven-size FNO instances (o ~ U{6..12}, v ~ U{24..48} kept of ceil(5v/3)), ground state in
     FP64 (at most 30 iterations: the sigma cost does not depend on how far they converged), then
     DIP (4h2p) and DEA (4p2h) roots with FP32 triples contractions and FP64 Davidson:
-    once through fno_batch_eom, once one instance after another.  value = algorithmic R3-sigma
+    once through fno_batch_eom, once one instance after another, once through
+    fno_batch_eom_grouped.  value = algorithmic R3-sigma
     flops of the batched solve / its wall time."""
     import paper_2509_14157_amd as P
     from synthetic import batch_instance_shapes, full_virtuals_for, make_hamiltonian
@@ -196,13 +197,21 @@ def bench_batched(args, nroots=4, eom_prec="fp32"):
         t_seq = time.perf_counter() - t0
         same = all(np.array_equal(b["omega"], s_["omega"]) and b["iters"] == s_["iters"]
                    for b, s_ in zip(bres, sres))
+        # grouped: one persistent GEMM launch per kernel instantiation and term over all instances
+        P.batch_eom(ctxs, kind, grouped=True, **dict(opts, max_iter=2))
+        t0 = time.perf_counter()
+        gres = P.batch_eom(ctxs, kind, grouped=True, **opts)
+        t_grp = time.perf_counter() - t0
+        dw = max(float(np.abs(g["omega"] - b["omega"]).max()) for g, b in zip(gres, bres))
         kinds[kind] = {"batched_s": round(t_batch, 4), "sequential_s": round(t_seq, 4),
                        "speedup": round(t_seq / t_batch, 3), "triples_gflop": round(flops / 1e9, 2),
                        "tflops_batched": round(flops / t_batch / 1e12, 3),
                        "iters": [b["iters"] for b in bres], "converged": all(b["converged"] for b in bres),
-                       "identical_to_sequential": bool(same)}
-        _log(f"[bench] {kind}: batched {t_batch:.3f} s, sequential {t_seq:.3f} s, "
-             f"{flops / 1e9:.1f} GF -> {flops / t_batch / 1e12:.2f} TFLOP/s")
+                       "identical_to_sequential": bool(same),
+                       "grouped_s": round(t_grp, 4), "grouped_speedup_vs_sequential": round(t_seq / t_grp, 3),
+                       "grouped_iters": [g["iters"] for g in gres], "grouped_max_domega_vs_batched": dw}
+        _log(f"[bench] {kind}: batched {t_batch:.3f} s, grouped {t_grp:.3f} s, sequential {t_seq:.3f} s, "
+             f"{flops / 1e9:.1f} GF -> {flops / t_batch / 1e12:.2f} TFLOP/s; grouped roots within {dw:.1e} Eh")
     for c in ctxs:
         c.close()
     tot_f = sum(k["triples_gflop"] for k in kinds.values()) * 1e9

@@ -1,5 +1,7 @@
 // extern "C" boundary: argument checks, error capture, status codes.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <exception>
 
@@ -236,6 +238,8 @@ int batch_eom(int n, fno_ctx* const* ctxs, fno_eom_kind kind, const fno_eom_opts
         all_done = all_done && d[i]->done;
       }
     }
+    if (grouped && std::getenv("FNO_TRACE"))
+      std::fprintf(stderr, "[fno] grouped sigma rounds: %d recordings, %d replays\n", gb.recordings, gb.replays);
     int status = FNO_OK;
     for (int i = 0; i < n; ++i) {
       failed = i;

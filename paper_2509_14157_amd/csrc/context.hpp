@@ -90,7 +90,18 @@ class Context {
     void *pin = nullptr, *dev = nullptr, *queue = nullptr;  // item tables (pinned host, device), queue counters
     size_t items = 0;                                      // capacity of each table, in items
     hipStream_t stream = nullptr;                          // the batch stream (destroyed with the buffers)
+    // fork/join events (batch stream, one per instance)
+    hipEvent_t ev_s = nullptr;
+    std::vector<hipEvent_t> ev;
+    // the recorded sigma sweep of a round (one hipGraph over every active
+    // instance) and the round structure it is valid for: active instances,
+    // their engines' epochs and precisions; `seen` holds the structure of the
+    // last round run from the host
+    hipGraphExec_t exec = nullptr;
+    std::vector<int64_t> key, seen;
+    int replays = 0, recordings = 0;
     void reserve(size_t n);
+    void drop_graph();
     ~GroupedBuffers();
   };
   static void dav_sigma_grouped(const std::vector<Context*>& cs, const std::vector<Davidson*>& ds,

@@ -1321,11 +1321,11 @@ void Engine::execute(const Plan& p, double scale) {
       launch_dot_acc((const double*)g.A, (const double*)g.B, g.K, part, (double*)g.C, g.alpha, g.beta, stream);
       return;
     }
-    if (sink) {
+    if (sink) {  // default tile and its split-K factor (the slices' partials in workspace 5)
       GemmArgs d = g;
       d.tile = -1;
-      d.split = 1;
-      d.ws = nullptr;
+      d.split = gemm_split_factor(d);
+      d.ws = d.split > 1 ? workspace(5, gemm_split_bytes(d, d.split)) : nullptr;
       sink->gemms.push_back(d);
       deferred = true;
       return;

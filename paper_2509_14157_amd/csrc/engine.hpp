@@ -210,6 +210,10 @@ class Engine {
   void replay(const Program& prog, bool defer = false);
   void flush_timers(const Program& prog);
   bool recording() const { return rec_ != nullptr; }
+  // Capture by another owner: the caller captures this engine's stream into
+  // a graph of its own; while set, the engine refuses the work that cannot be
+  // captured (allocations, new plans), as during its own recordings.
+  void set_external_record(Program* p) { rec_ = p; }
   hipStream_t own_stream() const { return own_stream_; }
 
   // --- GEMM tile autotuner: with autotune on, the first host-launched GEMM of

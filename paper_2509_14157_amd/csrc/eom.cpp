@@ -424,8 +424,12 @@ void Context::dav_sigma(Davidson& d) {
   }
 }
 
+// a term's GEMMs go into one grouped launch when none has this many tiles
+constexpr int64_t kGroupBelowTiles = 512;
+
 void Context::GroupedBuffers::reserve(size_t n) {
   if (n <= items) return;
+  drop_graph();
   if (stream) FNO_HIP(hipStreamSynchronize(stream));
   if (pin) (void)hipHostFree(pin);
   if (dev) (void)hipFree(dev);
@@ -437,57 +441,61 @@ void Context::GroupedBuffers::reserve(size_t n) {
   items = n;
 }
 
+void Context::GroupedBuffers::drop_graph() {
+  if (exec) {
+    if (stream) (void)hipStreamSynchronize(stream);
+    (void)hipGraphExecDestroy(exec);
+  }
+  exec = nullptr;
+  key.clear();
+}
+
 Context::GroupedBuffers::~GroupedBuffers() {
   if (stream) (void)hipStreamSynchronize(stream);
+  drop_graph();
   if (pin) (void)hipHostFree(pin);
   if (dev) (void)hipFree(dev);
   if (queue) (void)hipFree(queue);
+  if (ev_s) (void)hipEventDestroy(ev_s);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
   if (stream) (void)hipStreamDestroy(stream);
 }
 
+// A round: every active instance applies one block of its pending vectors.
+// The R blocks go into (and the sigma blocks out of) each instance's tensors
+// on its own stream, outside any graph (their addresses change every round);
+// the sweep between them (accumulators cleared, then term by term: every
+// instance's expansions on its own stream, the grouped GEMMs on the batch
+// stream after all of them, every instance's fold on its stream after those)
+// is run from the host the first time a round structure is seen, recorded
+// into one hipGraph the second time (when no engine allocated anything in
+// between) and replayed while the structure stays the same.
 void Context::dav_sigma_grouped(const std::vector<Context*>& cs, const std::vector<Davidson*>& ds,
                                 GroupedBuffers& gb) {
   const hipStream_t S = gb.stream;
   FNO_REQUIRE(S != nullptr, kEINVAL, "grouped sigma: no batch stream");
+  if (!gb.ev_s) FNO_HIP(hipEventCreateWithFlags(&gb.ev_s, hipEventDisableTiming));
+  while (gb.ev.size() < cs.size()) {
+    hipEvent_t e = nullptr;
+    FNO_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    gb.ev.push_back(e);
+  }
   for (;;) {
     std::vector<int> act;
     for (size_t i = 0; i < cs.size(); ++i)
       if (!ds[i]->done && ds[i]->ns < ds[i]->nv) act.push_back((int)i);
     if (act.empty()) return;
-    // the round runs on S, after each instance's own work so far; every
-    // instance's engine issues to S until the round has been issued
-    std::vector<hipStream_t> own(act.size());
-    for (size_t j = 0; j < act.size(); ++j) {
-      Engine& e = *cs[act[j]]->eng;
-      FNO_HIP(hipStreamSynchronize(e.stream));
-      own[j] = e.stream;
-      e.stream = S;
-    }
-    struct Restore {
-      const std::vector<Context*>& cs;
-      const std::vector<int>& act;
-      const std::vector<hipStream_t>& own;
-      ~Restore() {
-        for (size_t j = 0; j < act.size(); ++j) {
-          Engine& e = *cs[act[j]]->eng;
-          e.stream = own[j];
-          e.sink = nullptr;
-          e.prec = Prec::FP64;
-          e.record = false;
-        }
-      }
-    } restore{cs, act, own};
-    std::vector<int> cnt(act.size());
-    std::vector<const EomTables*> tab(act.size());
-    std::vector<std::unique_ptr<CacheScope>> scope(act.size());
-    for (size_t j = 0; j < act.size(); ++j) {
+    const size_t na = act.size();
+    std::vector<int> cnt(na);
+    std::vector<const EomTables*> tab(na);
+    for (size_t j = 0; j < na; ++j) {
       Context& c = *cs[act[j]];
       Davidson& d = *ds[act[j]];
       Engine& e = *c.eng;
       EomSpace& sp = *c.eom_;
-      const bool left = d.opt.left;
-      FNO_REQUIRE(!left || sp.left_made, kESTATE, "left-hand EOM tensors not set up");
-      const EomTables& t = left ? sp.ltab : sp.tab;
+      FNO_REQUIRE(!d.opt.left || sp.left_made, kESTATE, "left-hand EOM tensors not set up");
+      const EomTables& t = d.opt.left ? sp.ltab : sp.tab;
       tab[j] = &t;
       FNO_REQUIRE(t.nterms == tab[0]->nterms, kEINVAL, "grouped sigma: instances of different EOM kinds");
       cnt[j] = std::min(sp.nb, d.nv - d.ns);
@@ -495,82 +503,200 @@ void Context::dav_sigma_grouped(const std::vector<Context*>& cs, const std::vect
       for (int b = 0; b < t.nblocks; ++b) {
         const int64_t sz = sp.blocks[b].size;
         launch_scale_rows(e.get(t.in[b])->d, sz, r + sp.blocks[b].offset, d.dim, (double)t.sign[b], sz, cnt[j],
-                          sp.nb, S);
+                          sp.nb, e.stream);
       }
-      std::vector<Tensor*> cleared;
-      for (int i = 0; i < t.nzero; ++i) cleared.push_back(e.get(t.zero[i]));
-      e.zero_many(cleared);
-      e.stats.clear();
-      e.record = true;
-      std::vector<std::string> inputs;
-      for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
-      scope[j].reset(new CacheScope(e, inputs));
     }
     const int nterms = tab[0]->nterms;
-    gb.reserve((size_t)nterms * act.size());
-    std::vector<Engine::GemmSink> sink(act.size());
-    const size_t isz = gemm_group_item_bytes();
-    for (int k = 0; k < nterms; ++k) {
-      std::vector<GemmArgs> all;
-      for (size_t j = 0; j < act.size(); ++j) {
-        Context& c = *cs[act[j]];
-        Engine& e = *c.eng;
-        EomSpace& sp = *c.eom_;
-        const EomTables& t = *tab[j];
-        const std::string s(t.terms[k]);
-        bool tri = false;  // contractions that read or write the R3 block run in the requested precision
-        for (int b = 0; b < t.nblocks; ++b)
-          if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
-            tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
-            tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
-          }
-        e.prec = tri ? ds[act[j]]->opt.prec : Prec::FP64;
-        e.sink = &sink[j];
-        e.term(s);
-        e.sink = nullptr;
-        all.insert(all.end(), sink[j].gemms.begin(), sink[j].gemms.end());
-      }
-      // each term has its own region of the pinned table: the copies of
-      // earlier terms may still be pending when this one is written
-      launch_gemm_grouped(all, (char*)gb.pin + (size_t)k * act.size() * isz, gb.dev, gb.queue, S);
-      for (size_t j = 0; j < act.size(); ++j) {
-        for (auto& f : sink[j].after) f();
-        sink[j].gemms.clear();
-        sink[j].after.clear();
-      }
+    gb.reserve((size_t)nterms * na);
+    // the structure a recording is valid for
+    std::vector<int64_t> key;
+    bool profiled = false;  // or graphs off on some context: run from the host
+    for (size_t j = 0; j < na; ++j) {
+      const Engine& e = *cs[act[j]]->eng;
+      profiled = profiled || !cs[act[j]]->use_graphs;
+      key.push_back(act[j]);
+      key.push_back((int64_t)e.epoch);
+      key.push_back((int64_t)ds[act[j]]->opt.prec);
+      key.push_back(ds[act[j]]->opt.left ? 1 : 0);
+      profiled = profiled || e.profile;
     }
-    for (size_t j = 0; j < act.size(); ++j) {
+    auto join_to_batch = [&]() {  // S after every instance stream
+      for (size_t j = 0; j < na; ++j) {
+        FNO_HIP(hipEventRecord(gb.ev[j], cs[act[j]]->eng->stream));
+        FNO_HIP(hipStreamWaitEvent(S, gb.ev[j], 0));
+      }
+    };
+    auto fork_from_batch = [&]() {  // every instance stream after S
+      FNO_HIP(hipEventRecord(gb.ev_s, S));
+      for (size_t j = 0; j < na; ++j) FNO_HIP(hipStreamWaitEvent(cs[act[j]]->eng->stream, gb.ev_s, 0));
+    };
+    auto sweep = [&]() {
+      std::vector<std::unique_ptr<CacheScope>> scope(na);
+      struct Reset {
+        const std::vector<Context*>& cs;
+        const std::vector<int>& act;
+        ~Reset() {
+          for (int i : act) {
+            Engine& e = *cs[i]->eng;
+            e.sink = nullptr;
+            e.prec = Prec::FP64;
+            e.record = false;
+          }
+        }
+      } reset{cs, act};
+      for (size_t j = 0; j < na; ++j) {
+        Engine& e = *cs[act[j]]->eng;
+        const EomTables& t = *tab[j];
+        std::vector<Tensor*> cleared;
+        for (int i = 0; i < t.nzero; ++i) cleared.push_back(e.get(t.zero[i]));
+        e.zero_many(cleared);
+        e.stats.clear();
+        e.record = true;
+        std::vector<std::string> inputs;
+        for (int b = 0; b < t.nblocks; ++b) inputs.push_back(t.in[b]);
+        scope[j].reset(new CacheScope(e, inputs));
+      }
+      std::vector<Engine::GemmSink> sink(na);
+      const size_t isz = gemm_group_item_bytes();
+      for (int k = 0; k < nterms; ++k) {
+        std::vector<GemmArgs> all;
+        for (size_t j = 0; j < na; ++j) {
+          Context& c = *cs[act[j]];
+          Engine& e = *c.eng;
+          EomSpace& sp = *c.eom_;
+          const EomTables& t = *tab[j];
+          const std::string s(t.terms[k]);
+          bool tri = false;  // contractions that read or write the R3 block run in the requested precision
+          for (int b = 0; b < t.nblocks; ++b)
+            if (sp.blocks[b].nh + sp.blocks[b].np >= 5) {
+              tri |= s.find(std::string(t.in[b]) + "[") != std::string::npos;
+              tri |= s.rfind(std::string(t.out[b]) + "[", 0) == 0;
+            }
+          e.prec = tri ? ds[act[j]]->opt.prec : Prec::FP64;
+          e.sink = &sink[j];
+          e.term(s);
+          e.sink = nullptr;
+          all.insert(all.end(), sink[j].gemms.begin(), sink[j].gemms.end());
+        }
+        // grouped only when every GEMM of the term would leave the device
+        // under-filled on its own (the grouped launch joins all instances at
+        // the term); otherwise each instance runs its GEMM on its own stream
+        // (the same kernel, so the same bits)
+        bool group = !all.empty();
+        for (const GemmArgs& g : all) group = group && gemm_tiles(g) < kGroupBelowTiles;
+        if (group) {
+          join_to_batch();
+          // each term has its own regions of the item tables: the copies of
+          // earlier terms may still be pending when this one is written, and
+          // a recording keeps every term's items
+          launch_gemm_grouped(all, (char*)gb.pin + (size_t)k * na * isz, (char*)gb.dev + (size_t)k * na * isz,
+                              gb.queue, S);
+          fork_from_batch();
+        }
+        for (size_t j = 0; j < na; ++j) {
+          Engine& e = *cs[act[j]]->eng;
+          if (!group)
+            for (const GemmArgs& g : sink[j].gemms) launch_gemm(g, e.stream);
+          for (auto& f : sink[j].after) f();
+          sink[j].gemms.clear();
+          sink[j].after.clear();
+        }
+      }
+      for (size_t j = 0; j < na; ++j) scope[j].reset();
+    };
+    bool ran = false;
+    if (!profiled && gb.exec && key == gb.key) {
+      join_to_batch();
+      FNO_HIP(hipGraphLaunch(gb.exec, S));
+      fork_from_batch();
+      ++gb.replays;
+      ran = true;
+    } else if (!profiled && key == gb.seen) {
+      // record: the batch stream starts the capture, the instance streams
+      // join it through the fork event and leave it through the final join
+      gb.drop_graph();
+      join_to_batch();  // outside the capture: S after the R blocks are in place
+      Program dummy;
+      for (int i : act) cs[i]->eng->set_external_record(&dummy);
+      hipGraph_t graph = nullptr;
+      bool ok = false;
+      FNO_HIP(hipStreamBeginCapture(S, hipStreamCaptureModeRelaxed));
+      try {
+        fork_from_batch();
+        sweep();
+        join_to_batch();
+        ok = true;
+      } catch (const Error&) {
+        try {  // leave no instance stream inside the (now invalid) capture
+          join_to_batch();
+        } catch (const Error&) {
+        }
+      }
+      for (int i : act) cs[i]->eng->set_external_record(nullptr);
+      const hipError_t st = hipStreamEndCapture(S, &graph);
+      if (ok && st == hipSuccess && graph) {
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess) {
+          gb.exec = exec;
+          gb.key = key;
+          ++gb.recordings;
+        }
+      }
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipGetLastError();
+      if (gb.exec) {
+        FNO_HIP(hipGraphLaunch(gb.exec, S));
+        fork_from_batch();
+        ran = true;
+      }
+      gb.seen.clear();
+    }
+    if (!ran) {
+      // from the host (the host-written item tables of a recording would be
+      // overwritten: drop it)
+      gb.drop_graph();
+      join_to_batch();
+      fork_from_batch();
+      sweep();
+      std::vector<int64_t> after;
+      for (size_t j = 0; j < na; ++j) {
+        const Engine& e = *cs[act[j]]->eng;
+        after.push_back(act[j]);
+        after.push_back((int64_t)e.epoch);
+        after.push_back((int64_t)ds[act[j]]->opt.prec);
+        after.push_back(ds[act[j]]->opt.left ? 1 : 0);
+      }
+      gb.seen = after == key ? key : std::vector<int64_t>{};
+    }
+    for (size_t j = 0; j < na; ++j) {
       Context& c = *cs[act[j]];
       Davidson& d = *ds[act[j]];
       Engine& e = *c.eng;
       EomSpace& sp = *c.eom_;
       const EomTables& t = *tab[j];
-      scope[j].reset();
-      e.prec = Prec::FP64;
-      e.record = false;
-      double tf = 0, af = 0;
-      for (auto& st : e.stats) {
-        af += st.flops;
-        for (int b = 0; b < t.nblocks; ++b)
-          if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
-              (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
-               st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
-            tf += st.flops;
-            break;
-          }
+      {  // flops of the sweep (a replay has the statistics of the host-run or recorded sweep)
+        double tf = 0, af = 0;
+        for (auto& st : e.stats) {
+          af += st.flops;
+          for (int b = 0; b < t.nblocks; ++b)
+            if (sp.blocks[b].nh + sp.blocks[b].np >= 5 &&
+                (st.term.find(std::string(t.in[b]) + "[") != std::string::npos ||
+                 st.term.rfind(std::string(t.out[b]) + "[", 0) == 0)) {
+              tf += st.flops;
+              break;
+            }
+        }
+        c.last_triples_flops += tf;
+        c.last_all_flops += af;
       }
-      c.last_triples_flops += tf;
-      c.last_all_flops += af;
       double* sigma = d.S + (int64_t)d.ns * d.dim;
       for (int b = 0; b < t.nblocks; ++b) {
         const int64_t sz = sp.blocks[b].size;
         launch_scale_rows(sigma + sp.blocks[b].offset, d.dim, e.get(t.out[b])->d, sz, (double)t.sign[b], sz,
-                          cnt[j], cnt[j], S);
+                          cnt[j], cnt[j], e.stream);
       }
       d.ns += cnt[j];
     }
-    // the instances' own streams continue after the round
-    FNO_HIP(hipStreamSynchronize(S));
   }
 }
 

@@ -669,7 +669,9 @@ struct GroupItem {
   const void* B;
   void* C;
   double alpha, beta;
-  int64_t first;
+  int64_t first;           // first queue index; the item's tiles follow, split-K slice by slice
+  int64_t nmn;             // output tiles per split-K slice
+  int64_t kchunk, cz;      // split-K: k values per slice, partial-product stride (0: no split)
   int m_fast;
 };
 
@@ -695,9 +697,10 @@ __global__ void __launch_bounds__(256, 2) gemm_grouped_kernel(const GroupItem* _
         hi = mid - 1;
     }
     const GroupItem& it = items[lo];
+    const int64_t rem = w - it.first, z = rem / it.nmn;
     gemm_k4_body<T, BM, BN, AK, BN_FAST, 16, VW>(it.M, it.N, it.K, (const T*)it.A, it.lda, (const T*)it.B, it.ldb,
-                                                 (T*)it.C, it.ldc, (T)it.alpha, (T)it.beta, it.K > 0 ? it.K : 1, 0,
-                                                 it.m_fast, w - it.first, 0);
+                                                 (T*)it.C, it.ldc, (T)it.alpha, (T)it.beta, it.kchunk, it.cz,
+                                                 it.m_fast, rem - z * it.nmn, z);
     __syncthreads();  // the tile's LDS and w_s are reused by the next index
   }
 }
@@ -1001,6 +1004,12 @@ size_t gemm_split_bytes(const GemmArgs& g, int split) {
 
 int gemm_default_tile(const GemmArgs& g) { return default_tile(g); }
 
+int64_t gemm_tiles(const GemmArgs& g) {
+  const int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
+  return ((g.M + kTiles[t].bm - 1) / kTiles[t].bm) * ((g.N + kTiles[t].bn - 1) / kTiles[t].bn) *
+         (g.split > 1 ? g.split : 1);
+}
+
 std::string gemm_label(const GemmArgs& g) {
   int t = (g.tile >= 0 && g.tile < kNumTiles) ? g.tile : default_tile(g);
   if (t >= 15 && g.prec != Prec::FP32) t = 3;  // FP32-only tiles run as 128 x 128
@@ -1105,11 +1114,11 @@ void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, 
   for (int i = 0; i < (int)gs.size(); ++i) {
     GemmArgs g = gs[i];
     g.tile = -1;
-    g.split = 1;
     if (g.M == 0 || g.N == 0) continue;
     const int t = default_tile(g);
-    if (g.prec == Prec::BF16X3 || t >= kGroupTiles) {
+    if (g.prec == Prec::BF16X3 || t >= kGroupTiles || (g.split > 1 && !g.ws)) {
       g.tile = t;
+      if (!g.ws) g.split = 1;
       launch_gemm(g, s);
       continue;
     }
@@ -1119,6 +1128,7 @@ void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, 
   }
   GroupItem* hp = (GroupItem*)pin;
   int used = 0;
+  std::vector<std::pair<int, int>> reduce;  // (GEMM, slices) of the split-K items
   struct Launch {
     int key, off, n;
     int64_t total;
@@ -1136,15 +1146,30 @@ void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, 
       it.K = g.K;
       it.lda = g.lda;
       it.ldb = g.ldb;
-      it.ldc = g.ldc;
       it.A = g.A;
       it.B = g.B;
-      it.C = g.C;
-      it.alpha = g.alpha;
-      it.beta = g.beta;
       it.first = L.total;
+      it.nmn = ((g.M + kTiles[tile].bm - 1) / kTiles[tile].bm) * ((g.N + kTiles[tile].bn - 1) / kTiles[tile].bn);
       it.m_fast = m_fast_order(g);
-      L.total += ((g.M + kTiles[tile].bm - 1) / kTiles[tile].bm) * ((g.N + kTiles[tile].bn - 1) / kTiles[tile].bn);
+      int64_t nz = 1;
+      if (g.split > 1) {  // partial products of the K slices into g.ws, summed after the launch
+        it.kchunk = (((g.K + g.split - 1) / g.split + 15) / 16) * 16;
+        nz = (g.K + it.kchunk - 1) / it.kchunk;
+        it.C = g.ws;
+        it.ldc = g.N;
+        it.cz = g.M * g.N;
+        it.alpha = 1.0;
+        it.beta = 0.0;
+        reduce.push_back({i, (int)nz});
+      } else {
+        it.kchunk = g.K > 0 ? g.K : 1;
+        it.cz = 0;
+        it.C = g.C;
+        it.ldc = g.ldc;
+        it.alpha = g.alpha;
+        it.beta = g.beta;
+      }
+      L.total += it.nmn * nz;
       hp[used++] = it;
       ++L.n;
     }
@@ -1162,6 +1187,14 @@ void launch_gemm_grouped(const std::vector<GemmArgs>& gs, void* pin, void* dev, 
       grouped_launch<double>(tile, lay, d, L.n, L.total, q + j, s);
     else
       grouped_launch<float>(tile, lay, d, L.n, L.total, q + j, s);
+  }
+  for (auto& r : reduce) {
+    const GemmArgs& g = gs[r.first];
+    if (g.prec == Prec::FP64)
+      launch_splitk_reduce<double>((const double*)g.ws, r.second, g.M, g.N, (double*)g.C, g.ldc, g.alpha, g.beta, s);
+    else
+      launch_splitk_reduce<float>((const float*)g.ws, r.second, g.M, g.N, (float*)g.C, g.ldc, (float)g.alpha,
+                                  (float)g.beta, s);
   }
   FNO_HIP(hipGetLastError());
 }

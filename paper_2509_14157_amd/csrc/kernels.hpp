@@ -104,11 +104,14 @@ void launch_gemm(const GemmArgs& g, hipStream_t s);
 std::string gemm_label(const GemmArgs& g);
 int gemm_num_tiles(Prec p);
 int gemm_default_tile(const GemmArgs& g);  // the tile launch_gemm uses for tile = -1
+int64_t gemm_tiles(const GemmArgs& g);      // workgroups launch_gemm runs for g (split-K slices included)
 // Grouped GEMMs: the GEMMs of `gs` (independent: no output read by another)
 // in one persistent launch per kernel instantiation, each workgroup taking
 // tiles of any of them from a device work queue.  Every GEMM runs with its
-// default tile and without split-K and gives the bits launch_gemm gives with
-// those settings (split-BF16 and the non-default tiles run one by one).
+// default tile, split into g.split K slices when g.split > 1 and g.ws holds
+// their partial products (summed afterwards in a fixed order), and gives the
+// bits launch_gemm gives with those settings (split-BF16 and the non-default
+// tiles run one by one).
 // pin: pinned host table and dev: device table of gs.size() items of
 // gemm_group_item_bytes() each (the host table must stay unchanged until the
 // stream has passed the launch); queue: gemm_group_max_launches() 8-byte
