@@ -374,6 +374,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       // one 16 x 16 x 16 step per tile and block: lo*hi, hi*lo, then hi*hi,
       // each a sweep over the 8 accumulators
       const int kb = 4 * (lane >> 4);
+      __builtin_amdgcn_s_setprio(1);
       s4_t ah[2], al[2], bh[4], bl[4];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
@@ -399,6 +400,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      __builtin_amdgcn_s_setprio(0);
       return;
     } else {
     T af[2][2], bf[2][4];
@@ -410,6 +412,10 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       for (int j = 0; j < 4; ++j) bf[r][j] = L.Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
     };
     __builtin_amdgcn_iglp_opt(0);
+    // FP32: the wave raises its priority while it issues its MFMAs, so that
+    // the SIMD's other waves' staging work does not delay them (FP64 MFMAs
+    // are long enough that this only slows the staging)
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(1);
     read(0, 0);
 #pragma unroll
     for (int st = 0; st < kBK / 4; ++st) {
@@ -420,6 +426,7 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[r][i], bf[r][j], acc[i][j]);
     }
+    if constexpr (sizeof(T) == 4) __builtin_amdgcn_s_setprio(0);
     }
   };
   if constexpr (sizeof(T) == 4 && !B3) {
