@@ -239,11 +239,14 @@ void Context::dress() {
   Tensor* g0 = e.get("G");
   const double* t1 = e.get("T1")->d;  // t1[i][a], o x v
   if (launch_dress_first_slot(g0->d, gd->d, t1, nocc, nvir, e.stream)) {
-    // slot 0 done with the copy; slots 1 and 2 are strided passes (one
-    // thread per position of the other slots), slot 3 a GEMM on the rows
+    // slot 0 done with the copy; slot 1 is a strided pass (one thread per
+    // position of the other slots); slots 2 and 3 one pass over the
+    // contiguous (r, s) blocks, else a strided pass and a GEMM on the rows
     launch_dress_pass(gd->d, t1, nocc, nvir, 1, true, e.stream);
-    launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
-    dress_last_slot(gd->d, t1);
+    if (!launch_dress_ket_pair(gd->d, gd->d, t1, nocc, nvir, e.stream)) {
+      launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
+      dress_last_slot(gd->d, t1);
+    }
   } else {
     FNO_HIP(hipMemcpyAsync(gd->d, g0->d, (size_t)g0->elems * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
     dress_gemm_slots(gd->d, t1);
@@ -817,13 +820,12 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
       order.erase(order.begin());
     }
     order.push_back(slot);
-    launch_axpby(ht[slot], amp_, 1.0, 0.0, nt_, e.stream);
-    launch_jacobi(ht[slot], res_, den_, he[slot], nt_, e.stream);
-    // |r|^2 and every overlap <e_slot|e_s> in two launches; the DIIS system
-    // is solved on the device, so the host does not wait here: it reads
-    // |r|^2 with the energy, after the next residual has been enqueued
-    launch_dots(res_, nt_, 1, res_, nt_, scratch_, dres, e.stream);
-    if (m > 0) launch_dots(he[0], nt_, (int)order.size() > 0 ? mm : 0, he[slot], nt_, scratch_, dres + 2, e.stream);
+    // the Jacobi step into the history slot, its error vector, |r|^2 and every
+    // overlap <e_s|e_slot> in one pass; the DIIS system is solved on the
+    // device, so the host does not wait here: it reads |r|^2 with the energy,
+    // after the next residual has been enqueued
+    launch_diis_step(amp_, res_, den_, ht[slot], he[0], slot, m > 0 ? mm : 0, nt_, scratch_, dres, dres + 2,
+                     e.stream);
     FNO_HIP(hipMemcpyAsync(pinned() + 1, dres, sizeof(double), hipMemcpyDeviceToHost, e.stream));
     const bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
     if (m > 0) {

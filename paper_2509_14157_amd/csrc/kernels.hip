@@ -390,6 +390,96 @@ void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial
   FNO_HIP(hipGetLastError());
 }
 
+// One pass of a Jacobi step with its DIIS bookkeeping:
+//   e = r / d,  t_next = t + e,  e_slot = e,  |r|^2,  <e_k | e> for k < nk
+// (e_k = es + k * n; slot k == slot is the new e itself).  Reads t, r, d and
+// the nk - 1 older error vectors once; per-block partials (row 0: |r|^2, row
+// 1 + k: <e_k|e>) are summed in a fixed order by diis_final_kernel.
+constexpr int kDiisBlocks = 2048;
+constexpr int kDiisMaxVec = 16;
+
+template <int NK>
+__global__ void __launch_bounds__(256) diis_step_kernel(const double* __restrict__ t, const double* __restrict__ r,
+                                                        const double* __restrict__ d, double* __restrict__ t_next,
+                                                        double* __restrict__ es, int slot, int64_t n,
+                                                        double* __restrict__ partial) {
+  double acc[NK + 1];
+#pragma unroll
+  for (int k = 0; k <= NK; ++k) acc[k] = 0.0;
+  double* e_new = es + (int64_t)slot * n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    // every load of the element first (the slot's old value is read and
+    // replaced by the new error), then the arithmetic
+    double h[NK > 0 ? NK : 1];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) h[k] = es[(int64_t)k * n + i];
+    const double ri = r[i];
+    const double e = ri / d[i];
+    t_next[i] = t[i] + e;
+    e_new[i] = e;
+    acc[0] += ri * ri;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) acc[1 + k] += (k == slot ? e : h[k]) * e;
+  }
+  __shared__ double wsum[4][NK + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k <= NK; ++k) {
+    double a = acc[k];
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_down(a, o, 64);
+    if (lane == 0) wsum[w][k] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x <= NK)
+    partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] =
+        wsum[0][threadIdx.x] + wsum[1][threadIdx.x] + wsum[2][threadIdx.x] + wsum[3][threadIdx.x];
+}
+
+// out_rr = row 0 of the partials, out_ov[k] = row 1 + k
+__global__ void __launch_bounds__(256) diis_final_kernel(const double* __restrict__ partial, int nblk,
+                                                         double* __restrict__ out_rr, double* __restrict__ out_ov) {
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += blockDim.x) acc += partial[(int64_t)j * nblk + i];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (j == 0)
+      out_rr[0] = v;
+    else
+      out_ov[j - 1] = v;
+  }
+}
+
+int diis_step_partials(int nk) { return (nk + 1) * kDiisBlocks; }
+
+void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int slot,
+                      int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s) {
+  FNO_REQUIRE(nk >= 0 && nk <= kDiisMaxVec && (nk == 0 || (slot >= 0 && slot < nk)), kEINVAL,
+              "DIIS step: history of " + std::to_string(nk) + " vectors, slot " + std::to_string(slot));
+  if (n == 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > kDiisBlocks) blocks = kDiisBlocks;
+  const dim3 grid((unsigned)blocks), blk(256);
+  switch (nk) {
+#define FNO_DIIS_CASE(K) \
+  case K:                \
+    diis_step_kernel<K><<<grid, blk, 0, s>>>(t, r, d, t_next, es, slot, n, partial); \
+    break;
+    FNO_DIIS_CASE(0) FNO_DIIS_CASE(1) FNO_DIIS_CASE(2) FNO_DIIS_CASE(3) FNO_DIIS_CASE(4) FNO_DIIS_CASE(5)
+    FNO_DIIS_CASE(6) FNO_DIIS_CASE(7) FNO_DIIS_CASE(8) FNO_DIIS_CASE(9) FNO_DIIS_CASE(10) FNO_DIIS_CASE(11)
+    FNO_DIIS_CASE(12) FNO_DIIS_CASE(13) FNO_DIIS_CASE(14) FNO_DIIS_CASE(15) FNO_DIIS_CASE(16)
+#undef FNO_DIIS_CASE
+  }
+  FNO_HIP(hipGetLastError());
+  diis_final_kernel<<<dim3(nk + 1), dim3(256), 0, s>>>(partial, (int)blocks, out_rr, out_ov);
+  FNO_HIP(hipGetLastError());
+}
+
 // y -= sum_j c[j] * x_j   (Gram-Schmidt projection / Ritz combination)
 __global__ void __launch_bounds__(256) gemv_acc_kernel(double* __restrict__ y, const double* __restrict__ xs,
                                                        int64_t ldx, const double* __restrict__ c, int nvec,
@@ -1129,22 +1219,36 @@ __global__ void __launch_bounds__(256) dress_slice_kernel(double* __restrict__ g
       // g[a] -= sum_i t1[i][a] g[i]
 #pragma unroll
       for (int i = 0; i < MAXO; ++i) occ[i] = i < nocc ? base[(int64_t)i * inner] : 0.0;
-      for (int a = 0; a < nvir; ++a) {
-        double acc = 0.0;
+      // 8 virtual rows at a time: their loads are issued before any store
+      for (int a0 = 0; a0 < nvir; a0 += 8) {
+        double gv[8];
 #pragma unroll
-        for (int i = 0; i < MAXO; ++i)
-          if (i < nocc) acc += t1[(int64_t)i * nvir + a] * occ[i];
-        base[(int64_t)(nocc + a) * inner] -= acc;
+        for (int u = 0; u < 8; ++u) gv[u] = a0 + u < nvir ? base[(int64_t)(nocc + a0 + u) * inner] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (a0 + u >= nvir) break;
+          double acc = 0.0;
+#pragma unroll
+          for (int i = 0; i < MAXO; ++i)
+            if (i < nocc) acc += t1[(int64_t)i * nvir + a0 + u] * occ[i];
+          base[(int64_t)(nocc + a0 + u) * inner] = gv[u] - acc;
+        }
       }
     } else {
       // g[i] += sum_a t1[i][a] g[a]
 #pragma unroll
       for (int i = 0; i < MAXO; ++i) occ[i] = 0.0;
-      for (int a = 0; a < nvir; ++a) {
-        const double v = base[(int64_t)(nocc + a) * inner];
+      for (int a0 = 0; a0 < nvir; a0 += 8) {
+        double gv[8];
 #pragma unroll
-        for (int i = 0; i < MAXO; ++i)
-          if (i < nocc) occ[i] += t1[(int64_t)i * nvir + a] * v;
+        for (int u = 0; u < 8; ++u) gv[u] = a0 + u < nvir ? base[(int64_t)(nocc + a0 + u) * inner] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (a0 + u >= nvir) break;
+#pragma unroll
+          for (int i = 0; i < MAXO; ++i)
+            if (i < nocc) occ[i] += t1[(int64_t)i * nvir + a0 + u] * gv[u];
+        }
       }
 #pragma unroll
       for (int i = 0; i < MAXO; ++i)
@@ -1169,14 +1273,156 @@ __global__ void __launch_bounds__(256) dress_first_slot_kernel(const double* __r
         occ[i] = G[(int64_t)i * n3 + c];
         Gd[(int64_t)i * n3 + c] = occ[i];
       }
-    for (int a = 0; a < nvir; ++a) {
-      double acc = G[(int64_t)(nocc + a) * n3 + c];
+    for (int a0 = 0; a0 < nvir; a0 += 8) {
+      double gv[8];
 #pragma unroll
-      for (int i = 0; i < MAXO; ++i)
-        if (i < nocc) acc -= t1[(int64_t)i * nvir + a] * occ[i];
-      Gd[(int64_t)(nocc + a) * n3 + c] = acc;
+      for (int u = 0; u < 8; ++u) gv[u] = a0 + u < nvir ? G[(int64_t)(nocc + a0 + u) * n3 + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (a0 + u >= nvir) break;
+        double acc = gv[u];
+#pragma unroll
+        for (int i = 0; i < MAXO; ++i)
+          if (i < nocc) acc -= t1[(int64_t)i * nvir + a0 + u] * occ[i];
+        Gd[(int64_t)(nocc + a0 + u) * n3 + c] = acc;
+      }
     }
   }
+}
+
+// Both annihilation slots (2 and 3) in one pass: for each (p, q) the n x n
+// block B[r][s] = g[(p n + q) n^2 + r n + s] (contiguous) becomes Y^T B Y with
+// Y = 1 + t1 on the virtual-occupied block.  With T[i][a] = t1[i][a]:
+//   B'_vv = B_vv,  B'_vo = B_vo + B_vv T^T,  B'_ov = B_ov + T B_vv,
+//   B'_oo = B_oo + T B_vo + B'_ov T^T.
+// One workgroup per block: the block and T are staged in LDS, the three
+// products run as 16 x 16 FP64 MFMA tiles (one wave per tile, k in steps of
+// 4, operands past o or v read as zero) into an LDS side buffer, and the
+// block is written back whole, so the pass may run in place (src == dst).
+constexpr int kKetPairMaxLds = 8192;  // doubles: n^2 + 3 o v + o^2
+typedef double ketd4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) dress_ket_pair_kernel(const double* src, double* dst,
+                                                             const double* __restrict__ t1, int nocc, int nvir) {
+  extern __shared__ double lds[];
+  const int o = nocc, v = nvir, n = o + v;
+  const int nn = n * n;
+  double* B = lds;
+  double* Ts = B + nn;        // o x v, T[i][a]
+  double* Sov = Ts + o * v;   // o x v
+  double* Svo = Sov + o * v;  // v x o
+  double* Soo = Svo + v * o;  // o x o
+  const double* g = src + (int64_t)blockIdx.x * nn;
+  // the block and then T (contiguous behind it in LDS): 16 loads in flight
+  // per thread before any is stored
+  constexpr int U = 16;
+  const int nst = nn + o * v;
+  for (int base = 0; base < nst; base += 256 * U) {
+    double r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = base + u * 256 + (int)threadIdx.x;
+      r[u] = k < nn ? g[k] : k < nst ? t1[k - nn] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int k = base + u * 256 + (int)threadIdx.x;
+      if (k < nn)
+        B[k] = r[u];
+      else if (k < nst)
+        Ts[k - nn] = r[u];
+    }
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int lr = lane & 15, lk = lane >> 4;  // operand row/column and k of this lane
+  const int to = (o + 15) / 16, tv = (v + 15) / 16;
+  // One 16 x 16 tile: acc += sum over k < v of A(row, k) B(k, col), the
+  // operands of the next k step read from LDS before the current MFMA issues.
+  auto tile = [&](auto fa, auto fb, ketd4_t acc) {
+    double an = fa(lk), bn = fb(lk);
+    for (int k0 = 0; k0 < v; k0 += 4) {
+      const double ac = an, bc = bn;
+      if (k0 + 4 < v) {
+        an = fa(k0 + 4 + lk);
+        bn = fb(k0 + 4 + lk);
+      }
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac, bc, acc, 0, 0, 0);
+    }
+    return acc;
+  };
+  // phase 1: S_ov tiles (to x tv), S_vo tiles (tv x to), and the first half
+  // of the S_oo tiles (to x to): B_oo + T B_vo
+  const int n1 = to * tv, n2 = 2 * to * tv, n3 = n2 + to * to;
+  for (int job = wave; job < n3; job += 4) {
+    const ketd4_t zero = {0.0, 0.0, 0.0, 0.0};
+    if (job < n1) {
+      const int mt = job / tv, nt = job - mt * tv;
+      const int i = mt * 16 + lr, b = nt * 16 + lr;
+      const ketd4_t acc = tile([&](int a) { return (i < o && a < v) ? Ts[i * v + a] : 0.0; },
+                               [&](int a) { return (a < v && b < v) ? B[(o + a) * n + o + b] : 0.0; }, zero);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + lk + 4 * r;
+        if (row < o && b < v) Sov[row * v + b] = B[row * n + o + b] + acc[r];
+      }
+    } else if (job < n2) {
+      const int jb = job - n1, mt = jb / to, nt = jb - mt * to;
+      const int a = mt * 16 + lr, j = nt * 16 + lr;
+      const ketd4_t acc = tile([&](int b) { return (a < v && b < v) ? B[(o + a) * n + o + b] : 0.0; },
+                               [&](int b) { return (b < v && j < o) ? Ts[j * v + b] : 0.0; }, zero);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + lk + 4 * r;
+        if (row < v && j < o) Svo[row * o + j] = B[(o + row) * n + j] + acc[r];
+      }
+    } else {
+      const int jb = job - n2, mt = jb / to, nt = jb - mt * to;
+      const int i = mt * 16 + lr, j = nt * 16 + lr;
+      const ketd4_t acc = tile([&](int a) { return (i < o && a < v) ? Ts[i * v + a] : 0.0; },
+                               [&](int a) { return (a < v && j < o) ? B[(o + a) * n + j] : 0.0; }, zero);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = mt * 16 + lk + 4 * r;
+        if (row < o && j < o) Soo[row * o + j] = B[row * n + j] + acc[r];
+      }
+    }
+  }
+  __syncthreads();
+  // phase 2: S_oo += S_ov T^T
+  for (int job = wave; job < to * to; job += 4) {
+    const int mt = job / to, nt = job - mt * to;
+    const int i = mt * 16 + lr, j = nt * 16 + lr;
+    const ketd4_t zero = {0.0, 0.0, 0.0, 0.0};
+    const ketd4_t acc = tile([&](int b) { return (i < o && b < v) ? Sov[i * v + b] : 0.0; },
+                             [&](int b) { return (b < v && j < o) ? Ts[j * v + b] : 0.0; }, zero);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = mt * 16 + lk + 4 * r;
+      if (row < o && j < o) Soo[row * o + j] += acc[r];
+    }
+  }
+  __syncthreads();
+  double* out = dst + (int64_t)blockIdx.x * nn;
+  for (int k = threadIdx.x; k < nn; k += 256) {
+    const int r = k / n, c = k - r * n;
+    double val;
+    if (r < o)
+      val = c < o ? Soo[r * o + c] : Sov[r * v + (c - o)];
+    else
+      val = c < o ? Svo[(r - o) * o + c] : B[k];
+    out[k] = val;
+  }
+}
+
+bool launch_dress_ket_pair(const double* src, double* dst, const double* t1, int nocc, int nvir, hipStream_t s) {
+  const int64_t n = nocc + nvir;
+  const int64_t need = n * n + 3 * (int64_t)nocc * nvir + (int64_t)nocc * nocc;
+  if (nocc == 0 || nvir == 0 || need > kKetPairMaxLds) return false;
+  dress_ket_pair_kernel<<<(unsigned)(n * n), 256, (size_t)need * sizeof(double), s>>>(src, dst, t1, nocc, nvir);
+  FNO_HIP(hipGetLastError());
+  return true;
 }
 
 bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s) {

@@ -42,6 +42,10 @@ void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos,
 // Gd = G with the first creation slot dressed (one streaming pass); false
 // (nothing launched) for more than 32 occupied orbitals
 bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s);
+// Both annihilation slots (2, 3) of the T1 transform in one pass, dst = Y^T B Y
+// per (p, q) block of src (src == dst allowed); false (nothing launched) when
+// a block and its side buffers exceed 64 KiB of LDS
+bool launch_dress_ket_pair(const double* src, double* dst, const double* t1, int nocc, int nvir, hipStream_t s);
 // y_j = a * x_j for j < count, y_j = 0 for count <= j < rows (n elements each; y_j = y + j*ldy, x_j = x + j*ldx)
 void launch_scale_rows(double* y, int64_t ldy, const double* x, int64_t ldx, double a, int64_t n, int count, int rows,
                        hipStream_t s);
@@ -57,6 +61,14 @@ void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial
                     double beta, hipStream_t s);
 void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64_t n, double* partial, double* out,
                  hipStream_t s);
+// A Jacobi step with its DIIS bookkeeping in one pass over n elements:
+// e = r / d, t_next = t + e, es[slot] = e, *out_rr = |r|^2 and
+// out_ov[k] = <es[k] | e> for k < nk (es[k] = es + k * n, nk <= 16;
+// nk = 0: no history, es may then be t_next's own error buffer of one
+// vector).  partial needs diis_step_partials(nk) doubles; deterministic.
+int diis_step_partials(int nk);
+void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int slot,
+                      int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s);
 // History slots of a DIIS step, oldest first.
 struct DiisSlots {
   int k = 0;
