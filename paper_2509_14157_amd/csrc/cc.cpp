@@ -239,14 +239,11 @@ void Context::dress() {
   Tensor* g0 = e.get("G");
   const double* t1 = e.get("T1")->d;  // t1[i][a], o x v
   if (launch_dress_first_slot(g0->d, gd->d, t1, nocc, nvir, e.stream)) {
-    // slot 0 done with the copy; slot 1 is a strided pass (one thread per
-    // position of the other slots); slots 2 and 3 one pass over the
-    // contiguous (r, s) blocks, else a strided pass and a GEMM on the rows
+    // slot 0 done with the copy; slots 1 and 2 are strided passes (one
+    // thread per position of the other slots), slot 3 a GEMM on the rows
     launch_dress_pass(gd->d, t1, nocc, nvir, 1, true, e.stream);
-    if (!launch_dress_ket_pair(gd->d, gd->d, t1, nocc, nvir, e.stream)) {
-      launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
-      dress_last_slot(gd->d, t1);
-    }
+    launch_dress_pass(gd->d, t1, nocc, nvir, 2, false, e.stream);
+    dress_last_slot(gd->d, t1);
   } else {
     FNO_HIP(hipMemcpyAsync(gd->d, g0->d, (size_t)g0->elems * sizeof(double), hipMemcpyDeviceToDevice, e.stream));
     dress_gemm_slots(gd->d, t1);

@@ -1273,157 +1273,16 @@ __global__ void __launch_bounds__(256) dress_first_slot_kernel(const double* __r
         occ[i] = G[(int64_t)i * n3 + c];
         Gd[(int64_t)i * n3 + c] = occ[i];
       }
-    for (int a0 = 0; a0 < nvir; a0 += 8) {
-      double gv[8];
+    for (int a = 0; a < nvir; ++a) {
+      double acc = G[(int64_t)(nocc + a) * n3 + c];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) gv[u] = a0 + u < nvir ? G[(int64_t)(nocc + a0 + u) * n3 + c] : 0.0;
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        if (a0 + u >= nvir) break;
-        double acc = gv[u];
-#pragma unroll
-        for (int i = 0; i < MAXO; ++i)
-          if (i < nocc) acc -= t1[(int64_t)i * nvir + a0 + u] * occ[i];
-        Gd[(int64_t)(nocc + a0 + u) * n3 + c] = acc;
-      }
+      for (int i = 0; i < MAXO; ++i)
+        if (i < nocc) acc -= t1[(int64_t)i * nvir + a] * occ[i];
+      Gd[(int64_t)(nocc + a) * n3 + c] = acc;
     }
   }
 }
 
-// Both annihilation slots (2 and 3) in one pass: for each (p, q) the n x n
-// block B[r][s] = g[(p n + q) n^2 + r n + s] (contiguous) becomes Y^T B Y with
-// Y = 1 + t1 on the virtual-occupied block.  With T[i][a] = t1[i][a]:
-//   B'_vv = B_vv,  B'_vo = B_vo + B_vv T^T,  B'_ov = B_ov + T B_vv,
-//   B'_oo = B_oo + T B_vo + B'_ov T^T.
-// One workgroup per block: the block and T are staged in LDS, the three
-// products run as 16 x 16 FP64 MFMA tiles (one wave per tile, k in steps of
-// 4, operands past o or v read as zero) into an LDS side buffer, and the
-// block is written back whole, so the pass may run in place (src == dst).
-constexpr int kKetPairMaxLds = 8192;  // doubles: n^2 + 3 o v + o^2
-typedef double ketd4_t __attribute__((ext_vector_type(4)));
-
-__global__ void __launch_bounds__(256) dress_ket_pair_kernel(const double* src, double* dst,
-                                                             const double* __restrict__ t1, int nocc, int nvir) {
-  extern __shared__ double lds[];
-  const int o = nocc, v = nvir, n = o + v;
-  const int nn = n * n;
-  double* B = lds;
-  double* Ts = B + nn;        // o x v, T[i][a]
-  double* Sov = Ts + o * v;   // o x v
-  double* Svo = Sov + o * v;  // v x o
-  double* Soo = Svo + v * o;  // o x o
-  const double* g = src + (int64_t)blockIdx.x * nn;
-  // the block and then T (contiguous behind it in LDS): 16 loads in flight
-  // per thread before any is stored
-  constexpr int U = 16;
-  const int nst = nn + o * v;
-  for (int base = 0; base < nst; base += 256 * U) {
-    double r[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = base + u * 256 + (int)threadIdx.x;
-      r[u] = k < nn ? g[k] : k < nst ? t1[k - nn] : 0.0;
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int k = base + u * 256 + (int)threadIdx.x;
-      if (k < nn)
-        B[k] = r[u];
-      else if (k < nst)
-        Ts[k - nn] = r[u];
-    }
-  }
-  __syncthreads();
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  const int lr = lane & 15, lk = lane >> 4;  // operand row/column and k of this lane
-  const int to = (o + 15) / 16, tv = (v + 15) / 16;
-  // One 16 x 16 tile: acc += sum over k < v of A(row, k) B(k, col), the
-  // operands of the next k step read from LDS before the current MFMA issues.
-  auto tile = [&](auto fa, auto fb, ketd4_t acc) {
-    double an = fa(lk), bn = fb(lk);
-    for (int k0 = 0; k0 < v; k0 += 4) {
-      const double ac = an, bc = bn;
-      if (k0 + 4 < v) {
-        an = fa(k0 + 4 + lk);
-        bn = fb(k0 + 4 + lk);
-      }
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ac, bc, acc, 0, 0, 0);
-    }
-    return acc;
-  };
-  // phase 1: S_ov tiles (to x tv), S_vo tiles (tv x to), and the first half
-  // of the S_oo tiles (to x to): B_oo + T B_vo
-  const int n1 = to * tv, n2 = 2 * to * tv, n3 = n2 + to * to;
-  for (int job = wave; job < n3; job += 4) {
-    const ketd4_t zero = {0.0, 0.0, 0.0, 0.0};
-    if (job < n1) {
-      const int mt = job / tv, nt = job - mt * tv;
-      const int i = mt * 16 + lr, b = nt * 16 + lr;
-      const ketd4_t acc = tile([&](int a) { return (i < o && a < v) ? Ts[i * v + a] : 0.0; },
-                               [&](int a) { return (a < v && b < v) ? B[(o + a) * n + o + b] : 0.0; }, zero);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + lk + 4 * r;
-        if (row < o && b < v) Sov[row * v + b] = B[row * n + o + b] + acc[r];
-      }
-    } else if (job < n2) {
-      const int jb = job - n1, mt = jb / to, nt = jb - mt * to;
-      const int a = mt * 16 + lr, j = nt * 16 + lr;
-      const ketd4_t acc = tile([&](int b) { return (a < v && b < v) ? B[(o + a) * n + o + b] : 0.0; },
-                               [&](int b) { return (b < v && j < o) ? Ts[j * v + b] : 0.0; }, zero);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + lk + 4 * r;
-        if (row < v && j < o) Svo[row * o + j] = B[(o + row) * n + j] + acc[r];
-      }
-    } else {
-      const int jb = job - n2, mt = jb / to, nt = jb - mt * to;
-      const int i = mt * 16 + lr, j = nt * 16 + lr;
-      const ketd4_t acc = tile([&](int a) { return (i < o && a < v) ? Ts[i * v + a] : 0.0; },
-                               [&](int a) { return (a < v && j < o) ? B[(o + a) * n + j] : 0.0; }, zero);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = mt * 16 + lk + 4 * r;
-        if (row < o && j < o) Soo[row * o + j] = B[row * n + j] + acc[r];
-      }
-    }
-  }
-  __syncthreads();
-  // phase 2: S_oo += S_ov T^T
-  for (int job = wave; job < to * to; job += 4) {
-    const int mt = job / to, nt = job - mt * to;
-    const int i = mt * 16 + lr, j = nt * 16 + lr;
-    const ketd4_t zero = {0.0, 0.0, 0.0, 0.0};
-    const ketd4_t acc = tile([&](int b) { return (i < o && b < v) ? Sov[i * v + b] : 0.0; },
-                             [&](int b) { return (b < v && j < o) ? Ts[j * v + b] : 0.0; }, zero);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = mt * 16 + lk + 4 * r;
-      if (row < o && j < o) Soo[row * o + j] += acc[r];
-    }
-  }
-  __syncthreads();
-  double* out = dst + (int64_t)blockIdx.x * nn;
-  for (int k = threadIdx.x; k < nn; k += 256) {
-    const int r = k / n, c = k - r * n;
-    double val;
-    if (r < o)
-      val = c < o ? Soo[r * o + c] : Sov[r * v + (c - o)];
-    else
-      val = c < o ? Svo[(r - o) * o + c] : B[k];
-    out[k] = val;
-  }
-}
-
-bool launch_dress_ket_pair(const double* src, double* dst, const double* t1, int nocc, int nvir, hipStream_t s) {
-  const int64_t n = nocc + nvir;
-  const int64_t need = n * n + 3 * (int64_t)nocc * nvir + (int64_t)nocc * nocc;
-  if (nocc == 0 || nvir == 0 || need > kKetPairMaxLds) return false;
-  dress_ket_pair_kernel<<<(unsigned)(n * n), 256, (size_t)need * sizeof(double), s>>>(src, dst, t1, nocc, nvir);
-  FNO_HIP(hipGetLastError());
-  return true;
-}
 
 bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s) {
   if (nocc > kDressMaxOcc || nocc == 0 || nvir == 0) return false;

@@ -42,10 +42,6 @@ void launch_dress_pass(double* g, const double* t1, int nocc, int nvir, int pos,
 // Gd = G with the first creation slot dressed (one streaming pass); false
 // (nothing launched) for more than 32 occupied orbitals
 bool launch_dress_first_slot(const double* G, double* Gd, const double* t1, int nocc, int nvir, hipStream_t s);
-// Both annihilation slots (2, 3) of the T1 transform in one pass, dst = Y^T B Y
-// per (p, q) block of src (src == dst allowed); false (nothing launched) when
-// a block and its side buffers exceed 64 KiB of LDS
-bool launch_dress_ket_pair(const double* src, double* dst, const double* t1, int nocc, int nvir, hipStream_t s);
 // y_j = a * x_j for j < count, y_j = 0 for count <= j < rows (n elements each; y_j = y + j*ldy, x_j = x + j*ldx)
 void launch_scale_rows(double* y, int64_t ldy, const double* x, int64_t ldx, double a, int64_t n, int count, int rows,
                        hipStream_t s);
