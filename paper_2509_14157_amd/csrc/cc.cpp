@@ -81,7 +81,7 @@ void Context::setup_cc() {
   amp_ = alloc(nt_);
   res_ = alloc(nt_);
   den_ = alloc(nt_);
-  scratch_ = alloc(256 * 1024);  // per-block partial sums of up to 512 dot products
+  scratch_ = alloc(256 * 1024);  // per-block partial sums of dot products and of the DIIS step
   dscal_ = alloc(1024);
   for (int k = 0; k < 3; ++k) {
     e.create("T" + tblocks_[k].name, specs[k], sz_, amp_ + tblocks_[k].offset);
@@ -747,6 +747,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   e.prec = opt.prec;
   double* dres = alloc(2 + 16);  // |r|^2, then the overlaps of the new error vector
   const int mm = std::max(m, 1);
+  FNO_REQUIRE(diis_step_partials(mm) <= 256 * 1024, kEINVAL, "DIIS partial sums exceed the scratch buffer");
   // learned guess: after two plain Jacobi iterations the amplitudes are the
   // MP-style guess.  At the third iteration the residual is evaluated at the
   // plain guess and at the learned one (the network corrects the T3 block and

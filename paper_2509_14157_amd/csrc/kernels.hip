@@ -393,8 +393,9 @@ void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial
 // One pass of a Jacobi step with its DIIS bookkeeping:
 //   e = r / d,  t_next = t + e,  e_slot = e,  |r|^2,  <e_k | e> for k < nk
 // (e_k = es + k * n; slot k == slot is the new e itself).  Reads t, r, d and
-// the nk - 1 older error vectors once; per-block partials (row 0: |r|^2, row
-// 1 + k: <e_k|e>) are summed in a fixed order by diis_final_kernel.
+// the nk history error vectors once (the slot's old vector too, so that every
+// load is unconditional); per-block partials (row 0: |r|^2, row 1 + k:
+// <e_k|e>) are summed in a fixed order by diis_final_kernel.
 constexpr int kDiisBlocks = 2048;
 constexpr int kDiisMaxVec = 16;
 
