@@ -74,7 +74,8 @@ struct Params {
   int panel;                   // triples per panel of the tile order
 };
 
-// LDS tiles of one k tile, two stages.  FP64 / FP32: k-major tiles, one
+// LDS tiles of one k tile: one stage for FP64 (24.4 KB, so that four
+// workgroups fit a CU), two for FP32.  FP64 / FP32: k-major tiles, one
 // element per lane per v_mfma_*_16x16x4 step.  Split-BF16: the staged FP32
 // values split into hi + lo BF16 halves (x = hi + lo to about 16 bits),
 // stored with k contiguous per row, so that the four k values of a lane of
@@ -83,8 +84,9 @@ struct Params {
 constexpr int kB3Row = kBK + 4;
 template <typename T, bool B3>
 struct FusedTiles {
-  T As[2][kBK][kBM + 1];
-  __attribute__((aligned(16))) T Bs[2][kBK][kBN + ((sizeof(T) == 8) ? 2 : 4)];  // B rows 16-byte aligned
+  static constexpr int kStages = sizeof(T) == 8 ? 1 : 2;
+  T As[kStages][kBK][kBM + 1];
+  __attribute__((aligned(16))) T Bs[kStages][kBK][kBN + ((sizeof(T) == 8) ? 2 : 4)];  // B rows 16-byte aligned
 };
 template <>
 struct FusedTiles<float, true> {
@@ -110,8 +112,9 @@ __device__ __forceinline__ void split_bf16(float x, unsigned short& h, unsigned 
 //   B: 0 = rows of 16-byte vectors along the columns (k uniform per vector
 //      row: W3_vvvv^T, T3v), 1 = one element per lane, column fastest
 // (B3: split-BF16 products from FP32 operands, T = float)
+// (FP64: four waves per SIMD, i.e. at most 128 registers per lane)
 template <typename T, bool B3 = false>
-__global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
+__global__ void __launch_bounds__(kThreads, sizeof(T) == 8 ? 4 : 2) r3_fused_kernel(Params P) {
   constexpr int VW = 16 / sizeof(T);          // elements per 16-byte vector
   constexpr int AV = kBM * kBK / VW / kThreads;  // A vectors per thread
   constexpr int BV = kBK * kBN / VW / kThreads;  // B vectors per thread
@@ -412,6 +415,19 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       for (int j = 0; j < 4; ++j) bf[r][j] = L.Bs[cur][kr][wn * 64 + j * 16 + (lane & 15)];
     };
     __builtin_amdgcn_iglp_opt(0);
+    if constexpr (sizeof(T) == 8) {
+      // FP64 (four waves per SIMD): one operand register set, each k step's
+      // operands read right before its MFMAs; the other waves cover the wait
+#pragma unroll
+      for (int st = 0; st < kBK / 4; ++st) {
+        read(4 * st, 0);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = mma(af[0][i], bf[0][j], acc[i][j]);
+      }
+      return;
+    }
     // FP32: the wave raises its priority while it issues its MFMAs, so that
     // the SIMD's other waves' staging work does not delay them (FP64 MFMAs
     // are long enough that this only slows the staging)
@@ -454,6 +470,25 @@ __global__ void __launch_bounds__(kThreads, 2) r3_fused_kernel(Params P) {
       step(kt + 1, R1, R0);
     }
     if (kt < nk) step(kt, R0, R1);
+  } else if constexpr (sizeof(T) == 8) {
+    // FP64, one LDS stage: the loads of tile kt + 1 are issued before the
+    // MFMAs of tile kt and stored into the stage once every wave has read it
+    // (two barriers per k tile; four workgroups per CU keep the matrix pipes
+    // fed across them)
+    Regs R;
+    load_tile(0, R);
+    store_tile(0, R);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const bool more = kt + 1 < nk;
+      if (more) load_tile(kt + 1, R);
+      mma_stage(0);
+      __syncthreads();
+      if (more) {
+        store_tile(0, R);
+        __syncthreads();
+      }
+    }
   } else {
     // one k tile in flight: the loads of tile kt + 1 are issued before the
     // MFMAs of tile kt and stored to the other LDS stage after them
