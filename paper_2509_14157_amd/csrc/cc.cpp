@@ -261,14 +261,17 @@ double* Context::pinned() {
   return host_pin_;
 }
 
+// E[0] = the correlation energy of the current amplitudes, one closed-form
+// pass (the terms of kCCEnergy folded onto unique index pairs)
+void Context::energy_terms() {
+  Engine& e = *eng;
+  launch_cc_energy(e.get("F0")->d, e.get("G")->d, amp_ + tblocks_[0].offset, amp_ + tblocks_[1].offset, nocc, nvir,
+                   scratch_, e.get("E")->d, e.stream);
+}
+
 void Context::energy_async() {
   Engine& e = *eng;
-  Prec keep = e.prec;
-  e.prec = Prec::FP64;  // energies are always FP64
-  e.zero(e.get("E"));
-  e.zero(e.get("Ie"));
-  e.terms(kCCEnergy, count(kCCEnergy));
-  e.prec = keep;
+  energy_terms();
   FNO_HIP(hipMemcpyAsync(pinned(), e.get("E")->d, sizeof(double), hipMemcpyDeviceToHost, e.stream));
   if (!e_ready_) FNO_HIP(hipEventCreateWithFlags(&e_ready_, hipEventDisableTiming));
   FNO_HIP(hipEventRecord(e_ready_, e.stream));
@@ -276,12 +279,7 @@ void Context::energy_async() {
 
 double Context::energy() {
   Engine& e = *eng;
-  Prec keep = e.prec;
-  e.prec = Prec::FP64;  // energies are always FP64
-  e.zero(e.get("E"));
-  e.zero(e.get("Ie"));
-  e.terms(kCCEnergy, count(kCCEnergy));
-  e.prec = keep;
+  energy_terms();
   double r;
   FNO_HIP(hipMemcpyAsync(&r, e.get("E")->d, sizeof(double), hipMemcpyDeviceToHost, e.stream));
   FNO_HIP(hipStreamSynchronize(e.stream));

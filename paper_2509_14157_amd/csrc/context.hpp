@@ -135,6 +135,7 @@ class Context {
   void setup_cc();
   void dress();
   double energy();
+  void energy_terms();
   // energy terms and the copy of E into host_pin_[0], followed by e_ready_
   void energy_async();
   double* pinned();  // host_pin_ (kPinned doubles of pinned host memory), allocated on first use

@@ -481,6 +481,58 @@ void launch_diis_step(const double* t, const double* r, const double* d, double*
   FNO_HIP(hipGetLastError());
 }
 
+// CC correlation energy (eq 7) in closed form over unique index pairs:
+//   E = sum_ia f_ia t_ia + sum_{i<j, a<b} <ij||ab> (t_ij^ab + t_ia t_jb - t_ib t_ja)
+// (the quarter-weighted sum over all ijab of <ij||ab> t_ij^ab and the half-
+// weighted one of <ij||ab> t_ia t_jb, folded onto i < j, a < b with the
+// antisymmetry of the integrals).  f: n x n, g: n^4 (both row-major, occupied
+// orbitals first), t1: o x v, t2: packed [i<j][a<b] (colex pairs).  Per-block
+// partials in a fixed partition, summed in a fixed order by dot_final_acc.
+constexpr int kEnergyBlocks = 256;
+
+__device__ __forceinline__ void unpair(int64_t p, int& x0, int& x1) {
+  // x0 < x1 with p = x0 + x1 (x1 - 1) / 2
+  int h = (int)((1.0 + sqrt(1.0 + 8.0 * (double)p)) * 0.5);
+  while ((int64_t)h * (h - 1) / 2 > p) --h;
+  while ((int64_t)(h + 1) * h / 2 <= p) ++h;
+  x1 = h;
+  x0 = (int)(p - (int64_t)h * (h - 1) / 2);
+}
+
+__global__ void __launch_bounds__(256) cc_energy_kernel(const double* __restrict__ f, const double* __restrict__ g,
+                                                        const double* __restrict__ t1, const double* __restrict__ t2,
+                                                        int o, int v, double* __restrict__ partial) {
+  const int64_t n = o + v;
+  const int64_t nv2 = (int64_t)v * (v - 1) / 2, no2 = (int64_t)o * (o - 1) / 2;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  double acc = 0.0;
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < no2 * nv2; q += stride) {
+    int i, j, a, b;
+    unpair(q / nv2, i, j);
+    unpair(q % nv2, a, b);
+    const double gv = g[((i * n + j) * n + o + a) * n + o + b];
+    acc += gv * (t2[q] + t1[i * v + a] * t1[j * v + b] - t1[i * v + b] * t1[j * v + a]);
+  }
+  for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < (int64_t)o * v; q += stride) {
+    const int64_t i = q / v, a = q - i * v;
+    acc += f[i * n + o + a] * t1[q];
+  }
+  for (int s = 32; s > 0; s >>= 1) acc += __shfl_down(acc, s, 64);
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) wsum[w] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+}
+
+void launch_cc_energy(const double* f, const double* g, const double* t1, const double* t2, int o, int v,
+                      double* partial, double* out, hipStream_t s) {
+  cc_energy_kernel<<<dim3(kEnergyBlocks), dim3(256), 0, s>>>(f, g, t1, t2, o, v, partial);
+  FNO_HIP(hipGetLastError());
+  dot_final_acc_kernel<<<dim3(1), dim3(256), 0, s>>>(partial, kEnergyBlocks, out, 1.0, 0.0);
+  FNO_HIP(hipGetLastError());
+}
+
 // y -= sum_j c[j] * x_j   (Gram-Schmidt projection / Ritz combination)
 __global__ void __launch_bounds__(256) gemv_acc_kernel(double* __restrict__ y, const double* __restrict__ xs,
                                                        int64_t ldx, const double* __restrict__ c, int nvec,

@@ -65,6 +65,10 @@ void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64
 int diis_step_partials(int nk);
 void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int slot,
                       int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s);
+// *out = CC correlation energy from f (n x n), g (n^4), t1 (o x v) and packed
+// t2 (see kernels.hip); partial needs 256 doubles
+void launch_cc_energy(const double* f, const double* g, const double* t1, const double* t2, int o, int v,
+                      double* partial, double* out, hipStream_t s);
 // History slots of a DIIS step, oldest first.
 struct DiisSlots {
   int k = 0;
