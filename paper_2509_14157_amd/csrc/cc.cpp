@@ -360,10 +360,11 @@ void Context::residual_body(Prec tri) {
         }
       }
     } join{e};
-    // two lanes from here: the triples intermediates and residual on the main
-    // stream; the doubles intermediates and the T2 parts of the singles and
-    // doubles residual on the side lane, concurrently (they read T1, T2 and
-    // the dressed integrals, and write R1, R2 and the W2/F2 blocks).  The T3
+    // two lanes from here: the triples intermediates (split over both lanes
+    // where T3 is not involved) and residual on the main stream; the doubles
+    // intermediates and the T2 parts of the singles and doubles residual on
+    // the side lane, concurrently (they read T1, T2 and the dressed integrals,
+    // and write R1, R2 and the W2/F2 blocks).  The T3
     // feedback into R1 and R2 follows the triples on the main stream: it uses
     // expansions of T3 made by the triples terms, and the side lane has
     // finished long before the last triples term (the ring), which therefore
@@ -373,9 +374,21 @@ void Context::residual_body(Prec tri) {
     e.fork_mark();
     const bool side = side_ok(tri);
     if (side) {
-      // T3 pieces of W3_vvvo / W3_ovoo from T3v, the other intermediates per term
+      // the intermediates without T3 over both lanes, each output block's
+      // terms on one lane (W3_vvvv, W3_ovvo and F3 on the side lane, W3_oooo,
+      // W3_vvvo and W3_ovoo here), joined before the T3 pieces of W3_vvvo /
+      // W3_ovoo from T3v; the doubles lane then forks again
+      auto side_block = [](const char* t) {
+        return !std::strncmp(t, "W3_vvvv", 7) || !std::strncmp(t, "W3_ovvo", 7) || !std::strncmp(t, "F3_", 3);
+      };
+      e.begin_side();
       for (const char* t : kCCInter3)
-        if (!std::strstr(t, "T3[")) e.term(t);
+        if (!std::strstr(t, "T3[") && side_block(t)) e.term(t);
+      e.end_side();
+      for (const char* t : kCCInter3)
+        if (!std::strstr(t, "T3[") && !side_block(t)) e.term(t);
+      e.join_side();
+      e.fork_mark();
       side_products();
     } else {
       e.terms(kCCInter3, count(kCCInter3));
