@@ -103,6 +103,7 @@ void Engine::fork_mark() {
   }
   FNO_HIP(hipEventRecord(fork_ev_, stream));
   fork_marked_ = true;
+  ++fork_id_;
 }
 
 void Engine::begin_side() {
@@ -1215,27 +1216,28 @@ void Engine::execute(const Plan& p, double scale) {
     auto other_lane = [&](const CacheEntry& ce) {
       if (fork_marked_ && ce.ready_set && ce.lane != lane_) FNO_HIP(hipStreamWaitEvent(stream, ce.ready, 0));
     };
-    auto it = ecache_.find(key);
-    if (it != ecache_.end() && it->second.valid) {
-      other_lane(it->second);
-      hi = it->second.hi;
-      lo = it->second.lo;
-      fast = true;
-      ld = it->second.ld;
-      factor *= sgn * it->second.sign;
-      return true;
-    }
-    it = ecache_.find(keyT);
-    if (it != ecache_.end() && it->second.valid) {
-      other_lane(it->second);
-      hi = it->second.hi;
-      lo = it->second.lo;
-      fast = false;
-      ld = it->second.ld;  // stored as this use's transpose: its row stride
-      factor *= sgnT * it->second.sign;
-      return true;
-    }
-    CacheEntry& ce = ecache_[key];
+    // an entry the other lane made in the current fork cycle is not used
+    // (that would make this lane wait for the other one): each lane then
+    // keeps its own copy, under a lane-tagged key; entries made before the
+    // fork, or in an earlier (joined) cycle, serve both lanes
+    auto usable = [&](const CacheEntry& ce) {
+      return ce.valid && !(fork_marked_ && ce.ready_set && ce.lane != lane_ && ce.fork_id == fork_id_);
+    };
+    const std::string own = lane_ ? "1|" : "0|";
+    for (const std::string* k : {&key, &keyT})
+      for (const std::string& kk : {*k, own + *k}) {
+        auto it = ecache_.find(kk);
+        if (it == ecache_.end() || !usable(it->second)) continue;
+        other_lane(it->second);
+        hi = it->second.hi;
+        lo = it->second.lo;
+        fast = k == &key;
+        ld = it->second.ld;  // as the transpose: its row stride
+        factor *= (k == &key ? sgn : sgnT) * it->second.sign;
+        return true;
+      }
+    auto plain = ecache_.find(key);
+    CacheEntry& ce = ecache_[(plain != ecache_.end() && plain->second.valid) ? own + key : key];
     const int64_t ldp = padded(tab_ok, cols);
     const size_t need = (size_t)(rows * ldp) * esz;
     if (ce.bytes < need) {
@@ -1256,6 +1258,7 @@ void Engine::execute(const Plan& p, double scale) {
     ce.sign = sgn;
     ce.valid = true;
     ce.lane = lane_;
+    ce.fork_id = fork_id_;
     ce.ready_set = fork_marked_;
     if (fork_marked_) {
       if (!ce.ready) {

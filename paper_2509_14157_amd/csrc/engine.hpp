@@ -265,12 +265,14 @@ class Engine {
     int lane = 0;                 // lane that made the current contents
     hipEvent_t ready = nullptr;   // recorded after that expansion
     bool ready_set = false;       // made after the fork mark: consumers on the other lane wait
+    uint64_t fork_id = 0;         // fork cycle in which it was made
   };
   // lanes: `stream` and ws_ belong to the lane being issued to; other_* to the
   // other one (swapped by begin_side / end_side)
   hipStream_t side_stream_ = nullptr, other_stream_ = nullptr;
   hipEvent_t fork_ev_ = nullptr, join_ev_ = nullptr;
   int lane_ = 0;
+  uint64_t fork_id_ = 0;  // counts fork_mark() calls
   bool side_open_ = false, fork_marked_ = false;
   void* other_ws_[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   size_t other_ws_bytes_[7] = {0, 0, 0, 0, 0, 0, 0};
