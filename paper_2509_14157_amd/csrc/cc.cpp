@@ -742,10 +742,12 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
   launch_fill(amp_, 0.0, nt_, e.stream);
   const int m = opt.diis_n;
   std::vector<double*> ht(std::max(m, 1)), he(std::max(m, 1));
-  double* hist = alloc(2 * (int64_t)std::max(m, 1) * nt_);
+  // history vectors at an even stride, so that each starts 16-byte aligned
+  const int64_t ldh = (nt_ + 1) / 2 * 2;
+  double* hist = alloc(2 * (int64_t)std::max(m, 1) * ldh);
   for (int i = 0; i < std::max(m, 1); ++i) {
-    ht[i] = hist + (int64_t)i * nt_;
-    he[i] = hist + (int64_t)(std::max(m, 1) + i) * nt_;
+    ht[i] = hist + (int64_t)i * ldh;
+    he[i] = hist + (int64_t)(std::max(m, 1) + i) * ldh;
   }
   double* dcoef = alloc(32);
   double* dB = alloc(16 * 16);  // error overlaps indexed by slot
@@ -833,7 +835,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
     // overlap <e_s|e_slot> in one pass; the DIIS system is solved on the
     // device, so the host does not wait here: it reads |r|^2 with the energy,
     // after the next residual has been enqueued
-    launch_diis_step(amp_, res_, den_, ht[slot], he[0], slot, m > 0 ? mm : 0, nt_, scratch_, dres, dres + 2,
+    launch_diis_step(amp_, res_, den_, ht[slot], he[0], ldh, slot, m > 0 ? mm : 0, nt_, scratch_, dres, dres + 2,
                      e.stream);
     FNO_HIP(hipMemcpyAsync(pinned() + 1, dres, sizeof(double), hipMemcpyDeviceToHost, e.stream));
     const bool extrap = m > 0 && it >= opt.diis_start && order.size() >= 2;
@@ -844,7 +846,7 @@ int Context::ccsdt(const CCOptions& opt, double* ec, double* et, int* iters, dou
       launch_diis(dB, dres + 2, slot, ds, extrap, mm, dcoef, e.stream);
     }
     if (extrap)
-      launch_combine(amp_, ht[0], nt_, dcoef, mm, 1.0, 0.0, nt_, e.stream);
+      launch_combine(amp_, ht[0], ldh, dcoef, mm, 1.0, 0.0, nt_, e.stream);
     else
       launch_axpby(amp_, ht[slot], 1.0, 0.0, nt_, e.stream);
     energy_async();

@@ -392,7 +392,7 @@ void launch_dot_acc(const double* x, const double* y, int64_t n, double* partial
 
 // One pass of a Jacobi step with its DIIS bookkeeping:
 //   e = r / d,  t_next = t + e,  e_slot = e,  |r|^2,  <e_k | e> for k < nk
-// (e_k = es + k * n; slot k == slot is the new e itself).  Reads t, r, d and
+// (e_k = es + k * ld; slot k == slot is the new e itself).  Reads t, r, d and
 // the nk history error vectors once (the slot's old vector too, so that every
 // load is unconditional); per-block partials (row 0: |r|^2, row 1 + k:
 // <e_k|e>) are summed in a fixed order by diis_final_kernel.
@@ -402,25 +402,49 @@ constexpr int kDiisMaxVec = 16;
 template <int NK>
 __global__ void __launch_bounds__(256) diis_step_kernel(const double* __restrict__ t, const double* __restrict__ r,
                                                         const double* __restrict__ d, double* __restrict__ t_next,
-                                                        double* __restrict__ es, int slot, int64_t n,
+                                                        double* __restrict__ es, int64_t ld, int slot, int64_t n,
                                                         double* __restrict__ partial) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
   double acc[NK + 1];
 #pragma unroll
   for (int k = 0; k <= NK; ++k) acc[k] = 0.0;
-  double* e_new = es + (int64_t)slot * n;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    // every load of the element first (the slot's old value is read and
+  double* e_new = es + (int64_t)slot * ld;
+  // pairs of elements with 16-byte loads (every array starts 16-byte aligned
+  // and the history stride ld is even); the odd last element, if any, below
+  const int64_t np = n / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = 2 * p;
+    // every load of the pair first (the slot's old value is read and
     // replaced by the new error), then the arithmetic
-    double h[NK > 0 ? NK : 1];
+    d2 h[NK > 0 ? NK : 1];
 #pragma unroll
-    for (int k = 0; k < NK; ++k) h[k] = es[(int64_t)k * n + i];
-    const double ri = r[i];
-    const double e = ri / d[i];
+    for (int k = 0; k < NK; ++k) h[k] = *(const d2*)(es + (int64_t)k * ld + i);
+    const d2 ri = *(const d2*)(r + i);
+    const d2 di = *(const d2*)(d + i);
+    const d2 ti = *(const d2*)(t + i);
+    d2 e;
+    e.x = ri.x / di.x;
+    e.y = ri.y / di.y;
+    *(d2*)(t_next + i) = ti + e;
+    *(d2*)(e_new + i) = e;
+    acc[0] += ri.x * ri.x + ri.y * ri.y;
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      const d2 hk = k == slot ? e : h[k];
+      acc[1 + k] += hk.x * e.x + hk.y * e.y;
+    }
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = n - 1;
+    const double ri = r[i], e = ri / d[i];
+    double hk[NK > 0 ? NK : 1];
+#pragma unroll
+    for (int k = 0; k < NK; ++k) hk[k] = es[(int64_t)k * ld + i];
     t_next[i] = t[i] + e;
     e_new[i] = e;
     acc[0] += ri * ri;
 #pragma unroll
-    for (int k = 0; k < NK; ++k) acc[1 + k] += (k == slot ? e : h[k]) * e;
+    for (int k = 0; k < NK; ++k) acc[1 + k] += (k == slot ? e : hk[k]) * e;
   }
   __shared__ double wsum[4][NK + 1];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -458,18 +482,22 @@ __global__ void __launch_bounds__(256) diis_final_kernel(const double* __restric
 
 int diis_step_partials(int nk) { return (nk + 1) * kDiisBlocks; }
 
-void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int slot,
-                      int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s) {
+void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int64_t ld,
+                      int slot, int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s) {
   FNO_REQUIRE(nk >= 0 && nk <= kDiisMaxVec && (nk == 0 || (slot >= 0 && slot < nk)), kEINVAL,
               "DIIS step: history of " + std::to_string(nk) + " vectors, slot " + std::to_string(slot));
+  FNO_REQUIRE(ld >= n && ld % 2 == 0, kEINVAL, "DIIS step: history stride must be even and cover n");
+  for (const void* p : {(const void*)t, (const void*)r, (const void*)d, (const void*)t_next, (const void*)es})
+    FNO_REQUIRE(((uintptr_t)p & 15) == 0, kEINVAL, "DIIS step: arrays must be 16-byte aligned");
   if (n == 0) return;
-  int64_t blocks = (n + 255) / 256;
+  int64_t blocks = (n / 2 + 255) / 256;
+  if (blocks < 1) blocks = 1;
   if (blocks > kDiisBlocks) blocks = kDiisBlocks;
   const dim3 grid((unsigned)blocks), blk(256);
   switch (nk) {
 #define FNO_DIIS_CASE(K) \
   case K:                \
-    diis_step_kernel<K><<<grid, blk, 0, s>>>(t, r, d, t_next, es, slot, n, partial); \
+    diis_step_kernel<K><<<grid, blk, 0, s>>>(t, r, d, t_next, es, ld, slot, n, partial); \
     break;
     FNO_DIIS_CASE(0) FNO_DIIS_CASE(1) FNO_DIIS_CASE(2) FNO_DIIS_CASE(3) FNO_DIIS_CASE(4) FNO_DIIS_CASE(5)
     FNO_DIIS_CASE(6) FNO_DIIS_CASE(7) FNO_DIIS_CASE(8) FNO_DIIS_CASE(9) FNO_DIIS_CASE(10) FNO_DIIS_CASE(11)

@@ -59,12 +59,12 @@ void launch_dots(const double* xs, int64_t ldx, int nvec, const double* y, int64
                  hipStream_t s);
 // A Jacobi step with its DIIS bookkeeping in one pass over n elements:
 // e = r / d, t_next = t + e, es[slot] = e, *out_rr = |r|^2 and
-// out_ov[k] = <es[k] | e> for k < nk (es[k] = es + k * n, nk <= 16;
-// nk = 0: no history, es may then be t_next's own error buffer of one
-// vector).  partial needs diis_step_partials(nk) doubles; deterministic.
+// out_ov[k] = <es[k] | e> for k < nk (es[k] = es + k * ld with ld even and
+// >= n, nk <= 16; nk = 0: no history).  Every array 16-byte aligned.
+// partial needs diis_step_partials(nk) doubles; deterministic.
 int diis_step_partials(int nk);
-void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int slot,
-                      int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s);
+void launch_diis_step(const double* t, const double* r, const double* d, double* t_next, double* es, int64_t ld,
+                      int slot, int nk, int64_t n, double* partial, double* out_rr, double* out_ov, hipStream_t s);
 // *out = CC correlation energy from f (n x n), g (n^4), t1 (o x v) and packed
 // t2 (see kernels.hip); partial needs 256 doubles
 void launch_cc_energy(const double* f, const double* g, const double* t1, const double* t2, int o, int v,
