@@ -574,6 +574,36 @@ __global__ void __launch_bounds__(256) gemv_acc_kernel(double* __restrict__ y, c
   }
 }
 
+// The same on element pairs (16-byte loads and stores; every element gets the
+// same operations in the same order as in gemv_acc_kernel), for 16-byte
+// aligned y and x_j with an even stride; the odd last element separately.
+__global__ void __launch_bounds__(256) gemv_acc2_kernel(double* __restrict__ y, const double* __restrict__ xs,
+                                                        int64_t ldx, const double* __restrict__ c, int nvec,
+                                                        double alpha, double beta, int64_t n) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const int64_t np = n / 2;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < np; p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = 2 * p;
+    double a0 = 0.0, a1 = 0.0;
+    for (int j = 0; j < nvec; ++j) {
+      const d2 x = *(const d2*)(xs + (int64_t)j * ldx + i);
+      a0 += c[j] * x.x;
+      a1 += c[j] * x.y;
+    }
+    const d2 yv = *(const d2*)(y + i);
+    d2 out;
+    out.x = beta * yv.x + alpha * a0;
+    out.y = beta * yv.y + alpha * a1;
+    *(d2*)(y + i) = out;
+  }
+  if ((n & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t i = n - 1;
+    double acc = 0.0;
+    for (int j = 0; j < nvec; ++j) acc += c[j] * xs[(int64_t)j * ldx + i];
+    y[i] = beta * y[i] + alpha * acc;
+  }
+}
+
 // DIIS step on the device (one workgroup): store the overlaps of the newest
 // error vector (history slot `slot`) with the vectors of the slots in use
 // into the overlap matrix B (16 x 16, by slot), and, when extrapolating, solve
@@ -670,6 +700,13 @@ void launch_diis(double* B, const double* ov, int slot, const DiisSlots& ord, bo
 void launch_combine(double* y, const double* xs, int64_t ldx, const double* c, int nvec, double alpha, double beta,
                     int64_t n, hipStream_t s) {
   if (n == 0) return;
+  if (n >= 2 && ldx % 2 == 0 && (((uintptr_t)y | (uintptr_t)xs) & 15) == 0) {
+    int64_t blocks = (n / 2 + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    gemv_acc2_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(y, xs, ldx, c, nvec, alpha, beta, n);
+    FNO_HIP(hipGetLastError());
+    return;
+  }
   int64_t blocks = (n + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   gemv_acc_kernel<<<dim3((unsigned)blocks), dim3(256), 0, s>>>(y, xs, ldx, c, nvec, alpha, beta, n);
